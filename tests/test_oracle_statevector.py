@@ -1,0 +1,118 @@
+"""Pins of the FP64 reference simulator against things other than itself.
+
+* dense-unitary brute force (Kronecker products, matrix exponentials, gate
+  identities) on up to 8 qubits, every op kind with positive and negative
+  controls;
+* norm preservation over 10^4 random gates;
+* permutation identities (INC^(2^w) = I, INC DEC = I, MCX MCX = I, bit-exact);
+* closed-form states (uniform superposition, GHZ, basis-state increments).
+"""
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits.ir import Circuit
+from paper_2606_12770_amd.circuits.random_circuit import random_mixed_circuit, random_state
+
+
+@pytest.mark.parametrize("n,seed", [(3, 0), (5, 1), (6, 2), (8, 3)])
+def test_oracle_matches_dense_unitary(n, seed):
+    c = random_mixed_circuit(n, 60, seed=seed, max_ctrl=min(4, n - 1))
+    psi0 = random_state(n, seed + 100)
+    U = brute.unitary(c)
+    ref = U @ psi0
+    got = osv.run(c, psi0)
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_brute_unitary_is_unitary():
+    c = random_mixed_circuit(5, 40, seed=9)
+    U = brute.unitary(c)
+    assert np.max(np.abs(U.conj().T @ U - np.eye(32))) < 1e-12
+
+
+def test_norm_preservation_many_gates():
+    n = 12
+    c = random_mixed_circuit(n, 10_000, seed=4, max_ctrl=6)
+    psi = osv.run(c, random_state(n, 5))
+    assert abs(osv.prob(psi, n) - 1.0) < 1e-12
+
+
+def test_dagger_undoes_circuit():
+    n = 9
+    c = random_mixed_circuit(n, 300, seed=7)
+    psi0 = random_state(n, 8)
+    psi = osv.run(c, psi0)
+    back = osv.run(c.dagger(), psi)
+    assert np.max(np.abs(back - psi0)) < 1e-12
+
+
+def test_increment_cycle_identities_bit_exact():
+    n, base, w = 10, 3, 4
+    psi0 = random_state(n, 11)
+    c = Circuit(n)
+    for _ in range(1 << w):
+        c.inc(base, w, {0: 1, 9: 0})
+    out = osv.run(c, psi0)
+    assert np.array_equal(out, psi0)  # pure data movement: bit-exact
+    c2 = Circuit(n).inc(base, w, {1: 1}).dec(base, w, {1: 1}).x(5, [0, 2]).x(5, [0, 2])
+    assert np.array_equal(osv.run(c2, psi0), psi0)
+
+
+def test_increment_on_basis_states():
+    n, base, w = 7, 2, 3
+    for v in range(1 << w):
+        idx = 0b1000001 | (v << base)
+        psi = np.zeros(1 << n, complex)
+        psi[idx] = 1.0
+        out = osv.run(Circuit(n).inc(base, w), psi)
+        want = 0b1000001 | (((v + 1) % (1 << w)) << base)
+        assert out[want] == 1.0 and np.count_nonzero(out) == 1
+        out = osv.run(Circuit(n).dec(base, w), psi)
+        want = 0b1000001 | (((v - 1) % (1 << w)) << base)
+        assert out[want] == 1.0 and np.count_nonzero(out) == 1
+
+
+def test_closed_form_states():
+    n = 6
+    c = Circuit(n)
+    for q in range(n):
+        c.h(q)
+    psi = osv.run(c)
+    assert np.max(np.abs(psi - 1 / np.sqrt(1 << n))) < 1e-14
+    g = Circuit(n).h(0)
+    for q in range(1, n):
+        g.x(q, [0])
+    psi = osv.run(g)
+    want = np.zeros(1 << n, complex)
+    want[0] = want[-1] = 1 / np.sqrt(2)
+    assert np.max(np.abs(psi - want)) < 1e-15
+
+
+def test_projphase_closed_form():
+    # exp(i theta (1 - 2 (s xor z))) on every basis state
+    n, s, mask, val, th = 6, 2, 0b110001, 0b100000, 0.37
+    psi0 = random_state(n, 3)
+    out = osv.run(Circuit(n).projphase(s, mask, val, th), psi0)
+    idx = np.arange(1 << n)
+    z = (idx & mask) == val
+    sb = (idx >> s) & 1
+    ph = np.exp(1j * th * (1 - 2 * (sb ^ z)))
+    assert np.max(np.abs(out - ph * psi0)) < 1e-15
+
+
+def test_postselect_and_inner():
+    n = 8
+    psi = random_state(n, 21)
+    mask, val = 0b10010001, 0b00010000
+    idx = np.arange(1 << n)
+    keep = (idx & mask) == val
+    P = float(np.sum(np.abs(psi[keep]) ** 2))
+    work = psi.copy()
+    got = osv.postselect(work, n, mask, val, True)
+    assert abs(got - P) < 1e-15
+    want = np.where(keep, psi / np.sqrt(P), 0)
+    assert np.max(np.abs(work - want)) < 1e-15
+    b = random_state(n, 22)
+    assert abs(osv.inner(psi, b, n) - np.vdot(psi, b)) < 1e-14
