@@ -1,0 +1,171 @@
+"""Gate-throughput benchmark on one MI355X.
+
+Workload: seeded random layered circuit, 28 qubits, 200 layers (per layer a
+Haar U(2) on every qubit, 10 multi-controlled X with 1-8 controls, one cyclic
++1 on a 6-qubit register): 7,800 gates.  One step = the whole circuit applied
+once to a state resident in HBM.
+
+value      : gates/s of the fused complex64 path (FP32 arithmetic), warmup W
+             steps untimed, then K steps timed with HIP events.
+extra      : fused complex128, the plain per-gate FP64 path (one launch per
+             gate, complex128), the infidelity of the fused complex64 result
+             against the plain complex128 result (both on the GPU, FP64 inner
+             product), roofline of the dominant kernel (the fused tile pass)
+             and the FP64 CPU reference simulator on a bounded prefix.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(circ, budget_s: float):
+    """FP64 reference simulator on a prefix of the same circuit, ~budget_s of work."""
+    import numpy as np
+    from oracle import statevector as osv
+    ops, params = circ.arrays()
+    n = circ.n
+    psi = osv.zero_state(n)
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 4
+    while done < len(ops) and time.perf_counter() - t0 < budget_s:
+        osv.apply(psi, n, ops[done:done + chunk], params)
+        done += min(chunk, len(ops) - done)
+    dt = time.perf_counter() - t0
+    del psi
+    return {"value": done / dt, "unit": "gates/s", "cores": osv.threads(), "kind": "oracle",
+            "sample": f"first {done} of {len(ops)} gates of the same 28-qubit circuit, complex128, "
+                      f"{dt:.1f} s on {osv.threads()} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--qubits", type=int, default=28)
+    ap.add_argument("--layers", type=int, default=200)
+    ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--reg-qubits", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
+              f"single MI355X and has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2606_12770_amd import sv
+    from paper_2606_12770_amd.circuits.random_circuit import random_layered_circuit
+
+    n = args.qubits
+    circ = random_layered_circuit(n, args.layers, seed=0)
+    ops, params = circ.arrays()
+    n_gates = len(ops)
+    log(f"circuit: {n} qubits, {args.layers} layers, {n_gates} gates")
+
+    # ---- fused complex64 (the headline) ----
+    plan64 = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits)
+    info64 = sv.sv_plan_get_info(plan64)
+    log(f"fused c64 plan: {info64}")
+    st64 = sv.sv_alloc(n, sv.SV_C64)
+    for _ in range(args.warmup):
+        sv.sv_plan_execute(plan64, st64, 1)
+    ms64 = sv.sv_plan_time(plan64, st64, args.steps)
+    log(f"fused c64: {ms64 / args.steps:.2f} ms/step")
+
+    # fresh single application for the parity figure
+    sv.sv_free(st64)
+    st64 = sv.sv_alloc(n, sv.SV_C64)
+    sv.sv_plan_execute(plan64, st64, 1)
+
+    # ---- fused complex128 ----
+    plan128 = sv.sv_plan_create(n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits)
+    info128 = sv.sv_plan_get_info(plan128)
+    st128 = sv.sv_alloc(n, sv.SV_C128)
+    sv.sv_plan_execute(plan128, st128, 1)
+    ms128 = sv.sv_plan_time(plan128, st128, 1)
+    log(f"fused c128: {ms128:.2f} ms/step")
+    sv.sv_free(st128)
+    sv.sv_plan_free(plan128)
+
+    # ---- plain per-gate FP64 path ----
+    plain = None
+    infid = None
+    if not args.skip_plain:
+        planp = sv.sv_plan_create(n, sv.SV_C128, ops, params, sv.SV_MODE_PLAIN)
+        infop = sv.sv_plan_get_info(planp)
+        stp = sv.sv_alloc(n, sv.SV_C128)
+        msp = sv.sv_plan_time(planp, stp, 1)
+        log(f"plain c128: {msp:.1f} ms/step")
+        re, im = sv.sv_inner(stp, st64).real, sv.sv_inner(stp, st64).imag
+        n64 = sv.sv_postselect(st64, 0, 0, keep=False, renormalize=False)
+        np_ = sv.sv_postselect(stp, 0, 0, keep=False, renormalize=False)
+        infid = 1.0 - (re * re + im * im) / (n64 * np_)
+        plain = {"gates_per_s": n_gates / (msp / 1e3), "ms_per_step": msp, "launches": infop["n_launches"],
+                 "GBps_algorithmic": infop["bytes_moved"] / (msp / 1e3) / 1e9, "dtype": "f64"}
+        sv.sv_free(stp)
+        sv.sv_plan_free(planp)
+    sv.sv_free(st64)
+
+    # ---- roofline of the dominant kernel (fused tile pass, c64) ----
+    per_step_ms = ms64 / args.steps
+    launches = info64["n_launches"]
+    tile_launches = info64["n_tile_passes"]
+    avg_launch_ms = per_step_ms / launches
+    achieved = info64["tile_pass_bytes"] / (avg_launch_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_tile_pass<float,4>", "launches_per_step": launches,
+            "tile_pass_launches_per_step": tile_launches, "avg_launch_us": avg_launch_ms * 1e3}
+
+    cpu = None
+    if not args.skip_cpu:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(circ, args.cpu_seconds)
+
+    out = {
+        "metric": "gates/s + HBM GB/s per state pass (fused FP32 vs plain FP64, infidelity <=1e-6)",
+        "value": n_gates / (per_step_ms / 1e3),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"random layered circuit, {n} qubits, {args.layers} layers, {n_gates} gates, "
+                               f"complex64 fused", "qubits": n, "layers": args.layers, "gates": n_gates,
+                   "tile_qubits": info64["tile_qubits"], "reg_qubits": info64["reg_qubits"]},
+        "hbm_GBps_per_state_pass": achieved,
+        "infidelity_fused_c64_vs_plain_c128": infid,
+        "fused_c128": {"gates_per_s": n_gates / (ms128 / 1e3), "ms_per_step": ms128,
+                       "launches": info128["n_launches"]},
+        "plain_fp64": plain,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    sv.sv_plan_free(plan64)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * libsv — state-vector simulation of elementary-gate circuits on one MI355X
+ * (gfx950), the simulator behind the explicit circuit demonstration of the
+ * Carleman-linearised lattice Boltzmann QSVT solver (Sec. III.E; the circuit
+ * itself is built in Sec. II.D: block encodings, the L-matrix encoding and
+ * the QSVT ladder).
+ *
+ * Conventions shared by every entry point
+ *   - Qubit j is bit j of the amplitude index (little-endian).
+ *   - Host amplitude buffers are interleaved complex128: re0, im0, re1, im1, ...
+ *   - Every function returns SV_OK (0) or a negative SV_E* code.  Arguments are
+ *     validated on the host before any launch; on an error nothing is launched
+ *     and the state is unchanged.  sv_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Calls are synchronous with respect to the host: when a call returns, its
+ *     device work has completed.  Work is issued on the state's stream.
+ *   - The library owns all device memory it allocates.  Host buffers passed in
+ *     belong to the caller and are only read or written during the call.
+ *   - Calls that use one sv_state must not overlap in time (no internal locks).
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define SV_OK            0
+#define SV_EINVAL       -1  /* bad argument: qubit >= n, target among controls, overlap, bad kind ... */
+#define SV_ENOMEM       -2  /* the device cannot hold the requested state or plan */
+#define SV_EZEROPROB    -3  /* post-selection on a subspace of probability 0; state unchanged */
+#define SV_EDEVICE      -4  /* a HIP runtime call failed */
+#define SV_EUNSUPPORTED -5  /* valid request outside what this build implements */
+
+/* ---- amplitude precision -------------------------------------------------- */
+#define SV_C64  0   /* complex64: float re, im (8 bytes per amplitude)   */
+#define SV_C128 1   /* complex128: double re, im (16 bytes per amplitude) */
+
+/* ---- gate IR --------------------------------------------------------------
+ * One op is a 40-byte POD record.  A gate with controls acts only on the basis
+ * states i with (i & ctrl_mask) == ctrl_val (ctrl_val must be a subset of
+ * ctrl_mask; a 0 under a mask bit is an open control).  `param` is an offset
+ * into the caller's float64 parameter pool.
+ *
+ *  kind             target      width        params  action
+ *  SV_OP_U          qubit t     0            8       2x2 complex matrix (u00,u01,u10,u11 as re,im)
+ *                                                    on each pair (i, i|2^t), i with bit t = 0
+ *  SV_OP_X          qubit t     0            0       exchange the two amplitudes of each pair
+ *  SV_OP_PHASE      qubit t     0            1       multiply by exp(i theta) where bit t = 1
+ *  SV_OP_RY         qubit t     0            1       [[cos th/2, -sin th/2],[sin th/2, cos th/2]]
+ *  SV_OP_INC        base b      width w      0       register v = bits [b,b+w): v -> v+1 mod 2^w
+ *  SV_OP_DEC        base b      width w      0       v -> v-1 mod 2^w
+ *  SV_OP_SWAP       qubit a     qubit b      0       exchange qubits a and b
+ *  SV_OP_PROJPHASE  signal s    0            1       multiply by exp(i theta (1 - 2 (s xor z))),
+ *                                                    z = [(i & ctrl_mask) == ctrl_val]: the
+ *                                                    projector-controlled phase of one QSVT step
+ *                                                    (QSVT circuit figure, Sec. II.D.5); here
+ *                                                    ctrl_* is the projector condition
+ * The elementary gate set of Sec. III (Toffoli, CNOT, H, X, R_Y, S, S^dagger and
+ * their multi-controlled forms) maps onto U, X, RY and PHASE.
+ */
+#define SV_OP_U          0
+#define SV_OP_X          1
+#define SV_OP_PHASE      2
+#define SV_OP_RY         3
+#define SV_OP_INC        4
+#define SV_OP_DEC        5
+#define SV_OP_SWAP       6
+#define SV_OP_PROJPHASE  7
+
+typedef struct {
+    uint32_t kind;
+    uint32_t target;
+    uint32_t width;
+    uint32_t flags;      /* must be 0 */
+    uint64_t ctrl_mask;
+    uint64_t ctrl_val;
+    uint64_t param;
+} sv_op;
+
+/* ---- execution options ---------------------------------------------------- */
+#define SV_MODE_PLAIN 0   /* one kernel launch per gate, each a sweep of the touched subspace */
+#define SV_MODE_FUSED 1   /* gates grouped into LDS-resident tile passes (one HBM sweep each) */
+
+typedef struct {
+    int mode;          /* SV_MODE_PLAIN or SV_MODE_FUSED                                  */
+    int tile_qubits;   /* fused: qubits resident per tile, 0 = automatic                   */
+    int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic        */
+    int reserved;      /* must be 0                                                        */
+} sv_apply_opts;
+
+typedef struct sv_state sv_state;
+typedef struct sv_plan sv_plan;
+
+typedef struct {
+    uint64_t n_ops;           /* IR ops planned                                      */
+    uint64_t n_launches;      /* kernel launches per execution                       */
+    uint64_t n_tile_passes;   /* launches that are fused tile passes                 */
+    uint64_t n_stages;        /* register stages summed over tile passes             */
+    uint64_t bytes_moved;     /* algorithmic HBM bytes per execution (reads+writes)  */
+    uint64_t tile_pass_bytes; /* algorithmic HBM bytes of one tile pass              */
+    int      tile_qubits;     /* b actually used (fused)                             */
+    int      reg_qubits;      /* register qubits actually used (fused)               */
+} sv_plan_info;
+
+/* ---- state lifetime ------------------------------------------------------- */
+
+/* Allocate a 2^n_qubits-amplitude state in device memory (1 <= n_qubits <= 36).
+ * init: NULL for |0...0>, else 2^n interleaved complex128 values (converted to the
+ * state's precision).  stream: a hipStream_t to issue work on, or NULL for a
+ * stream the library creates.  On success *out owns the state. */
+int sv_alloc(int n_qubits, int dtype, const double *init, void *stream, sv_state **out);
+
+/* Release a state (NULL is accepted). */
+int sv_free(sv_state *s);
+
+/* Qubit count and precision of a state. */
+int sv_info(const sv_state *s, int *n_qubits, int *dtype);
+
+/* ---- circuits ------------------------------------------------------------- */
+
+/* Apply ops[0..n_ops) in order (plans, runs, frees the plan).  opts NULL = fused. */
+int sv_apply_circuit(sv_state *s, const sv_op *ops, size_t n_ops,
+                     const double *params, size_t n_params, const sv_apply_opts *opts);
+
+/* Plan an op list once for states of n_qubits qubits and precision dtype, so it
+ * can be executed many times (the QSVT ladder repeats the same U_L / U_L^dagger
+ * op lists d times).  The plan copies everything it needs. */
+int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops,
+                   const double *params, size_t n_params, const sv_apply_opts *opts,
+                   sv_plan **out);
+int sv_plan_free(sv_plan *p);
+int sv_plan_get_info(const sv_plan *p, sv_plan_info *info);
+
+/* Execute a plan `repeat` times on a state of matching size and precision. */
+int sv_plan_execute(sv_plan *p, sv_state *s, int repeat);
+
+/* Execute a sequence of plans: plans[seq[0]], plans[seq[1]], ... seq_len entries,
+ * one host call (the QSVT ladder: phase, U_L, phase, U_L^dagger, ...). */
+int sv_plan_execute_seq(sv_plan *const *plans, const int32_t *seq, size_t seq_len, sv_state *s);
+
+/* Execute a plan `repeat` times bracketed by HIP events on the state's stream;
+ * *ms is the elapsed device time of all repeats. */
+int sv_plan_time(sv_plan *p, sv_state *s, int repeat, double *ms);
+
+/* ---- reductions, post-selection, read-out (all accumulate in FP64) ---------- */
+
+/* P = sum of |a_i|^2 over (i & mask) == value.  If keep != 0 the other amplitudes
+ * are set to zero, and if renormalize != 0 the kept ones are divided by sqrt(P).
+ * mask = 0, value = 0, keep = 0 returns the squared norm (norm drift check).
+ * P == 0 with keep != 0 gives SV_EZEROPROB and leaves the state unchanged. */
+int sv_postselect(sv_state *s, uint64_t mask, uint64_t value, int keep, int renormalize,
+                  double *prob_out);
+
+/* Copy amplitudes [offset, offset+count) to host as interleaved complex128. */
+int sv_amplitudes(const sv_state *s, uint64_t offset, uint64_t count, double *out);
+
+/* Overwrite amplitudes [offset, offset+count) from host interleaved complex128. */
+int sv_set_amplitudes(sv_state *s, uint64_t offset, uint64_t count, const double *in);
+
+/* Copy the amplitudes of src into dst (same qubit count; precisions may differ). */
+int sv_copy(sv_state *dst, const sv_state *src);
+
+/* <a|b> = sum conj(a_i) b_i in FP64 (same qubit count; precisions may differ). */
+int sv_inner(const sv_state *a, const sv_state *b, double *re, double *im);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+const char *sv_strerror(int code);
+const char *sv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

@@ -1,0 +1,449 @@
+// Plain per-gate kernels (one launch = one sweep of the subspace a gate
+// touches), FP64 reductions, post-selection and conversions.
+//
+// Work items are enumerated over the free index bits only: a compact counter
+// w is spread into an index by inserting zero bits at the sorted positions of
+// the target/register/control bits, then the control values are OR-ed in.  A
+// gate with c controls therefore reads and writes 2^(n-c) amplitudes, not 2^n.
+// Consecutive threads take consecutive counters, so accesses are coalesced on
+// the lowest free qubits.
+
+#include <hip/hip_runtime.h>
+
+#include "sv_internal.h"
+
+namespace svi {
+
+template <typename R> struct CT;
+template <> struct CT<float> { using T = float2; };
+template <> struct CT<double> { using T = double2; };
+
+struct Deposit {
+    uint32_t n;
+    uint8_t pos[64];  // ascending
+};
+
+__device__ __forceinline__ uint64_t deposit_zeros(uint64_t x, const Deposit &d)
+{
+    for (uint32_t k = 0; k < d.n; ++k) {
+        const uint32_t p = d.pos[k];
+        x = ((x >> p) << (p + 1)) | (x & ((1ull << p) - 1ull));
+    }
+    return x;
+}
+
+template <typename R> struct Mat2 { R v[8]; };
+
+template <typename C, typename R>
+__device__ __forceinline__ C mat_row(R ar, R ai, R br, R bi, C a, C b)
+{
+    // (ar + i ai) a + (br + i bi) b
+    C r;
+    r.x = fma(ar, a.x, fma(-ai, a.y, fma(br, b.x, -bi * b.y)));
+    r.y = fma(ar, a.y, fma(ai, a.x, fma(br, b.y, bi * b.x)));
+    return r;
+}
+
+static inline int grid_for(uint64_t work, int block)
+{
+    uint64_t g = (work + block - 1) / block;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_u(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                                Deposit d, uint64_t cval, uint64_t tbit, Mat2<R> m)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t i0 = deposit_zeros(w, d) | cval;
+        const uint64_t i1 = i0 | tbit;
+        const C a = psi[i0], b = psi[i1];
+        psi[i0] = mat_row(m.v[0], m.v[1], m.v[2], m.v[3], a, b);
+        psi[i1] = mat_row(m.v[4], m.v[5], m.v[6], m.v[7], a, b);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_x(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                                Deposit d, uint64_t cval, uint64_t tbit)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t i0 = deposit_zeros(w, d) | cval;
+        const uint64_t i1 = i0 | tbit;
+        const C a = psi[i0], b = psi[i1];
+        psi[i0] = b;
+        psi[i1] = a;
+    }
+}
+
+// multiply by (c, s) every amplitude whose target bit is 1 and controls hold
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_phase(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                                    Deposit d, uint64_t setbits, R c, R s)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t i = deposit_zeros(w, d) | setbits;
+        const C a = psi[i];
+        C r;
+        r.x = fma(a.x, c, -a.y * s);
+        r.y = fma(a.x, s, a.y * c);
+        psi[i] = r;
+    }
+}
+
+// exchange amplitude i (bit a = 1, bit b = 0) with i ^ abit ^ bbit
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_swap(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                                   Deposit d, uint64_t cval, uint64_t abit, uint64_t bbit)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t i = deposit_zeros(w, d) | cval | abit;
+        const uint64_t j = i ^ abit ^ bbit;
+        const C x = psi[i], y = psi[j];
+        psi[i] = y;
+        psi[j] = x;
+    }
+}
+
+// cyclic shift of the register [b, b+w) on one orbit per work item
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_shift(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                                    Deposit d, uint64_t cval, int base, int width, int up)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t len = 1ull << width;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t r = deposit_zeros(w, d) | cval;
+        if (up) {  // new[v] = old[v-1]
+            C prev = psi[r | ((len - 1) << base)];
+            for (uint64_t v = 0; v < len; ++v) {
+                const uint64_t i = r | (v << base);
+                const C cur = psi[i];
+                psi[i] = prev;
+                prev = cur;
+            }
+        } else {   // new[v] = old[v+1]
+            C prev = psi[r];
+            for (uint64_t v = len; v-- > 0;) {
+                const uint64_t i = r | (v << base);
+                const C cur = psi[i];
+                psi[i] = prev;
+                prev = cur;
+            }
+        }
+    }
+}
+
+// exp(i theta (1 - 2 (s xor z))), z = [(i & mask) == val], s = bit `sig`
+template <typename R>
+__global__ void __launch_bounds__(256) k_projphase(typename CT<R>::T *__restrict__ psi, uint64_t dim,
+                                                   uint64_t mask, uint64_t val, int sig, R c, R s)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        const uint32_t z = (i & mask) == val;
+        const uint32_t sb = (uint32_t)(i >> sig) & 1u;
+        const R sn = (sb ^ z) ? -s : s;
+        const C a = psi[i];
+        C r;
+        r.x = fma(a.x, c, -a.y * sn);
+        r.y = fma(a.x, sn, a.y * c);
+        psi[i] = r;
+    }
+}
+
+static Deposit make_deposit(uint64_t fixed_bits)
+{
+    Deposit d{};
+    d.n = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((fixed_bits >> q) & 1ull) d.pos[d.n++] = (uint8_t)q;
+    return d;
+}
+
+template <typename R>
+static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
+{
+    using C = typename CT<R>::T;
+    C *psi = (C *)psi_v;
+    const int B = 256;
+    const int c = __builtin_popcountll(op.mask);
+    switch (op.kind) {
+    case SV_OP_U: {
+        const uint64_t nwork = 1ull << (n - 1 - c);
+        Mat2<R> m;
+        for (int k = 0; k < 8; ++k) m.v[k] = (R)op.m[k];
+        hipLaunchKernelGGL(k_gate_u<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                           make_deposit(op.mask | (1ull << op.target)), op.val, 1ull << op.target, m);
+        break;
+    }
+    case SV_OP_X: {
+        const uint64_t nwork = 1ull << (n - 1 - c);
+        hipLaunchKernelGGL(k_gate_x<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                           make_deposit(op.mask | (1ull << op.target)), op.val, 1ull << op.target);
+        break;
+    }
+    case SV_OP_PHASE: {
+        const uint64_t nwork = 1ull << (n - 1 - c);
+        hipLaunchKernelGGL(k_gate_phase<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                           make_deposit(op.mask | (1ull << op.target)), op.val | (1ull << op.target),
+                           (R)cos(op.m[0]), (R)sin(op.m[0]));
+        break;
+    }
+    case SV_OP_SWAP: {
+        const uint64_t ab = 1ull << op.target, bb = 1ull << op.width;
+        const uint64_t nwork = 1ull << (n - 2 - c);
+        hipLaunchKernelGGL(k_gate_swap<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                           make_deposit(op.mask | ab | bb), op.val, ab, bb);
+        break;
+    }
+    case SV_OP_INC:
+    case SV_OP_DEC: {
+        const uint64_t reg = ((1ull << op.width) - 1ull) << op.target;
+        const uint64_t nwork = 1ull << (n - (int)op.width - c);
+        hipLaunchKernelGGL(k_gate_shift<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                           make_deposit(op.mask | reg), op.val, (int)op.target, (int)op.width,
+                           op.kind == SV_OP_INC ? 1 : 0);
+        break;
+    }
+    case SV_OP_PROJPHASE: {
+        const uint64_t dim = 1ull << n;
+        hipLaunchKernelGGL(k_projphase<R>, dim3(grid_for(dim, B)), dim3(B), 0, st, psi, dim, op.mask,
+                           op.val, (int)op.target, (R)cos(op.m[0]), (R)sin(op.m[0]));
+        break;
+    }
+    default:
+        return SV_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+int launch_plain(const PlainOp &op, int n, int dtype, void *psi, hipStream_t stream)
+{
+    return dtype == SV_C64 ? launch_plain_t<float>(op, n, psi, stream)
+                           : launch_plain_t<double>(op, n, psi, stream);
+}
+
+// ---------------------------------------------------------------------------
+// reductions (FP64 accumulation for every precision)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < nw; ++k) t += red[k];
+    }
+    return t;  // valid in thread 0
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_prob(const typename CT<R>::T *__restrict__ psi, uint64_t nwork,
+                                              Deposit d, uint64_t val, double *__restrict__ partial)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const auto a = psi[deposit_zeros(w, d) | val];
+        const double x = (double)a.x, y = (double)a.y;
+        acc = fma(x, x, fma(y, y, acc));
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__ partial, int count, int stride2,
+                                                      double *__restrict__ out)
+{
+    // sums partial[k*stride2 + j] over k for j in [0, stride2); stride2 <= 2
+    for (int j = 0; j < stride2; ++j) {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < count; k += blockDim.x) acc += partial[k * stride2 + j];
+        const double t = block_sum(acc);
+        if (threadIdx.x == 0) out[j] = t;
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_keep_scale(typename CT<R>::T *__restrict__ psi, uint64_t dim,
+                                                    uint64_t mask, uint64_t val, R scale)
+{
+    using C = typename CT<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        C a = psi[i];
+        if ((i & mask) == val) {
+            a.x *= scale;
+            a.y *= scale;
+        } else {
+            a.x = 0;
+            a.y = 0;
+        }
+        psi[i] = a;
+    }
+}
+
+template <typename RA, typename RB>
+__global__ void __launch_bounds__(256) k_inner(const typename CT<RA>::T *__restrict__ a,
+                                               const typename CT<RB>::T *__restrict__ b, uint64_t dim,
+                                               double *__restrict__ partial)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    double re = 0.0, im = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        const double ax = a[i].x, ay = a[i].y, bx = b[i].x, by = b[i].y;
+        re = fma(ax, bx, fma(ay, by, re));   // conj(a) b
+        im = fma(ax, by, fma(-ay, bx, im));
+    }
+    const double tr = block_sum(re);
+    __syncthreads();
+    const double ti = block_sum(im);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = tr;
+        partial[2 * blockIdx.x + 1] = ti;
+    }
+}
+
+template <typename RS, typename RD>
+__global__ void __launch_bounds__(256) k_convert(typename CT<RD>::T *__restrict__ dst,
+                                                 const typename CT<RS>::T *__restrict__ src, uint64_t count)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        typename CT<RD>::T v;
+        v.x = (RD)src[i].x;
+        v.y = (RD)src[i].y;
+        dst[i] = v;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_basis0(typename CT<R>::T *__restrict__ psi, uint64_t dim)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        typename CT<R>::T v;
+        v.x = (i == 0) ? (R)1 : (R)0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+static int status() { return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE; }
+
+int launch_init_basis(void *psi, int n, int dtype, hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_basis0<float>, dim3(grid_for(dim, 256)), dim3(256), 0, st, (float2 *)psi, dim);
+    else
+        hipLaunchKernelGGL(k_basis0<double>, dim3(grid_for(dim, 256)), dim3(256), 0, st, (double2 *)psi, dim);
+    return status();
+}
+
+int launch_from_c128(void *psi, int dtype, const void *d_src, uint64_t offset, uint64_t count,
+                     hipStream_t st)
+{
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count, 256)), dim3(256), 0, st,
+                           (float2 *)psi + offset, (const double2 *)d_src, count);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(grid_for(count, 256)), dim3(256), 0, st,
+                           (double2 *)psi + offset, (const double2 *)d_src, count);
+    return status();
+}
+
+int launch_to_c128(const void *psi, int dtype, void *d_dst, uint64_t offset, uint64_t count,
+                   hipStream_t st)
+{
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count, 256)), dim3(256), 0, st,
+                           (double2 *)d_dst, (const float2 *)psi + offset, count);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(grid_for(count, 256)), dim3(256), 0, st,
+                           (double2 *)d_dst, (const double2 *)psi + offset, count);
+    return status();
+}
+
+int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    const dim3 g(grid_for(dim, 256)), b(256);
+    if (dts == SV_C64 && dtd == SV_C64)
+        hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, st, (float2 *)dst, (const float2 *)src, dim);
+    else if (dts == SV_C64)
+        hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, st, (double2 *)dst, (const float2 *)src, dim);
+    else if (dtd == SV_C64)
+        hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, st, (float2 *)dst, (const double2 *)src, dim);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, st, (double2 *)dst, (const double2 *)src, dim);
+    return status();
+}
+
+int launch_prob(const void *psi, int n, int dtype, uint64_t mask, uint64_t val, double *d_partial,
+                int max_blocks, double *d_out, hipStream_t st)
+{
+    const int c = __builtin_popcountll(mask);
+    const uint64_t nwork = 1ull << (n - c);
+    uint64_t g = (nwork + 255) / 256;
+    if (g > (uint64_t)max_blocks) g = max_blocks;
+    const Deposit d = make_deposit(mask);
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_prob<float>, dim3(g), dim3(256), 0, st, (const float2 *)psi, nwork, d, val, d_partial);
+    else
+        hipLaunchKernelGGL(k_prob<double>, dim3(g), dim3(256), 0, st, (const double2 *)psi, nwork, d, val, d_partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double *)d_partial, (int)g, 1, d_out);
+    return status();
+}
+
+int launch_keep_scale(void *psi, int n, int dtype, uint64_t mask, uint64_t val, double scale,
+                      hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_keep_scale<float>, dim3(grid_for(dim, 256)), dim3(256), 0, st, (float2 *)psi, dim,
+                           mask, val, (float)scale);
+    else
+        hipLaunchKernelGGL(k_keep_scale<double>, dim3(grid_for(dim, 256)), dim3(256), 0, st, (double2 *)psi, dim,
+                           mask, val, scale);
+    return status();
+}
+
+int launch_inner(const void *a, int dta, const void *b, int dtb, int n, double *d_partial, int max_blocks,
+                 double *d_out, hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    uint64_t g = (dim + 255) / 256;
+    if (g > (uint64_t)max_blocks) g = max_blocks;
+    const dim3 G(g), B(256);
+    if (dta == SV_C64 && dtb == SV_C64)
+        hipLaunchKernelGGL((k_inner<float, float>), G, B, 0, st, (const float2 *)a, (const float2 *)b, dim, d_partial);
+    else if (dta == SV_C64)
+        hipLaunchKernelGGL((k_inner<float, double>), G, B, 0, st, (const float2 *)a, (const double2 *)b, dim, d_partial);
+    else if (dtb == SV_C64)
+        hipLaunchKernelGGL((k_inner<double, float>), G, B, 0, st, (const double2 *)a, (const float2 *)b, dim, d_partial);
+    else
+        hipLaunchKernelGGL((k_inner<double, double>), G, B, 0, st, (const double2 *)a, (const double2 *)b, dim, d_partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double *)d_partial, (int)g, 2, d_out);
+    return status();
+}
+
+}  // namespace svi

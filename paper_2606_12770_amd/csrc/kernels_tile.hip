@@ -1,0 +1,271 @@
+// Fused tile-pass kernel: one HBM read and one HBM write of the state for a
+// whole run of gates.
+//
+// Workgroup = one tile = the 2^b amplitudes that agree on the n-b tile qubits.
+// Thread count 2^(b-RB); each thread keeps 2^RB amplitudes in registers.
+//   load   : register slot s <- local index (s << nthr) | tid   (coalesced on the
+//            lowest local qubits, which are the lowest qubits of the index)
+//   stages : gates on register bits run in registers (unrolled per slot bit);
+//            between stages the tile goes through LDS, where permutation gates
+//            are applied to the write address
+//   store  : back through the load mapping
+// Gate conditions are split into a local part (checked per amplitude on the
+// local index) and a tile part (uniform per workgroup: the whole gate is
+// skipped when it fails).
+
+#include <hip/hip_runtime.h>
+
+#include "sv_internal.h"
+
+namespace svi {
+
+template <typename R> struct CTT;
+template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4; };
+template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
+
+// XOR-fold the higher bits of a local index into its lowest LOWB bits so that
+// threads strided by any power of two land in different LDS banks.
+template <int LOWB>
+__device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
+{
+    const uint32_t h = (l >> LOWB) ^ (l >> (2 * LOWB)) ^ (l >> (3 * LOWB)) ^ (l >> (4 * LOWB));
+    return l ^ (h & ((1u << LOWB) - 1u));
+}
+
+template <typename C, typename R>
+__device__ __forceinline__ C row2(R ar, R ai, R br, R bi, C a, C b)
+{
+    C r;
+    r.x = fma(ar, a.x, fma(-ai, a.y, fma(br, b.x, -bi * b.y)));
+    r.y = fma(ar, a.y, fma(ai, a.x, fma(br, b.y, bi * b.x)));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t apply_perms(uint32_t l, const TileOp *__restrict__ perms, uint32_t pb,
+                                                uint32_t pe, uint64_t base)
+{
+    for (uint32_t k = pb; k < pe; ++k) {
+        const TileOp p = perms[k];
+        if ((base & p.gmask) != p.gval) continue;
+        if ((l & p.lmask) != p.lval) continue;
+        switch (p.kind) {
+        case T_INC:
+        case T_DEC: {
+            const uint32_t m = (1u << p.b) - 1u;
+            uint32_t v = (l >> p.a) & m;
+            v = (p.kind == T_INC ? v + 1u : v - 1u) & m;
+            l = (l & ~(m << p.a)) | (v << p.a);
+            break;
+        }
+        case T_SWAP:
+            if (((l >> p.a) ^ (l >> p.b)) & 1u) l ^= (1u << p.a) | (1u << p.b);
+            break;
+        case T_XFLIP:
+            l ^= 1u << p.a;
+            break;
+        default:
+            break;
+        }
+    }
+    return l;
+}
+
+template <int K, int NR, typename C, typename R>
+__device__ __forceinline__ void reg_u(C (&x)[NR], const R *m, uint32_t thr, const uint32_t (&ro)[NR],
+                                      uint32_t lmask, uint32_t lval)
+{
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+        if (s & (1 << K)) continue;
+        const int s1 = s | (1 << K);
+        if (((thr | ro[s]) & lmask) == lval) {
+            const C a = x[s], b = x[s1];
+            x[s] = row2(m[0], m[1], m[2], m[3], a, b);
+            x[s1] = row2(m[4], m[5], m[6], m[7], a, b);
+        }
+    }
+}
+
+template <int K, int NR, typename C>
+__device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t thr, const uint32_t (&ro)[NR], uint32_t lmask,
+                                      uint32_t lval)
+{
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+        if (s & (1 << K)) continue;
+        const int s1 = s | (1 << K);
+        if (((thr | ro[s]) & lmask) == lval) {
+            const C a = x[s];
+            x[s] = x[s1];
+            x[s1] = a;
+        }
+    }
+}
+
+template <typename R, int RB>
+__global__ void __launch_bounds__(256)
+k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
+            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
+{
+    using C = typename CTT<R>::T;
+    constexpr int NR = 1 << RB;
+    constexpr int LOWB = CTT<R>::LOWB;
+    extern __shared__ unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nthr = pass->nthr;
+    const uint32_t ntile = pass->ntile;
+
+    // absolute index bits of this tile
+    const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    uint64_t base = 0;
+    for (uint32_t j = 0; j < ntile; ++j) base |= ((tile >> j) & 1ull) << pass->tpos[j];
+
+    // load mapping: thread bits = local bits [0, nthr), slots = local bits [nthr, b)
+    uint64_t gthr = 0;
+    for (uint32_t j = 0; j < nthr; ++j) gthr |= (uint64_t)((tid >> j) & 1u) << pass->spos[j];
+    const uint64_t gbase = base | gthr;
+
+    C x[NR];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) x[s] = psi[gbase | pass->goff[s]];
+
+    uint32_t thr = tid;
+    uint32_t ro[NR];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) ro[s] = (uint32_t)s << nthr;
+
+    const uint32_t sb = pass->stage_begin, se = pass->stage_end;
+    for (uint32_t st = sb; st < se; ++st) {
+        const TileStage &S = stages[st];
+        if (st != sb) {
+            // exchange: write under the old mapping (permuted), read under the new one
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < NR; ++s) {
+                const uint32_t l = apply_perms(thr | ro[s], ops, S.perm_begin, S.perm_end, base);
+                lds[lds_swizzle<LOWB>(l)] = x[s];
+            }
+            __syncthreads();
+            uint32_t t2 = 0;
+            for (uint32_t j = 0; j < nthr; ++j) t2 |= ((tid >> j) & 1u) << S.thrpos[j];
+            thr = t2;
+#pragma unroll
+            for (int s = 0; s < NR; ++s) ro[s] = S.regoff[s];
+#pragma unroll
+            for (int s = 0; s < NR; ++s) x[s] = lds[lds_swizzle<LOWB>(thr | ro[s])];
+        }
+        for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
+            const TileOp op = ops[k];
+            if (op.kind == T_PROJ) {
+                const bool zg = (base & op.gmask) == op.gval;
+                const R c = prm[op.param], sn = prm[op.param + 1];
+                const uint32_t sglob = (op.a == 0xff) ? (uint32_t)((base >> op.b) & 1ull) : 0u;
+#pragma unroll
+                for (int s = 0; s < NR; ++s) {
+                    const uint32_t l = thr | ro[s];
+                    const uint32_t z = (zg && ((l & op.lmask) == op.lval)) ? 1u : 0u;
+                    const uint32_t sbit = (op.a == 0xff) ? sglob : ((l >> op.a) & 1u);
+                    const R si = (sbit ^ z) ? -sn : sn;
+                    const C a = x[s];
+                    C r;
+                    r.x = fma(a.x, c, -a.y * si);
+                    r.y = fma(a.x, si, a.y * c);
+                    x[s] = r;
+                }
+                continue;
+            }
+            if ((base & op.gmask) != op.gval) continue;
+            if (op.kind == T_U) {
+                R m[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) m[j] = prm[op.param + j];
+                switch (op.slot) {
+                case 0: reg_u<0, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
+                case 1: reg_u<1, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
+                case 2: reg_u<2, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
+                case 3: reg_u<3, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
+                default:
+                    if constexpr (RB > 4) reg_u<(RB > 4 ? 4 : 0), NR, C, R>(x, m, thr, ro, op.lmask, op.lval);
+                    break;
+                }
+            } else if (op.kind == T_X) {
+                switch (op.slot) {
+                case 0: reg_x<0, NR, C>(x, thr, ro, op.lmask, op.lval); break;
+                case 1: reg_x<1, NR, C>(x, thr, ro, op.lmask, op.lval); break;
+                case 2: reg_x<2, NR, C>(x, thr, ro, op.lmask, op.lval); break;
+                case 3: reg_x<3, NR, C>(x, thr, ro, op.lmask, op.lval); break;
+                default:
+                    if constexpr (RB > 4) reg_x<(RB > 4 ? 4 : 0), NR, C>(x, thr, ro, op.lmask, op.lval);
+                    break;
+                }
+            } else if (op.kind == T_PHASE) {
+                const R c = prm[op.param], sn = prm[op.param + 1];
+#pragma unroll
+                for (int s = 0; s < NR; ++s) {
+                    if (((thr | ro[s]) & op.lmask) == op.lval) {
+                        const C a = x[s];
+                        C r;
+                        r.x = fma(a.x, c, -a.y * sn);
+                        r.y = fma(a.x, sn, a.y * c);
+                        x[s] = r;
+                    }
+                }
+            }
+        }
+    }
+
+    if (pass->final_exchange) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NR; ++s) {
+            const uint32_t l = apply_perms(thr | ro[s], ops, pass->fperm_begin, pass->fperm_end, base);
+            lds[lds_swizzle<LOWB>(l)] = x[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NR; ++s) x[s] = lds[lds_swizzle<LOWB>(((uint32_t)s << nthr) | tid)];
+    }
+#pragma unroll
+    for (int s = 0; s < NR; ++s) psi[gbase | pass->goff[s]] = x[s];
+}
+
+template <typename R, int RB>
+static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
+{
+    using C = typename CTT<R>::T;
+    const TilePass &P = p->passes[pi];
+    const uint64_t tiles = 1ull << P.ntile;
+    const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
+    const uint32_t gy = (uint32_t)(tiles / gx);
+    const dim3 grid(gx, gy);
+    const dim3 block(1u << P.nthr);
+    const size_t lds = sizeof(C) << P.b;
+    hipLaunchKernelGGL((k_tile_pass<R, RB>), grid, block, lds, st, (C *)psi,
+                       (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
+                       (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+    return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
+{
+    if (p->dtype == SV_C64)
+        return p->rb == 5 ? launch_tile_t<float, 5>(p, pi, psi, st) : launch_tile_t<float, 4>(p, pi, psi, st);
+    return p->rb == 5 ? launch_tile_t<double, 5>(p, pi, psi, st) : launch_tile_t<double, 4>(p, pi, psi, st);
+}
+
+// LDS above 64 KiB per workgroup must be requested per kernel.  A refusal is
+// not fatal: a launch that then exceeds the limit fails with a runtime error.
+int tile_kernel_setup()
+{
+    const int big = 160 * 1024;
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipGetLastError();
+    return SV_OK;
+}
+
+}  // namespace svi

@@ -1,0 +1,115 @@
+// Plan structures of libsv shared by the planner (host) and the kernels.
+// Free of HIP types so host-only code can include it.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sv.h"
+
+namespace svi {
+
+// ---------------------------------------------------------------------------
+// Fused tile passes.
+//
+// A tile pass keeps b "local" qubits of the index resident on chip: one
+// workgroup loads the 2^b amplitudes that share the values of the other n-b
+// ("tile") qubits, applies a whole run of gates to them, and writes them back
+// once.  Local qubit k of a pass is qubit spos[k] (ascending), so local bit
+// positions preserve the order of the qubits.
+//
+// Inside the workgroup each thread holds 2^RB amplitudes in registers.  A
+// "stage" fixes which RB local bits index the register slots (regoff[s] is the
+// local index offset of slot s) and which b-RB local bits index the thread
+// (thrpos).  Gates whose target is a register bit are applied in registers;
+// moving to the next stage exchanges the tile through LDS, and permutation
+// gates (INC/DEC/SWAP/X on local bits) are applied to the LDS address during
+// that exchange.
+// ---------------------------------------------------------------------------
+
+enum : uint8_t {
+    T_U = 0,      // 2x2 matrix on register slot bit `slot`
+    T_X = 1,      // exchange on register slot bit `slot`
+    T_PHASE = 2,  // diagonal phase where the (local, tile) condition holds
+    T_PROJ = 3,   // projector phase; a = local signal bit or 0xff (then b = signal qubit)
+    T_INC = 4,    // permutation: local register [a, a+b) += 1
+    T_DEC = 5,    // permutation: local register [a, a+b) -= 1
+    T_SWAP = 6,   // permutation: exchange local bits a and b
+    T_XFLIP = 7,  // permutation: flip local bit a
+};
+
+struct TileOp {
+    uint8_t kind;
+    uint8_t slot;
+    uint8_t a;
+    uint8_t b;
+    uint32_t param;   // offset (in reals) into the plan's parameter array
+    uint32_t lmask;   // condition on the local index
+    uint32_t lval;
+    uint64_t gmask;   // condition on the absolute index bits of tile qubits
+    uint64_t gval;
+};
+static_assert(sizeof(TileOp) == 32, "TileOp layout");
+
+constexpr int kMaxRB = 5;
+constexpr int kMaxB = 14;
+
+struct TileStage {
+    uint32_t op_begin, op_end;      // register-level ops of the stage
+    uint32_t perm_begin, perm_end;  // permutations applied on entry to the stage
+    uint8_t thrpos[16];             // local bit index of thread bit j
+    uint16_t regoff[1 << kMaxRB];   // local index offset of register slot s
+};
+
+struct TilePass {
+    uint32_t stage_begin, stage_end;
+    uint32_t fperm_begin, fperm_end;  // permutations on the final exchange
+    uint8_t b, rb, nthr, ntile;
+    uint8_t final_exchange;           // 1: exchange back to the load mapping before the store
+    uint8_t pad[3];
+    uint8_t spos[kMaxB];              // local bit -> qubit
+    uint8_t pad2[2];
+    uint8_t tpos[48];                 // tile bit -> qubit
+    uint64_t goff[1 << kMaxRB];       // absolute index offset of load-mapping register slot s
+};
+
+// ---------------------------------------------------------------------------
+// Plain per-gate launches.
+// ---------------------------------------------------------------------------
+struct PlainOp {
+    uint32_t kind;       // SV_OP_* (RY already turned into U)
+    uint32_t target, width;
+    uint64_t mask, val;
+    double m[8];         // U matrix or phase angle in m[0]
+};
+
+struct Step {
+    int type;            // 0 = plain op, 1 = tile pass
+    uint32_t index;
+};
+
+}  // namespace svi
+
+
+
+struct sv_plan {
+    int n = 0;
+    int dtype = SV_C64;
+    int b = 0, rb = 0;
+    std::vector<svi::Step> steps;
+    std::vector<svi::PlainOp> plain;
+    std::vector<svi::TilePass> passes;
+    std::vector<svi::TileStage> stages;
+    std::vector<svi::TileOp> tops;
+    std::vector<double> tparams;      // host copy (double); converted on upload
+    void *d_passes = nullptr, *d_stages = nullptr, *d_tops = nullptr, *d_tparams = nullptr;
+    int device = -1;
+    sv_plan_info info{};
+};
+
+namespace svi {
+// Builds steps/passes/stages/ops on the host; returns SV_OK or an error code.
+int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
+               const sv_apply_opts &opts, std::string &err);
+}  // namespace svi

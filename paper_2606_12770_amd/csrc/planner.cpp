@@ -1,0 +1,407 @@
+// Host planner: turns a validated op list into launch steps.
+//
+// Plain mode: one step per op.
+// Fused mode: ops are grouped into tile passes.  An op can join a pass whose
+// resident ("local") qubit set S contains the qubits it moves amplitudes
+// along (target of U/X, register of INC/DEC, both qubits of SWAP); diagonal
+// ops (PHASE, PROJPHASE) and all control qubits impose nothing, because tile
+// qubits are constant inside a workgroup and conditions on them are uniform.
+// Ops may be moved ahead of earlier ops they commute with: two ops commute
+// when every qubit they share is diagonal-type (control or phase) in both, or
+// the target of an X in both.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "plan_types.h"
+
+namespace svi {
+
+namespace {
+
+struct OpInfo {
+    uint32_t kind;
+    uint32_t target, width;
+    uint64_t mask, val;
+    double m[8];
+    uint64_t req;   // qubits that must be resident
+    uint64_t z, x, g;
+};
+
+OpInfo normalize(const sv_op &o, const double *params)
+{
+    OpInfo r{};
+    r.kind = o.kind;
+    r.target = o.target;
+    r.width = o.width;
+    r.mask = o.ctrl_mask;
+    r.val = o.ctrl_val;
+    const double *p = params + o.param;
+    const uint64_t tb = 1ull << o.target;
+    switch (o.kind) {
+    case SV_OP_U:
+        for (int k = 0; k < 8; ++k) r.m[k] = p[k];
+        r.req = tb;
+        r.g = tb;
+        r.z = o.ctrl_mask;
+        break;
+    case SV_OP_RY: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        r.kind = SV_OP_U;
+        const double m[8] = {c, 0, -s, 0, s, 0, c, 0};
+        std::memcpy(r.m, m, sizeof m);
+        r.req = tb;
+        r.g = tb;
+        r.z = o.ctrl_mask;
+        break;
+    }
+    case SV_OP_X:
+        r.req = tb;
+        r.x = tb;
+        r.z = o.ctrl_mask;
+        break;
+    case SV_OP_PHASE:
+        r.m[0] = p[0];
+        r.z = o.ctrl_mask | tb;
+        break;
+    case SV_OP_PROJPHASE:
+        r.m[0] = p[0];
+        r.z = o.ctrl_mask | tb;
+        break;
+    case SV_OP_INC:
+    case SV_OP_DEC: {
+        const uint64_t reg = ((1ull << o.width) - 1ull) << o.target;
+        r.req = reg;
+        r.g = reg;
+        r.z = o.ctrl_mask;
+        break;
+    }
+    case SV_OP_SWAP: {
+        const uint64_t ab = tb | (1ull << o.width);
+        r.req = ab;
+        r.g = ab;
+        r.z = o.ctrl_mask;
+        break;
+    }
+    default:
+        break;
+    }
+    return r;
+}
+
+PlainOp to_plain(const OpInfo &o)
+{
+    PlainOp p{};
+    p.kind = o.kind;
+    p.target = o.target;
+    p.width = o.width;
+    p.mask = o.mask;
+    p.val = o.val;
+    std::memcpy(p.m, o.m, sizeof p.m);
+    return p;
+}
+
+uint64_t plain_bytes(const OpInfo &o, int n, int s)
+{
+    const int c = __builtin_popcountll(o.mask);
+    switch (o.kind) {
+    case SV_OP_U:
+    case SV_OP_X:
+        return 2ull * (1ull << (n - c)) * s;
+    case SV_OP_PHASE:
+        return 2ull * (1ull << (n - 1 - c)) * s;
+    case SV_OP_SWAP:
+        return 2ull * (1ull << (n - 1 - c)) * s;
+    case SV_OP_INC:
+    case SV_OP_DEC:
+        return 2ull * (1ull << (n - c)) * s;
+    default:
+        return 2ull * (1ull << n) * s;
+    }
+}
+
+// j commutes with every op whose roles are accumulated in (Z, X, G)
+inline bool commutes_with_all(const OpInfo &o, uint64_t Z, uint64_t X, uint64_t G)
+{
+    const uint64_t fp = o.z | o.x | o.g;
+    return (fp & G) == 0 && (o.g & (Z | X)) == 0 && (o.z & X) == 0 && (o.x & Z) == 0;
+}
+
+struct PassBuild {
+    uint64_t S = 0;
+    std::vector<uint32_t> ops;
+};
+
+}  // namespace
+
+int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params, const sv_apply_opts &opts,
+               std::string &err)
+{
+    const int n = p->n;
+    const int esize = p->dtype == SV_C64 ? 8 : 16;
+    std::vector<OpInfo> info(n_ops);
+    for (size_t k = 0; k < n_ops; ++k) info[k] = normalize(ops[k], params);
+
+    p->info = sv_plan_info{};
+    p->info.n_ops = n_ops;
+
+    // ---- tile geometry ----
+    int rb = opts.reg_qubits ? opts.reg_qubits : 4;
+    int b = opts.tile_qubits ? opts.tile_qubits : (p->dtype == SV_C64 ? 12 : 12);
+    bool fused = opts.mode == SV_MODE_FUSED;
+    if (fused) {
+        if (rb < 4 || rb > kMaxRB) {
+            err = "reg_qubits must be 4 or 5";
+            return SV_EINVAL;
+        }
+        if (b > n) b = n;
+        if (b > kMaxB || (size_t)esize << b > 160 * 1024) {
+            err = "tile_qubits too large for LDS";
+            return SV_EINVAL;
+        }
+        if (b - rb > 8) {
+            err = "tile_qubits - reg_qubits must be at most 8 (256 threads)";
+            return SV_EINVAL;
+        }
+        if (b - rb < 6) fused = false;  // fewer than 64 threads: use plain launches
+        if (n - b > 48) {
+            err = "too many tile qubits";
+            return SV_EUNSUPPORTED;
+        }
+    }
+    p->b = fused ? b : 0;
+    p->rb = fused ? rb : 0;
+    p->info.tile_qubits = p->b;
+    p->info.reg_qubits = p->rb;
+
+    p->steps.clear();
+    p->plain.clear();
+    p->passes.clear();
+    p->stages.clear();
+    p->tops.clear();
+    p->tparams.clear();
+
+    auto add_plain = [&](const OpInfo &o) {
+        p->steps.push_back(Step{0, (uint32_t)p->plain.size()});
+        p->plain.push_back(to_plain(o));
+        p->info.bytes_moved += plain_bytes(o, n, esize);
+    };
+
+    if (!fused) {
+        for (size_t k = 0; k < n_ops; ++k) add_plain(info[k]);
+        p->info.n_launches = p->steps.size();
+        return SV_OK;
+    }
+
+    const int nthr = b - rb;
+    const int L0 = std::min(nthr, p->dtype == SV_C64 ? 5 : 4);
+    const uint64_t lowmask = (1ull << L0) - 1ull;
+    const size_t W = 1024;
+
+    std::vector<char> done(n_ops, 0);
+    size_t first = 0;
+    while (true) {
+        while (first < n_ops && done[first]) ++first;
+        if (first >= n_ops) break;
+        if (__builtin_popcountll(info[first].req | lowmask) > b) {
+            // cannot be made resident: its own launch (all earlier ops are done)
+            add_plain(info[first]);
+            done[first] = 1;
+            continue;
+        }
+        PassBuild pb;
+        pb.S = lowmask;
+        const size_t wend = std::min(n_ops, first + W);
+        while (true) {
+            uint64_t Z = 0, X = 0, G = 0;
+            long cand = -1;
+            for (size_t j = first; j < wend; ++j) {
+                if (done[j]) continue;
+                const OpInfo &o = info[j];
+                const bool ready = commutes_with_all(o, Z, X, G);
+                if (ready && (o.req & ~pb.S) == 0) {
+                    done[j] = 1;
+                    pb.ops.push_back((uint32_t)j);
+                    continue;
+                }
+                if (ready && cand < 0 && __builtin_popcountll(pb.S | o.req) <= b) cand = (long)j;
+                Z |= o.z;
+                X |= o.x;
+                G |= o.g;
+            }
+            if (cand < 0) break;
+            pb.S |= info[cand].req;
+        }
+        // fill the resident set up to b qubits with the lowest unused ones
+        for (int q = 0; q < n && __builtin_popcountll(pb.S) < b; ++q) pb.S |= 1ull << q;
+
+        // ---- lay out the pass ----
+        TilePass P{};
+        P.b = (uint8_t)b;
+        P.rb = (uint8_t)rb;
+        P.nthr = (uint8_t)nthr;
+        P.ntile = (uint8_t)(n - b);
+        int lpos[64];
+        for (int q = 0; q < 64; ++q) lpos[q] = -1;
+        {
+            int k = 0, t = 0;
+            for (int q = 0; q < n; ++q) {
+                if ((pb.S >> q) & 1ull) {
+                    P.spos[k] = (uint8_t)q;
+                    lpos[q] = k++;
+                } else {
+                    P.tpos[t++] = (uint8_t)q;
+                }
+            }
+        }
+        for (int s = 0; s < (1 << rb); ++s) {
+            uint64_t off = 0;
+            for (int k = 0; k < rb; ++k)
+                if ((s >> k) & 1) off |= 1ull << P.spos[nthr + k];
+            P.goff[s] = off;
+        }
+        auto split = [&](uint64_t mask, uint64_t val, TileOp &t) {
+            t.lmask = 0;
+            t.lval = 0;
+            for (int q = 0; q < n; ++q) {
+                if (!((mask >> q) & 1ull) || !((pb.S >> q) & 1ull)) continue;
+                t.lmask |= 1u << lpos[q];
+                if ((val >> q) & 1ull) t.lval |= 1u << lpos[q];
+            }
+            t.gmask = mask & ~pb.S;
+            t.gval = val & ~pb.S;
+        };
+
+        // register sets: slot k <-> local bit rs[k]
+        std::vector<int> cur_rs(rb);
+        for (int k = 0; k < rb; ++k) cur_rs[k] = nthr + k;
+        auto open_stage = [&](const std::vector<int> &rs, uint32_t perm_b, uint32_t perm_e) {
+            TileStage S{};
+            S.op_begin = S.op_end = (uint32_t)p->tops.size();
+            S.perm_begin = perm_b;
+            S.perm_end = perm_e;
+            std::vector<char> isreg(b, 0);
+            for (int k = 0; k < rb; ++k) isreg[rs[k]] = 1;
+            int j = 0;
+            for (int l = 0; l < b; ++l)
+                if (!isreg[l]) S.thrpos[j++] = (uint8_t)l;
+            for (int s = 0; s < (1 << rb); ++s) {
+                uint32_t off = 0;
+                for (int k = 0; k < rb; ++k)
+                    if ((s >> k) & 1) off |= 1u << rs[k];
+                S.regoff[s] = (uint16_t)off;
+            }
+            p->stages.push_back(S);
+        };
+        auto is_reg_kind = [&](uint32_t k) { return k == SV_OP_U || k == SV_OP_X; };
+        auto is_perm_kind = [&](uint32_t k) { return k == SV_OP_INC || k == SV_OP_DEC || k == SV_OP_SWAP; };
+
+        P.stage_begin = (uint32_t)p->stages.size();
+        // perms are collected in a side list and copied into tops when a stage opens
+        std::vector<TileOp> pending;
+        open_stage(cur_rs, 0, 0);
+        auto flush_into_new_stage = [&](const std::vector<int> &rs) {
+            // close current stage's op range, then append pending perms and open the next stage
+            p->stages.back().op_end = (uint32_t)p->tops.size();
+            const uint32_t pbeg = (uint32_t)p->tops.size();
+            for (auto &t : pending) p->tops.push_back(t);
+            const uint32_t pend = (uint32_t)p->tops.size();
+            pending.clear();
+            open_stage(rs, pbeg, pend);
+            cur_rs = rs;
+        };
+        auto choose_rs = [&](size_t from) {
+            std::vector<int> rs;
+            for (size_t i = from; i < pb.ops.size() && (int)rs.size() < rb; ++i) {
+                const OpInfo &o = info[pb.ops[i]];
+                if (is_perm_kind(o.kind)) break;
+                if (!is_reg_kind(o.kind)) continue;
+                const int l = lpos[o.target];
+                if (std::find(rs.begin(), rs.end(), l) == rs.end()) rs.push_back(l);
+            }
+            for (int k = 0; k < rb && (int)rs.size() < rb; ++k)
+                if (std::find(rs.begin(), rs.end(), cur_rs[k]) == rs.end()) rs.push_back(cur_rs[k]);
+            for (int l = 0; l < b && (int)rs.size() < rb; ++l)
+                if (std::find(rs.begin(), rs.end(), l) == rs.end()) rs.push_back(l);
+            std::sort(rs.begin(), rs.end());
+            return rs;
+        };
+
+        for (size_t i = 0; i < pb.ops.size(); ++i) {
+            const OpInfo &o = info[pb.ops[i]];
+            TileOp t{};
+            if (is_perm_kind(o.kind)) {
+                split(o.mask, o.val, t);
+                if (o.kind == SV_OP_SWAP) {
+                    t.kind = T_SWAP;
+                    t.a = (uint8_t)lpos[o.target];
+                    t.b = (uint8_t)lpos[o.width];
+                } else {
+                    t.kind = o.kind == SV_OP_INC ? T_INC : T_DEC;
+                    t.a = (uint8_t)lpos[o.target];
+                    t.b = (uint8_t)o.width;
+                }
+                pending.push_back(t);
+                continue;
+            }
+            if (is_reg_kind(o.kind)) {
+                const int l = lpos[o.target];
+                auto it = std::find(cur_rs.begin(), cur_rs.end(), l);
+                if (it == cur_rs.end() || !pending.empty()) {
+                    flush_into_new_stage(it == cur_rs.end() ? choose_rs(i) : cur_rs);
+                    it = std::find(cur_rs.begin(), cur_rs.end(), l);
+                }
+                split(o.mask, o.val, t);
+                t.slot = (uint8_t)(it - cur_rs.begin());
+                if (o.kind == SV_OP_U) {
+                    t.kind = T_U;
+                    t.param = (uint32_t)p->tparams.size();
+                    for (int k = 0; k < 8; ++k) p->tparams.push_back(o.m[k]);
+                } else {
+                    t.kind = T_X;
+                }
+                p->tops.push_back(t);
+                continue;
+            }
+            // diagonal ops
+            if (!pending.empty()) flush_into_new_stage(cur_rs);
+            if (o.kind == SV_OP_PHASE) {
+                split(o.mask | (1ull << o.target), o.val | (1ull << o.target), t);
+                t.kind = T_PHASE;
+            } else {  // PROJPHASE
+                split(o.mask, o.val, t);
+                t.kind = T_PROJ;
+                if ((pb.S >> o.target) & 1ull) {
+                    t.a = (uint8_t)lpos[o.target];
+                } else {
+                    t.a = 0xff;
+                    t.b = (uint8_t)o.target;
+                }
+            }
+            t.param = (uint32_t)p->tparams.size();
+            p->tparams.push_back(std::cos(o.m[0]));
+            p->tparams.push_back(std::sin(o.m[0]));
+            p->tops.push_back(t);
+        }
+        p->stages.back().op_end = (uint32_t)p->tops.size();
+        P.stage_end = (uint32_t)p->stages.size();
+        bool at_load_mapping = true;
+        for (int k = 0; k < rb; ++k) at_load_mapping = at_load_mapping && cur_rs[k] == nthr + k;
+        P.fperm_begin = (uint32_t)p->tops.size();
+        for (auto &t : pending) p->tops.push_back(t);
+        P.fperm_end = (uint32_t)p->tops.size();
+        P.final_exchange = (!at_load_mapping || !pending.empty()) ? 1 : 0;
+        pending.clear();
+
+        p->steps.push_back(Step{1, (uint32_t)p->passes.size()});
+        p->passes.push_back(P);
+        p->info.n_tile_passes += 1;
+        p->info.n_stages += P.stage_end - P.stage_begin;
+        p->info.bytes_moved += 2ull * (1ull << n) * esize;
+    }
+    p->info.tile_pass_bytes = 2ull * (1ull << n) * esize;
+    p->info.n_launches = p->steps.size();
+    return SV_OK;
+}
+
+}  // namespace svi

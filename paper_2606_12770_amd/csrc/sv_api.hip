@@ -1,0 +1,475 @@
+// C ABI of libsv: argument validation, state and plan lifetime, execution.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+
+#include "sv_internal.h"
+
+namespace svi {
+int tile_kernel_setup();
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(SV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int ensure_device_setup(int dev)
+{
+    static std::mutex mu;
+    static std::set<int> ready;
+    std::lock_guard<std::mutex> lk(mu);
+    if (ready.count(dev)) return SV_OK;
+    int rc = svi::tile_kernel_setup();
+    if (rc != SV_OK) return fail(rc, "could not raise the LDS limit of the tile kernels");
+    ready.insert(dev);
+    return SV_OK;
+}
+
+int validate_ops(int n, const sv_op *ops, size_t n_ops, const double *params, size_t n_params)
+{
+    if (n_ops && !ops) return fail(SV_EINVAL, "ops is NULL");
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    char buf[256];
+    for (size_t k = 0; k < n_ops; ++k) {
+        const sv_op &o = ops[k];
+        auto bad = [&](const char *why) {
+            snprintf(buf, sizeof buf, "op %zu (kind %u): %s", k, o.kind, why);
+            return fail(SV_EINVAL, buf);
+        };
+        if (o.kind > SV_OP_PROJPHASE) return bad("unknown kind");
+        if (o.flags != 0) return bad("flags must be 0");
+        if (o.ctrl_val & ~o.ctrl_mask) return bad("ctrl_val has bits outside ctrl_mask");
+        if (o.ctrl_mask & ~all) return bad("control qubit >= n");
+        size_t np = 0;
+        switch (o.kind) {
+        case SV_OP_U: np = 8; break;
+        case SV_OP_PHASE:
+        case SV_OP_RY:
+        case SV_OP_PROJPHASE: np = 1; break;
+        default: break;
+        }
+        if (np && (!params || o.param + np > n_params)) return bad("parameter offset out of range");
+        switch (o.kind) {
+        case SV_OP_U:
+        case SV_OP_X:
+        case SV_OP_PHASE:
+        case SV_OP_RY:
+        case SV_OP_PROJPHASE:
+            if ((int)o.target >= n) return bad("target qubit >= n");
+            if ((o.ctrl_mask >> o.target) & 1ull) return bad("target is also a control");
+            if (o.width != 0) return bad("width must be 0");
+            break;
+        case SV_OP_INC:
+        case SV_OP_DEC: {
+            if (o.width < 1 || o.width > 24) return bad("register width must be in [1, 24]");
+            if ((int)(o.target + o.width) > n) return bad("register exceeds the qubit count");
+            const uint64_t reg = ((1ull << o.width) - 1ull) << o.target;
+            if (reg & o.ctrl_mask) return bad("register overlaps the controls");
+            break;
+        }
+        case SV_OP_SWAP:
+            if ((int)o.target >= n || (int)o.width >= n) return bad("swap qubit >= n");
+            if (o.target == o.width) return bad("swap of a qubit with itself");
+            if (((o.ctrl_mask >> o.target) & 1ull) || ((o.ctrl_mask >> o.width) & 1ull))
+                return bad("swap qubit is also a control");
+            break;
+        }
+    }
+    return SV_OK;
+}
+
+size_t esize(int dtype) { return dtype == SV_C64 ? 8 : 16; }
+
+struct Scratch {
+    double *d_partial = nullptr;  // kReduceBlocks * 2 doubles + 2 result doubles
+    double *d_out() { return d_partial + 2 * svi::kReduceBlocks; }
+};
+
+// per-state reduction scratch, allocated with the state
+struct StateExt {
+    sv_state s;
+    Scratch scratch;
+};
+
+StateExt *ext(const sv_state *s) { return reinterpret_cast<StateExt *>(const_cast<sv_state *>(s)); }
+
+int upload_plan(sv_plan *p)
+{
+    HIP_TRY(hipGetDevice(&p->device));
+    auto up = [&](void **dst, const void *src, size_t bytes) -> int {
+        if (!bytes) bytes = 16;
+        HIP_TRY(hipMalloc(dst, bytes));
+        if (src) HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return SV_OK;
+    };
+    int rc;
+    if ((rc = up(&p->d_passes, p->passes.empty() ? nullptr : p->passes.data(),
+                 p->passes.size() * sizeof(svi::TilePass))) != SV_OK)
+        return rc;
+    if ((rc = up(&p->d_stages, p->stages.empty() ? nullptr : p->stages.data(),
+                 p->stages.size() * sizeof(svi::TileStage))) != SV_OK)
+        return rc;
+    if ((rc = up(&p->d_tops, p->tops.empty() ? nullptr : p->tops.data(), p->tops.size() * sizeof(svi::TileOp))) !=
+        SV_OK)
+        return rc;
+    if (p->dtype == SV_C64) {
+        std::vector<float> f(p->tparams.begin(), p->tparams.end());
+        rc = up(&p->d_tparams, f.empty() ? nullptr : f.data(), f.size() * sizeof(float));
+    } else {
+        rc = up(&p->d_tparams, p->tparams.empty() ? nullptr : p->tparams.data(), p->tparams.size() * sizeof(double));
+    }
+    return rc;
+}
+
+void release_plan(sv_plan *p)
+{
+    if (p->d_passes) (void)hipFree(p->d_passes);
+    if (p->d_stages) (void)hipFree(p->d_stages);
+    if (p->d_tops) (void)hipFree(p->d_tops);
+    if (p->d_tparams) (void)hipFree(p->d_tparams);
+    p->d_passes = p->d_stages = p->d_tops = p->d_tparams = nullptr;
+}
+
+int run_plan_once(const sv_plan *p, sv_state *s)
+{
+    for (const auto &st : p->steps) {
+        int rc = st.type == 0 ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, s->stream)
+                              : svi::launch_tile_pass(p, st.index, s->d_psi, s->stream);
+        if (rc != SV_OK) return fail(rc, "kernel launch failed");
+    }
+    return SV_OK;
+}
+
+int check_plan_state(const sv_plan *p, const sv_state *s)
+{
+    if (!p || !s) return fail(SV_EINVAL, "NULL plan or state");
+    if (p->n != s->n || p->dtype != s->dtype) return fail(SV_EINVAL, "plan and state differ in size or precision");
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_strerror(int code)
+{
+    switch (code) {
+    case SV_OK: return "ok";
+    case SV_EINVAL: return "invalid argument";
+    case SV_ENOMEM: return "out of device memory";
+    case SV_EZEROPROB: return "post-selection on a zero-probability subspace";
+    case SV_EDEVICE: return "HIP runtime error";
+    case SV_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown error";
+    }
+}
+
+const char *sv_last_error(void) { return g_last_error.c_str(); }
+
+int sv_alloc(int n_qubits, int dtype, const double *init, void *stream, sv_state **out)
+{
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 36) return fail(SV_EINVAL, "n_qubits must be in [1, 36]");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    const size_t bytes = esize(dtype) << n_qubits;
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (bytes + (64ull << 20) > free_b) return fail(SV_ENOMEM, "state does not fit in free device memory");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int rc = ensure_device_setup(dev);
+    if (rc != SV_OK) return rc;
+
+    StateExt *e = new (std::nothrow) StateExt();
+    if (!e) return fail(SV_ENOMEM, "host allocation failed");
+    e->s.n = n_qubits;
+    e->s.dtype = dtype;
+    e->s.device = dev;
+    hipError_t he = hipMalloc(&e->s.d_psi, bytes);
+    if (he != hipSuccess) {
+        delete e;
+        (void)hipGetLastError();
+        return fail(SV_ENOMEM, "hipMalloc of the state failed");
+    }
+    he = hipMalloc((void **)&e->scratch.d_partial, sizeof(double) * (2 * svi::kReduceBlocks + 2));
+    if (he != hipSuccess) {
+        (void)hipFree(e->s.d_psi);
+        delete e;
+        return fail(SV_ENOMEM, "hipMalloc of the reduction scratch failed");
+    }
+    if (stream) {
+        e->s.stream = (hipStream_t)stream;
+    } else {
+        he = hipStreamCreateWithFlags(&e->s.stream, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            (void)hipFree(e->s.d_psi);
+            (void)hipFree(e->scratch.d_partial);
+            delete e;
+            return hip_fail(he, "hipStreamCreateWithFlags");
+        }
+        e->s.own_stream = true;
+    }
+    if (init) {
+        rc = sv_set_amplitudes(&e->s, 0, 1ull << n_qubits, init);
+    } else {
+        rc = svi::launch_init_basis(e->s.d_psi, n_qubits, dtype, e->s.stream);
+        if (rc == SV_OK && hipStreamSynchronize(e->s.stream) != hipSuccess) rc = fail(SV_EDEVICE, "init failed");
+    }
+    if (rc != SV_OK) {
+        sv_free(&e->s);
+        return rc;
+    }
+    *out = &e->s;
+    return SV_OK;
+}
+
+int sv_free(sv_state *s)
+{
+    if (!s) return SV_OK;
+    StateExt *e = ext(s);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->d_psi) (void)hipFree(s->d_psi);
+    if (e->scratch.d_partial) (void)hipFree(e->scratch.d_partial);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete e;
+    return SV_OK;
+}
+
+int sv_info(const sv_state *s, int *n_qubits, int *dtype)
+{
+    if (!s) return fail(SV_EINVAL, "NULL state");
+    if (n_qubits) *n_qubits = s->n;
+    if (dtype) *dtype = s->dtype;
+    return SV_OK;
+}
+
+int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, const double *params, size_t n_params,
+                   const sv_apply_opts *opts, sv_plan **out)
+{
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 36) return fail(SV_EINVAL, "n_qubits must be in [1, 36]");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    sv_apply_opts o{};
+    o.mode = SV_MODE_FUSED;
+    if (opts) o = *opts;
+    if (o.mode != SV_MODE_PLAIN && o.mode != SV_MODE_FUSED) return fail(SV_EINVAL, "unknown mode");
+    if (o.reserved != 0) return fail(SV_EINVAL, "reserved option must be 0");
+    int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
+    if (rc != SV_OK) return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    rc = ensure_device_setup(dev);
+    if (rc != SV_OK) return rc;
+    sv_plan *p = new (std::nothrow) sv_plan();
+    if (!p) return fail(SV_ENOMEM, "host allocation failed");
+    p->n = n_qubits;
+    p->dtype = dtype;
+    std::string err;
+    rc = svi::build_plan(p, ops, n_ops, params, o, err);
+    if (rc != SV_OK) {
+        delete p;
+        return fail(rc, err);
+    }
+    rc = upload_plan(p);
+    if (rc != SV_OK) {
+        release_plan(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SV_OK;
+}
+
+int sv_plan_free(sv_plan *p)
+{
+    if (!p) return SV_OK;
+    release_plan(p);
+    delete p;
+    return SV_OK;
+}
+
+int sv_plan_get_info(const sv_plan *p, sv_plan_info *info)
+{
+    if (!p || !info) return fail(SV_EINVAL, "NULL argument");
+    *info = p->info;
+    return SV_OK;
+}
+
+int sv_plan_execute(sv_plan *p, sv_state *s, int repeat)
+{
+    int rc = check_plan_state(p, s);
+    if (rc != SV_OK) return rc;
+    if (repeat < 0) return fail(SV_EINVAL, "repeat < 0");
+    for (int r = 0; r < repeat; ++r)
+        if ((rc = run_plan_once(p, s)) != SV_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+int sv_plan_execute_seq(sv_plan *const *plans, const int32_t *seq, size_t seq_len, sv_state *s)
+{
+    if (!plans || (!seq && seq_len)) return fail(SV_EINVAL, "NULL argument");
+    for (size_t k = 0; k < seq_len; ++k) {
+        int rc = check_plan_state(plans[seq[k]], s);
+        if (rc != SV_OK) return rc;
+    }
+    for (size_t k = 0; k < seq_len; ++k) {
+        int rc = run_plan_once(plans[seq[k]], s);
+        if (rc != SV_OK) return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+int sv_plan_time(sv_plan *p, sv_state *s, int repeat, double *ms)
+{
+    int rc = check_plan_state(p, s);
+    if (rc != SV_OK) return rc;
+    if (!ms || repeat < 1) return fail(SV_EINVAL, "ms is NULL or repeat < 1");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s->stream));
+    for (int r = 0; r < repeat && rc == SV_OK; ++r) rc = run_plan_once(p, s);
+    HIP_TRY(hipEventRecord(e1, s->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = f;
+    return rc;
+}
+
+int sv_apply_circuit(sv_state *s, const sv_op *ops, size_t n_ops, const double *params, size_t n_params,
+                     const sv_apply_opts *opts)
+{
+    if (!s) return fail(SV_EINVAL, "NULL state");
+    sv_plan *p = nullptr;
+    int rc = sv_plan_create(s->n, s->dtype, ops, n_ops, params, n_params, opts, &p);
+    if (rc != SV_OK) return rc;
+    rc = sv_plan_execute(p, s, 1);
+    sv_plan_free(p);
+    return rc;
+}
+
+int sv_postselect(sv_state *s, uint64_t mask, uint64_t value, int keep, int renormalize, double *prob_out)
+{
+    if (!s) return fail(SV_EINVAL, "NULL state");
+    const uint64_t all = (1ull << s->n) - 1ull;
+    if ((mask & ~all) || (value & ~mask)) return fail(SV_EINVAL, "mask/value outside the state or value not in mask");
+    Scratch &sc = ext(s)->scratch;
+    int rc = svi::launch_prob(s->d_psi, s->n, s->dtype, mask, value, sc.d_partial, svi::kReduceBlocks, sc.d_out(),
+                              s->stream);
+    if (rc != SV_OK) return fail(rc, "reduction launch failed");
+    double P = 0.0;
+    HIP_TRY(hipMemcpyAsync(&P, sc.d_out(), sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (prob_out) *prob_out = P;
+    if (!keep) return SV_OK;
+    if (!(P > 0.0)) return fail(SV_EZEROPROB, "post-selected subspace has probability 0");
+    const double scale = renormalize ? 1.0 / std::sqrt(P) : 1.0;
+    rc = svi::launch_keep_scale(s->d_psi, s->n, s->dtype, mask, value, scale, s->stream);
+    if (rc != SV_OK) return fail(rc, "post-selection launch failed");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+static const uint64_t kChunk = 1ull << 22;  // amplitudes per staged copy (64 MiB of complex128)
+
+int sv_amplitudes(const sv_state *s, uint64_t offset, uint64_t count, double *out)
+{
+    if (!s || (!out && count)) return fail(SV_EINVAL, "NULL argument");
+    const uint64_t dim = 1ull << s->n;
+    if (offset > dim || count > dim - offset) return fail(SV_EINVAL, "range outside the state");
+    if (!count) return SV_OK;
+    void *stage = nullptr;
+    const uint64_t cap = count < kChunk ? count : kChunk;
+    HIP_TRY(hipMalloc(&stage, cap * 16));
+    int rc = SV_OK;
+    for (uint64_t k = 0; k < count && rc == SV_OK; k += cap) {
+        const uint64_t m = (count - k) < cap ? (count - k) : cap;
+        rc = svi::launch_to_c128(s->d_psi, s->dtype, stage, offset + k, m, s->stream);
+        if (rc == SV_OK && hipMemcpyAsync(out + 2 * k, stage, m * 16, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+            rc = fail(SV_EDEVICE, "device-to-host copy failed");
+        if (rc == SV_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(SV_EDEVICE, "sync failed");
+    }
+    (void)hipFree(stage);
+    return rc;
+}
+
+int sv_set_amplitudes(sv_state *s, uint64_t offset, uint64_t count, const double *in)
+{
+    if (!s || (!in && count)) return fail(SV_EINVAL, "NULL argument");
+    const uint64_t dim = 1ull << s->n;
+    if (offset > dim || count > dim - offset) return fail(SV_EINVAL, "range outside the state");
+    if (!count) return SV_OK;
+    void *stage = nullptr;
+    const uint64_t cap = count < kChunk ? count : kChunk;
+    HIP_TRY(hipMalloc(&stage, cap * 16));
+    int rc = SV_OK;
+    for (uint64_t k = 0; k < count && rc == SV_OK; k += cap) {
+        const uint64_t m = (count - k) < cap ? (count - k) : cap;
+        if (hipMemcpyAsync(stage, in + 2 * k, m * 16, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+            rc = fail(SV_EDEVICE, "host-to-device copy failed");
+        if (rc == SV_OK) rc = svi::launch_from_c128(s->d_psi, s->dtype, stage, offset + k, m, s->stream);
+        if (rc == SV_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(SV_EDEVICE, "sync failed");
+    }
+    (void)hipFree(stage);
+    return rc;
+}
+
+int sv_copy(sv_state *dst, const sv_state *src)
+{
+    if (!dst || !src) return fail(SV_EINVAL, "NULL state");
+    if (dst->n != src->n) return fail(SV_EINVAL, "states differ in qubit count");
+    HIP_TRY(hipStreamSynchronize(src->stream));
+    int rc = svi::launch_copy(dst->d_psi, dst->dtype, src->d_psi, src->dtype, dst->n, dst->stream);
+    if (rc != SV_OK) return fail(rc, "copy launch failed");
+    HIP_TRY(hipStreamSynchronize(dst->stream));
+    return SV_OK;
+}
+
+int sv_inner(const sv_state *a, const sv_state *b, double *re, double *im)
+{
+    if (!a || !b) return fail(SV_EINVAL, "NULL state");
+    if (a->n != b->n) return fail(SV_EINVAL, "states differ in qubit count");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    Scratch &sc = ext(a)->scratch;
+    int rc = svi::launch_inner(a->d_psi, a->dtype, b->d_psi, b->dtype, a->n, sc.d_partial, svi::kReduceBlocks,
+                               sc.d_out(), a->stream);
+    if (rc != SV_OK) return fail(rc, "inner-product launch failed");
+    double v[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(v, sc.d_out(), sizeof v, hipMemcpyDeviceToHost, a->stream));
+    HIP_TRY(hipStreamSynchronize(a->stream));
+    if (re) *re = v[0];
+    if (im) *im = v[1];
+    return SV_OK;
+}
+
+}  // extern "C"

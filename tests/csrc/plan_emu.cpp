@@ -1,0 +1,278 @@
+// CPU emulation of libsv's launch steps, used only by the host-side tests of
+// the planner.  It runs the planner's tile programs exactly as the tile kernel
+// does (same load mapping, register stages, LDS exchanges with permutations,
+// final exchange) in double precision on a host array, and checks on the way
+// that every global and LDS index is in range, that each exchange writes every
+// LDS cell exactly once, and that each pass reads and writes every amplitude
+// exactly once.  Return codes: 0 ok, >0 a violated check, <0 planner error.
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "plan_types.h"
+
+using cd = std::complex<double>;
+using namespace svi;
+
+namespace {
+
+uint64_t deposit_zeros(uint64_t x, uint64_t fixed)
+{
+    for (int p = 0; p < 64; ++p) {
+        if (!((fixed >> p) & 1ull)) continue;
+        x = ((x >> p) << (p + 1)) | (x & ((1ull << p) - 1ull));
+    }
+    return x;
+}
+
+void emu_plain(const PlainOp &op, int n, cd *psi)
+{
+    const int c = __builtin_popcountll(op.mask);
+    const uint64_t tb = 1ull << op.target;
+    switch (op.kind) {
+    case SV_OP_U: {
+        const cd m0(op.m[0], op.m[1]), m1(op.m[2], op.m[3]), m2(op.m[4], op.m[5]), m3(op.m[6], op.m[7]);
+        for (uint64_t w = 0; w < (1ull << (n - 1 - c)); ++w) {
+            const uint64_t i0 = deposit_zeros(w, op.mask | tb) | op.val, i1 = i0 | tb;
+            const cd a = psi[i0], b = psi[i1];
+            psi[i0] = m0 * a + m1 * b;
+            psi[i1] = m2 * a + m3 * b;
+        }
+        break;
+    }
+    case SV_OP_X:
+        for (uint64_t w = 0; w < (1ull << (n - 1 - c)); ++w) {
+            const uint64_t i0 = deposit_zeros(w, op.mask | tb) | op.val;
+            std::swap(psi[i0], psi[i0 | tb]);
+        }
+        break;
+    case SV_OP_PHASE:
+        for (uint64_t w = 0; w < (1ull << (n - 1 - c)); ++w)
+            psi[deposit_zeros(w, op.mask | tb) | op.val | tb] *= std::polar(1.0, op.m[0]);
+        break;
+    case SV_OP_SWAP: {
+        const uint64_t ab = tb, bb = 1ull << op.width;
+        for (uint64_t w = 0; w < (1ull << (n - 2 - c)); ++w) {
+            const uint64_t i = deposit_zeros(w, op.mask | ab | bb) | op.val | ab;
+            std::swap(psi[i], psi[i ^ ab ^ bb]);
+        }
+        break;
+    }
+    case SV_OP_INC:
+    case SV_OP_DEC: {
+        const uint64_t len = 1ull << op.width, reg = (len - 1) << op.target;
+        for (uint64_t w = 0; w < (1ull << (n - (int)op.width - c)); ++w) {
+            const uint64_t r = deposit_zeros(w, op.mask | reg) | op.val;
+            std::vector<cd> cyc(len);
+            for (uint64_t v = 0; v < len; ++v) cyc[v] = psi[r | (v << op.target)];
+            for (uint64_t v = 0; v < len; ++v) {
+                const uint64_t src = op.kind == SV_OP_INC ? (v + len - 1) % len : (v + 1) % len;
+                psi[r | (v << op.target)] = cyc[src];
+            }
+        }
+        break;
+    }
+    case SV_OP_PROJPHASE:
+        for (uint64_t i = 0; i < (1ull << n); ++i) {
+            const int z = (i & op.mask) == op.val, s = (i >> op.target) & 1;
+            psi[i] *= std::polar(1.0, op.m[0] * (1 - 2 * (s ^ z)));
+        }
+        break;
+    }
+}
+
+uint32_t perms(uint32_t l, const std::vector<TileOp> &ops, uint32_t pb, uint32_t pe, uint64_t base)
+{
+    for (uint32_t k = pb; k < pe; ++k) {
+        const TileOp &p = ops[k];
+        if ((base & p.gmask) != p.gval) continue;
+        if ((l & p.lmask) != p.lval) continue;
+        if (p.kind == T_INC || p.kind == T_DEC) {
+            const uint32_t m = (1u << p.b) - 1u;
+            uint32_t v = (l >> p.a) & m;
+            v = (p.kind == T_INC ? v + 1u : v - 1u) & m;
+            l = (l & ~(m << p.a)) | (v << p.a);
+        } else if (p.kind == T_SWAP) {
+            if (((l >> p.a) ^ (l >> p.b)) & 1u) l ^= (1u << p.a) | (1u << p.b);
+        } else if (p.kind == T_XFLIP) {
+            l ^= 1u << p.a;
+        }
+    }
+    return l;
+}
+
+int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::vector<int> &wr)
+{
+    const TilePass &P = p.passes[pi];
+    const int n = p.n, b = P.b, rb = P.rb, nthr = P.nthr, NR = 1 << rb, T = 1 << nthr;
+    const uint64_t dim = 1ull << n;
+    if (b != nthr + rb || P.ntile != n - b) return 1;
+    std::fill(rd.begin(), rd.end(), 0);
+    std::fill(wr.begin(), wr.end(), 0);
+    std::vector<cd> x((size_t)T * NR), lds((size_t)1 << b);
+    std::vector<int> filled((size_t)1 << b);
+    std::vector<uint32_t> thr(T);
+    std::vector<uint32_t> ro(NR);
+    for (uint64_t tile = 0; tile < (1ull << P.ntile); ++tile) {
+        uint64_t base = 0;
+        for (int j = 0; j < P.ntile; ++j) base |= ((tile >> j) & 1ull) << P.tpos[j];
+        auto gidx = [&](int t, int s) {
+            uint64_t g = 0;
+            for (int j = 0; j < nthr; ++j) g |= (uint64_t)((t >> j) & 1) << P.spos[j];
+            return base | g | P.goff[s];
+        };
+        for (int t = 0; t < T; ++t)
+            for (int s = 0; s < NR; ++s) {
+                const uint64_t g = gidx(t, s);
+                if (g >= dim) return 2;
+                rd[g]++;
+                x[(size_t)t * NR + s] = psi[g];
+            }
+        for (int t = 0; t < T; ++t) thr[t] = t;
+        for (int s = 0; s < NR; ++s) ro[s] = (uint32_t)s << nthr;
+        auto exchange = [&](uint32_t pb, uint32_t pe, const uint8_t *thrpos, const uint16_t *regoff) -> int {
+            std::fill(filled.begin(), filled.end(), 0);
+            for (int t = 0; t < T; ++t)
+                for (int s = 0; s < NR; ++s) {
+                    const uint32_t l = perms(thr[t] | ro[s], p.tops, pb, pe, base);
+                    if (l >= (1u << b)) return 3;
+                    if (filled[l]++) return 4;
+                    lds[l] = x[(size_t)t * NR + s];
+                }
+            for (int t = 0; t < T; ++t) {
+                uint32_t t2 = 0;
+                for (int j = 0; j < nthr; ++j) t2 |= (uint32_t)((t >> j) & 1) << thrpos[j];
+                thr[t] = t2;
+            }
+            for (int s = 0; s < NR; ++s) ro[s] = regoff[s];
+            for (int t = 0; t < T; ++t)
+                for (int s = 0; s < NR; ++s) {
+                    const uint32_t l = thr[t] | ro[s];
+                    if (l >= (1u << b) || !filled[l]) return 5;
+                    x[(size_t)t * NR + s] = lds[l];
+                }
+            return 0;
+        };
+        for (uint32_t st = P.stage_begin; st < P.stage_end; ++st) {
+            const TileStage &S = p.stages[st];
+            if (st != P.stage_begin) {
+                int rc = exchange(S.perm_begin, S.perm_end, S.thrpos, S.regoff);
+                if (rc) return rc;
+            }
+            for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
+                const TileOp &op = p.tops[k];
+                const double *prm = p.tparams.data() + op.param;
+                if (op.kind == T_PROJ) {
+                    const bool zg = (base & op.gmask) == op.gval;
+                    const uint32_t sglob = op.a == 0xff ? (uint32_t)((base >> op.b) & 1ull) : 0u;
+                    for (int t = 0; t < T; ++t)
+                        for (int s = 0; s < NR; ++s) {
+                            const uint32_t l = thr[t] | ro[s];
+                            const uint32_t z = (zg && ((l & op.lmask) == op.lval)) ? 1u : 0u;
+                            const uint32_t sb = op.a == 0xff ? sglob : ((l >> op.a) & 1u);
+                            x[(size_t)t * NR + s] *= cd(prm[0], (sb ^ z) ? -prm[1] : prm[1]);
+                        }
+                    continue;
+                }
+                if ((base & op.gmask) != op.gval) continue;
+                if (op.kind == T_PHASE) {
+                    for (int t = 0; t < T; ++t)
+                        for (int s = 0; s < NR; ++s)
+                            if (((thr[t] | ro[s]) & op.lmask) == op.lval) x[(size_t)t * NR + s] *= cd(prm[0], prm[1]);
+                    continue;
+                }
+                if (op.slot >= rb) return 6;
+                const int K = op.slot;
+                for (int t = 0; t < T; ++t)
+                    for (int s = 0; s < NR; ++s) {
+                        if (s & (1 << K)) continue;
+                        if (((thr[t] | ro[s]) & op.lmask) != op.lval) continue;
+                        cd &a = x[(size_t)t * NR + s];
+                        cd &bb = x[(size_t)t * NR + (s | (1 << K))];
+                        if (op.kind == T_U) {
+                            const cd m0(prm[0], prm[1]), m1(prm[2], prm[3]), m2(prm[4], prm[5]), m3(prm[6], prm[7]);
+                            const cd a0 = a, b0 = bb;
+                            a = m0 * a0 + m1 * b0;
+                            bb = m2 * a0 + m3 * b0;
+                        } else if (op.kind == T_X) {
+                            std::swap(a, bb);
+                        } else {
+                            return 7;
+                        }
+                    }
+            }
+        }
+        // the last stage must leave the load mapping unless a final exchange follows
+        if (P.final_exchange) {
+            uint8_t thrpos0[16];
+            uint16_t regoff0[1 << kMaxRB];
+            for (int j = 0; j < nthr; ++j) thrpos0[j] = (uint8_t)j;
+            for (int s = 0; s < NR; ++s) regoff0[s] = (uint16_t)(s << nthr);
+            int rc = exchange(P.fperm_begin, P.fperm_end, thrpos0, regoff0);
+            if (rc) return rc;
+        } else {
+            for (int t = 0; t < T; ++t)
+                if (thr[t] != (uint32_t)t) return 8;
+            for (int s = 0; s < NR; ++s)
+                if (ro[s] != ((uint32_t)s << nthr)) return 8;
+        }
+        for (int t = 0; t < T; ++t)
+            for (int s = 0; s < NR; ++s) {
+                const uint64_t g = gidx(t, s);
+                wr[g]++;
+                psi[g] = x[(size_t)t * NR + s];
+            }
+    }
+    for (uint64_t i = 0; i < dim; ++i)
+        if (rd[i] != 1 || wr[i] != 1) return 9;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode,
+                       int tile_qubits, int reg_qubits, double *psi_io, uint64_t *stats)
+{
+    sv_plan p;
+    p.n = n;
+    p.dtype = dtype;
+    sv_apply_opts o{mode, tile_qubits, reg_qubits, 0};
+    std::string err;
+    int rc = build_plan(&p, ops, n_ops, params, o, err);
+    if (rc != SV_OK) return rc;
+    cd *psi = reinterpret_cast<cd *>(psi_io);
+    std::vector<int> rd(1ull << n), wr(1ull << n);
+    for (const auto &st : p.steps) {
+        if (st.type == 0) {
+            emu_plain(p.plain[st.index], n, psi);
+        } else {
+            rc = emu_tile(p, st.index, psi, rd, wr);
+            if (rc) return 100 + rc;
+        }
+    }
+    if (stats) {
+        stats[0] = p.info.n_launches;
+        stats[1] = p.info.n_tile_passes;
+        stats[2] = p.info.n_stages;
+        stats[3] = p.info.bytes_moved;
+    }
+    return 0;
+}
+
+// Plan only (no emulation): launch/pass/stage counts and algorithmic bytes.
+extern "C" int emu_plan_stats(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode,
+                              int tile_qubits, int reg_qubits, uint64_t *stats)
+{
+    sv_plan p;
+    p.n = n;
+    p.dtype = dtype;
+    sv_apply_opts o{mode, tile_qubits, reg_qubits, 0};
+    std::string err;
+    int rc = build_plan(&p, ops, n_ops, params, o, err);
+    if (rc != SV_OK) return rc;
+    stats[0] = p.info.n_launches;
+    stats[1] = p.info.n_tile_passes;
+    stats[2] = p.info.n_stages;
+    stats[3] = p.info.bytes_moved;
+    return 0;
+}

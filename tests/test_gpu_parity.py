@@ -1,0 +1,165 @@
+"""GPU parity of the HIP path against the FP64 reference simulator.
+
+Bars: complex128 runs agree with the oracle to 1e-12 (max abs amplitude
+difference on normalised states) and infidelity <= 1e-12; complex64 runs to
+infidelity <= 1e-6; permutation-only circuits are bit-exact.  Sizes span
+several tiles and both tile geometries; the 28-qubit case is the benchmark's
+launch configuration on a prefix of its circuit.
+"""
+import numpy as np
+import pytest
+
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits.ir import Circuit
+from paper_2606_12770_amd.circuits.random_circuit import (random_layered_circuit, random_mixed_circuit,
+                                                          random_state)
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def infid(a, b):
+    return 1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+def run_gpu(sv, circ, psi0, dtype, mode, b=0, rb=0):
+    st = sv.State(circ.n, dtype, psi0)
+    st.apply(circ, mode, b, rb)
+    out = st.amplitudes()
+    st.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [6, 10, 14])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_plain_every_kind(n, dtype):
+    sv = require_gpu()
+    c = random_mixed_circuit(n, 300, seed=n + 10 * dtype, max_ctrl=min(5, n - 2))
+    psi0 = random_state(n, 1)
+    want = osv.run(c, psi0)
+    got = run_gpu(sv, c, psi0, dtype, sv.SV_MODE_PLAIN)
+    print(f"plain n={n} dtype={dtype} maxabs={np.max(np.abs(got - want)):.2e} infid={infid(want, got):.2e}", flush=True)
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+        assert infid(want, got) < 1e-12
+    else:
+        assert infid(want, got) < 1e-6
+
+
+@pytest.mark.parametrize("n,b,rb", [(10, 10, 4), (12, 12, 4), (14, 12, 4), (16, 12, 4), (16, 13, 5),
+                                    (18, 12, 4), (20, 11, 5)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_fused_mixed(n, b, rb, dtype):
+    sv = require_gpu()
+    if dtype == 1 and b == 13:
+        b = 12
+    c = random_mixed_circuit(n, 400, seed=3 * n + b + dtype, max_ctrl=6)
+    psi0 = random_state(n, 2)
+    want = osv.run(c, psi0)
+    got = run_gpu(sv, c, psi0, dtype, sv.SV_MODE_FUSED, b, rb)
+    print(f"fused n={n} b={b} rb={rb} dtype={dtype} infid={infid(want, got):.2e}", flush=True)
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+        assert infid(want, got) < 1e-12
+    else:
+        assert infid(want, got) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_layered_20q(dtype, mode):
+    sv = require_gpu()
+    n = 20
+    c = random_layered_circuit(n, 40, seed=5)
+    want = osv.run(c)
+    got = run_gpu(sv, c, osv.zero_state(n), dtype, mode)
+    f = infid(want, got)
+    print(f"layered n=20 dtype={dtype} mode={mode} infid={f:.2e}", flush=True)
+    assert f < (1e-12 if dtype == 1 else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_permutations_bit_exact(dtype, mode):
+    sv = require_gpu()
+    n = 16
+    rng = np.random.default_rng(7)
+    c = Circuit(n)
+    for _ in range(200):
+        k = int(rng.integers(0, 4))
+        qs = [int(v) for v in rng.permutation(n)]
+        ctrl = {q: int(rng.integers(0, 2)) for q in qs[2:2 + int(rng.integers(0, 4))]}
+        if k == 0:
+            c.x(qs[0], ctrl)
+        elif k == 1:
+            c.swap(qs[0], qs[1], ctrl)
+        else:
+            w = int(rng.integers(1, 7))
+            base = int(rng.integers(0, n - w + 1))
+            ctrl = {q: v for q, v in ctrl.items() if not base <= q < base + w}
+            (c.inc if k == 2 else c.dec)(base, w, ctrl)
+    psi0 = random_state(n, 8)
+    if dtype == 0:  # the state holds float values; permuting them must not change a bit
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = osv.run(c, psi0)
+    got = run_gpu(sv, c, psi0, dtype, mode)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_reductions_postselect_inner():
+    sv = require_gpu()
+    n = 18
+    psi = random_state(n, 4)
+    for dtype in (0, 1):
+        st = sv.State(n, dtype, psi)
+        assert abs(st.prob() - 1.0) < (1e-6 if dtype == 0 else 1e-13)
+        mask, val = 0b101000000000010001, 0b001000000000000001
+        idx = np.arange(1 << n)
+        keep = (idx & mask) == val
+        P = float(np.sum(np.abs(psi[keep]) ** 2))
+        assert abs(st.prob(mask, val) - P) < (1e-7 if dtype == 0 else 1e-14)
+        got = st.postselect(mask, val)
+        assert abs(got - P) < (1e-7 if dtype == 0 else 1e-14)
+        amp = st.amplitudes()
+        want = np.where(keep, psi / np.sqrt(P), 0)
+        assert np.max(np.abs(amp - want)) < (1e-5 if dtype == 0 else 1e-13)
+        other = sv.State(n, 1, random_state(n, 5))
+        ip = sv.sv_inner(st.h, other.h)
+        ref = np.vdot(amp, other.amplitudes())
+        assert abs(ip - ref) < 1e-12
+        st.close()
+        other.close()
+
+
+def test_errors_are_reported_before_launch():
+    sv = require_gpu()
+    n = 8
+    st = sv.State(n, 1)
+    bad = [Circuit(n).x(8), Circuit(n).x(2, [2]), Circuit(n).inc(6, 3), Circuit(n).swap(1, 1),
+           Circuit(n).inc(0, 3, [1])]
+    for c in bad:
+        with pytest.raises(sv.SVError) as e:
+            st.apply(c)
+        assert e.value.code == sv.SV_EINVAL
+    assert abs(st.amplitudes()[0] - 1.0) == 0.0  # untouched
+    # zero-probability post-selection leaves the state unchanged
+    with pytest.raises(sv.SVError) as e:
+        st.postselect(1, 1)
+    assert e.value.code == sv.SV_EZEROPROB
+    assert st.amplitudes()[0] == 1.0
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_benchmark_configuration_28q_prefix(dtype):
+    """28 qubits, the benchmark's fused launch configuration, on the first two
+    layers of the benchmark circuit, compared amplitude by amplitude with the
+    FP64 reference simulator."""
+    sv = require_gpu()
+    n = 28
+    c = random_layered_circuit(n, 2, seed=0)
+    want = osv.run(c)
+    got = run_gpu(sv, c, osv.zero_state(n), dtype, sv.SV_MODE_FUSED)
+    f = infid(want, got)
+    print(f"28q prefix dtype={dtype} infid={f:.2e}", flush=True)
+    assert f < (1e-12 if dtype == 1 else 1e-6)
