@@ -70,37 +70,66 @@ __device__ __forceinline__ uint32_t apply_perms(uint32_t l, const TileOp *__rest
     return l;
 }
 
+// Register-level ops: slot s (with the target slot bit clear) is processed when
+// bit s of the uniform slotmask is set; the thread part of the condition has
+// already been applied by the caller.
 template <int K, int NR, typename C, typename R>
-__device__ __forceinline__ void reg_u(C (&x)[NR], const R *m, uint32_t thr, const uint32_t (&ro)[NR],
-                                      uint32_t lmask, uint32_t lval)
+__device__ __forceinline__ void reg_u(C (&x)[NR], const R *m, uint32_t slotmask)
 {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
         if (s & (1 << K)) continue;
+        if (!((slotmask >> s) & 1u)) continue;
         const int s1 = s | (1 << K);
-        if (((thr | ro[s]) & lmask) == lval) {
-            const C a = x[s], b = x[s1];
-            x[s] = row2(m[0], m[1], m[2], m[3], a, b);
-            x[s1] = row2(m[4], m[5], m[6], m[7], a, b);
-        }
+        const C a = x[s], b = x[s1];
+        x[s] = row2(m[0], m[1], m[2], m[3], a, b);
+        x[s1] = row2(m[4], m[5], m[6], m[7], a, b);
+    }
+}
+
+template <int K, int NR, typename C, typename R>
+__device__ __forceinline__ void reg_ur(C (&x)[NR], const R *m, uint32_t slotmask)
+{
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+        if (s & (1 << K)) continue;
+        if (!((slotmask >> s) & 1u)) continue;
+        const int s1 = s | (1 << K);
+        const C a = x[s], b = x[s1];
+        C r0, r1;
+        r0.x = fma(m[0], a.x, m[1] * b.x);
+        r0.y = fma(m[0], a.y, m[1] * b.y);
+        r1.x = fma(m[2], a.x, m[3] * b.x);
+        r1.y = fma(m[2], a.y, m[3] * b.y);
+        x[s] = r0;
+        x[s1] = r1;
     }
 }
 
 template <int K, int NR, typename C>
-__device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t thr, const uint32_t (&ro)[NR], uint32_t lmask,
-                                      uint32_t lval)
+__device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
 {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
         if (s & (1 << K)) continue;
+        if (!((slotmask >> s) & 1u)) continue;
         const int s1 = s | (1 << K);
-        if (((thr | ro[s]) & lmask) == lval) {
-            const C a = x[s];
-            x[s] = x[s1];
-            x[s1] = a;
-        }
+        const C a = x[s];
+        x[s] = x[s1];
+        x[s1] = a;
     }
 }
+
+#define SV_SLOT_DISPATCH(FN, ...)                                   \
+    switch (op.slot) {                                              \
+    case 0: FN<0, NR>(__VA_ARGS__); break;                          \
+    case 1: FN<1, NR>(__VA_ARGS__); break;                          \
+    case 2: FN<2, NR>(__VA_ARGS__); break;                          \
+    case 3: FN<3, NR>(__VA_ARGS__); break;                          \
+    default:                                                        \
+        if constexpr (RB > 4) FN<(RB > 4 ? 4 : 0), NR>(__VA_ARGS__); \
+        break;                                                      \
+    }
 
 template <typename R, int RB>
 __global__ void __launch_bounds__(256)
@@ -131,43 +160,48 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 #pragma unroll
     for (int s = 0; s < NR; ++s) x[s] = psi[gbase | pass->goff[s]];
 
+    // current mapping: local index of slot s = thr | ro[s] (disjoint bits); the
+    // LDS swizzle is GF(2)-linear, so swz(thr | ro[s]) = swz(thr) ^ swz(ro[s])
     uint32_t thr = tid;
-    uint32_t ro[NR];
-#pragma unroll
-    for (int s = 0; s < NR; ++s) ro[s] = (uint32_t)s << nthr;
-
-    const uint32_t sb = pass->stage_begin, se = pass->stage_end;
-    for (uint32_t st = sb; st < se; ++st) {
+    const TileStage *S0 = stages + pass->stage_begin;
+    const uint32_t se = pass->stage_end;
+    for (uint32_t st = pass->stage_begin; st < se; ++st) {
         const TileStage &S = stages[st];
-        if (st != sb) {
-            // exchange: write under the old mapping (permuted), read under the new one
+        if (st != pass->stage_begin) {
+            const TileStage &P = stages[st - 1];
             __syncthreads();
+            if (S.perm_begin == S.perm_end) {
+                const uint32_t tw = lds_swizzle<LOWB>(thr);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) {
-                const uint32_t l = apply_perms(thr | ro[s], ops, S.perm_begin, S.perm_end, base);
-                lds[lds_swizzle<LOWB>(l)] = x[s];
+                for (int s = 0; s < NR; ++s) lds[tw ^ lds_swizzle<LOWB>(P.regoff[s])] = x[s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < NR; ++s) {
+                    const uint32_t l = apply_perms(thr | P.regoff[s], ops, S.perm_begin, S.perm_end, base);
+                    lds[lds_swizzle<LOWB>(l)] = x[s];
+                }
             }
             __syncthreads();
             uint32_t t2 = 0;
             for (uint32_t j = 0; j < nthr; ++j) t2 |= ((tid >> j) & 1u) << S.thrpos[j];
             thr = t2;
+            const uint32_t tr = lds_swizzle<LOWB>(thr);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) ro[s] = S.regoff[s];
-#pragma unroll
-            for (int s = 0; s < NR; ++s) x[s] = lds[lds_swizzle<LOWB>(thr | ro[s])];
+            for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ lds_swizzle<LOWB>(S.regoff[s])];
         }
         for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
             const TileOp op = ops[k];
+            const bool tc = (tid & op.tidmask) == op.tidval;
             if (op.kind == T_PROJ) {
                 const bool zg = (base & op.gmask) == op.gval;
                 const R c = prm[op.param], sn = prm[op.param + 1];
-                const uint32_t sglob = (op.a == 0xff) ? (uint32_t)((base >> op.b) & 1ull) : 0u;
+                const uint32_t sig_thread = op.a == 2 ? ((tid >> op.b) & 1u) : 0u;
+                const uint32_t sig_tile = op.a == 0 ? (uint32_t)((base >> op.b) & 1ull) : 0u;
 #pragma unroll
                 for (int s = 0; s < NR; ++s) {
-                    const uint32_t l = thr | ro[s];
-                    const uint32_t z = (zg && ((l & op.lmask) == op.lval)) ? 1u : 0u;
-                    const uint32_t sbit = (op.a == 0xff) ? sglob : ((l >> op.a) & 1u);
-                    const R si = (sbit ^ z) ? -sn : sn;
+                    const uint32_t z = (zg && tc && ((op.slotmask >> s) & 1u)) ? 1u : 0u;
+                    const uint32_t sig_slot = op.a == 1 ? (((uint32_t)s >> op.b) & 1u) : 0u;
+                    const R si = ((sig_thread ^ sig_tile ^ sig_slot) ^ z) ? -sn : sn;
                     const C a = x[s];
                     C r;
                     r.x = fma(a.x, c, -a.y * si);
@@ -177,56 +211,54 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
                 continue;
             }
             if ((base & op.gmask) != op.gval) continue;
+            if (!tc) continue;
             if (op.kind == T_U) {
                 R m[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) m[j] = prm[op.param + j];
-                switch (op.slot) {
-                case 0: reg_u<0, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
-                case 1: reg_u<1, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
-                case 2: reg_u<2, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
-                case 3: reg_u<3, NR, C, R>(x, m, thr, ro, op.lmask, op.lval); break;
-                default:
-                    if constexpr (RB > 4) reg_u<(RB > 4 ? 4 : 0), NR, C, R>(x, m, thr, ro, op.lmask, op.lval);
-                    break;
-                }
+                SV_SLOT_DISPATCH(reg_u, x, m, op.slotmask)
+            } else if (op.kind == T_UR) {
+                R m[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) m[j] = prm[op.param + j];
+                SV_SLOT_DISPATCH(reg_ur, x, m, op.slotmask)
             } else if (op.kind == T_X) {
-                switch (op.slot) {
-                case 0: reg_x<0, NR, C>(x, thr, ro, op.lmask, op.lval); break;
-                case 1: reg_x<1, NR, C>(x, thr, ro, op.lmask, op.lval); break;
-                case 2: reg_x<2, NR, C>(x, thr, ro, op.lmask, op.lval); break;
-                case 3: reg_x<3, NR, C>(x, thr, ro, op.lmask, op.lval); break;
-                default:
-                    if constexpr (RB > 4) reg_x<(RB > 4 ? 4 : 0), NR, C>(x, thr, ro, op.lmask, op.lval);
-                    break;
-                }
+                SV_SLOT_DISPATCH(reg_x, x, op.slotmask)
             } else if (op.kind == T_PHASE) {
                 const R c = prm[op.param], sn = prm[op.param + 1];
 #pragma unroll
                 for (int s = 0; s < NR; ++s) {
-                    if (((thr | ro[s]) & op.lmask) == op.lval) {
-                        const C a = x[s];
-                        C r;
-                        r.x = fma(a.x, c, -a.y * sn);
-                        r.y = fma(a.x, sn, a.y * c);
-                        x[s] = r;
-                    }
+                    if (!((op.slotmask >> s) & 1u)) continue;
+                    const C a = x[s];
+                    C r;
+                    r.x = fma(a.x, c, -a.y * sn);
+                    r.y = fma(a.x, sn, a.y * c);
+                    x[s] = r;
                 }
             }
         }
     }
 
     if (pass->final_exchange) {
+        const TileStage &L = stages[se - 1];
         __syncthreads();
+        if (pass->fperm_begin == pass->fperm_end) {
+            const uint32_t tw = lds_swizzle<LOWB>(thr);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) {
-            const uint32_t l = apply_perms(thr | ro[s], ops, pass->fperm_begin, pass->fperm_end, base);
-            lds[lds_swizzle<LOWB>(l)] = x[s];
+            for (int s = 0; s < NR; ++s) lds[tw ^ lds_swizzle<LOWB>(L.regoff[s])] = x[s];
+        } else {
+#pragma unroll
+            for (int s = 0; s < NR; ++s) {
+                const uint32_t l = apply_perms(thr | L.regoff[s], ops, pass->fperm_begin, pass->fperm_end, base);
+                lds[lds_swizzle<LOWB>(l)] = x[s];
+            }
         }
         __syncthreads();
+        const uint32_t tr = lds_swizzle<LOWB>(tid);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) x[s] = lds[lds_swizzle<LOWB>(((uint32_t)s << nthr) | tid)];
+        for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ lds_swizzle<LOWB>((uint32_t)s << nthr)];
     }
+    (void)S0;
 #pragma unroll
     for (int s = 0; s < NR; ++s) psi[gbase | pass->goff[s]] = x[s];
 }

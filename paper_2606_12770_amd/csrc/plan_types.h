@@ -29,28 +29,38 @@ namespace svi {
 // ---------------------------------------------------------------------------
 
 enum : uint8_t {
-    T_U = 0,      // 2x2 matrix on register slot bit `slot`
+    T_U = 0,      // complex 2x2 matrix on register slot bit `slot` (8 reals)
     T_X = 1,      // exchange on register slot bit `slot`
-    T_PHASE = 2,  // diagonal phase where the (local, tile) condition holds
-    T_PROJ = 3,   // projector phase; a = local signal bit or 0xff (then b = signal qubit)
+    T_PHASE = 2,  // diagonal phase (cos, sin) where the condition holds
+    T_PROJ = 3,   // projector phase (cos, sin); signal: a = 0 tile qubit b,
+                  // a = 1 register slot bit b, a = 2 thread bit b
     T_INC = 4,    // permutation: local register [a, a+b) += 1
     T_DEC = 5,    // permutation: local register [a, a+b) -= 1
     T_SWAP = 6,   // permutation: exchange local bits a and b
     T_XFLIP = 7,  // permutation: flip local bit a
+    T_UR = 8,     // real 2x2 matrix on register slot bit `slot` (4 reals)
 };
 
+// Conditions of register-level ops are pre-split for the stage they run in:
+//   slotmask bit s : the register-slot part of the condition holds for slot s
+//   (tid & tidmask) == tidval : the thread part holds
+//   (tile base & gmask) == gval : the tile part holds (uniform)
+// Permutations keep the condition on the whole local index (lmask, lval).
 struct TileOp {
     uint8_t kind;
     uint8_t slot;
     uint8_t a;
     uint8_t b;
     uint32_t param;   // offset (in reals) into the plan's parameter array
-    uint32_t lmask;   // condition on the local index
+    uint32_t slotmask;
+    uint16_t tidmask;
+    uint16_t tidval;
+    uint32_t lmask;
     uint32_t lval;
-    uint64_t gmask;   // condition on the absolute index bits of tile qubits
+    uint64_t gmask;
     uint64_t gval;
 };
-static_assert(sizeof(TileOp) == 32, "TileOp layout");
+static_assert(sizeof(TileOp) == 40, "TileOp layout");
 
 constexpr int kMaxRB = 5;
 constexpr int kMaxB = 14;

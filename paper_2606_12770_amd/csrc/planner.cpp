@@ -327,6 +327,26 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             return rs;
         };
 
+        // split a local condition (t.lmask, t.lval) for the current stage into the
+        // register-slot part (slotmask over all 2^rb slots) and the thread part
+        auto stage_split = [&](TileOp &t) {
+            const TileStage &S = p->stages.back();
+            uint32_t regbits = 0;
+            for (int k = 0; k < rb; ++k) regbits |= 1u << cur_rs[k];
+            const uint32_t rm = t.lmask & regbits;
+            t.slotmask = 0;
+            for (int s = 0; s < (1 << rb); ++s)
+                if ((S.regoff[s] & rm) == (t.lval & rm)) t.slotmask |= 1u << s;
+            t.tidmask = 0;
+            t.tidval = 0;
+            for (int j = 0; j < nthr; ++j) {
+                const uint32_t bit = 1u << S.thrpos[j];
+                if (t.lmask & bit) {
+                    t.tidmask |= (uint16_t)(1u << j);
+                    if (t.lval & bit) t.tidval |= (uint16_t)(1u << j);
+                }
+            }
+        };
         for (size_t i = 0; i < pb.ops.size(); ++i) {
             const OpInfo &o = info[pb.ops[i]];
             TileOp t{};
@@ -352,11 +372,17 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                     it = std::find(cur_rs.begin(), cur_rs.end(), l);
                 }
                 split(o.mask, o.val, t);
+                stage_split(t);
                 t.slot = (uint8_t)(it - cur_rs.begin());
                 if (o.kind == SV_OP_U) {
-                    t.kind = T_U;
+                    const bool real = o.m[1] == 0.0 && o.m[3] == 0.0 && o.m[5] == 0.0 && o.m[7] == 0.0;
+                    t.kind = real ? T_UR : T_U;
                     t.param = (uint32_t)p->tparams.size();
-                    for (int k = 0; k < 8; ++k) p->tparams.push_back(o.m[k]);
+                    if (real) {
+                        for (int k = 0; k < 8; k += 2) p->tparams.push_back(o.m[k]);
+                    } else {
+                        for (int k = 0; k < 8; ++k) p->tparams.push_back(o.m[k]);
+                    }
                 } else {
                     t.kind = T_X;
                 }
@@ -371,13 +397,24 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             } else {  // PROJPHASE
                 split(o.mask, o.val, t);
                 t.kind = T_PROJ;
-                if ((pb.S >> o.target) & 1ull) {
-                    t.a = (uint8_t)lpos[o.target];
-                } else {
-                    t.a = 0xff;
+                if (!((pb.S >> o.target) & 1ull)) {
+                    t.a = 0;
                     t.b = (uint8_t)o.target;
+                } else {
+                    const int l = lpos[o.target];
+                    auto it = std::find(cur_rs.begin(), cur_rs.end(), l);
+                    if (it != cur_rs.end()) {
+                        t.a = 1;
+                        t.b = (uint8_t)(it - cur_rs.begin());
+                    } else {
+                        const TileStage &S = p->stages.back();
+                        t.a = 2;
+                        for (int j = 0; j < nthr; ++j)
+                            if (S.thrpos[j] == l) t.b = (uint8_t)j;
+                    }
                 }
             }
+            stage_split(t);
             t.param = (uint32_t)p->tparams.size();
             p->tparams.push_back(std::cos(o.m[0]));
             p->tparams.push_back(std::sin(o.m[0]));

@@ -162,44 +162,58 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
             for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
                 const TileOp &op = p.tops[k];
                 const double *prm = p.tparams.data() + op.param;
+                // the slot/thread split of the condition must agree with the local condition
+                for (int t = 0; t < T; ++t)
+                    for (int s = 0; s < NR; ++s) {
+                        const uint32_t l = thr[t] | ro[s];
+                        const bool split_ok = ((op.slotmask >> s) & 1u) && ((t & op.tidmask) == op.tidval);
+                        if (split_ok != ((l & op.lmask) == op.lval)) return 10;
+                    }
                 if (op.kind == T_PROJ) {
                     const bool zg = (base & op.gmask) == op.gval;
-                    const uint32_t sglob = op.a == 0xff ? (uint32_t)((base >> op.b) & 1ull) : 0u;
-                    for (int t = 0; t < T; ++t)
+                    for (int t = 0; t < T; ++t) {
+                        const bool tc = (t & op.tidmask) == op.tidval;
                         for (int s = 0; s < NR; ++s) {
-                            const uint32_t l = thr[t] | ro[s];
-                            const uint32_t z = (zg && ((l & op.lmask) == op.lval)) ? 1u : 0u;
-                            const uint32_t sb = op.a == 0xff ? sglob : ((l >> op.a) & 1u);
+                            const uint32_t z = (zg && tc && ((op.slotmask >> s) & 1u)) ? 1u : 0u;
+                            uint32_t sb = 0;
+                            if (op.a == 0) sb = (uint32_t)((base >> op.b) & 1ull);
+                            else if (op.a == 1) sb = ((uint32_t)s >> op.b) & 1u;
+                            else if (op.a == 2) sb = ((uint32_t)t >> op.b) & 1u;
+                            else return 11;
                             x[(size_t)t * NR + s] *= cd(prm[0], (sb ^ z) ? -prm[1] : prm[1]);
                         }
+                    }
                     continue;
                 }
                 if ((base & op.gmask) != op.gval) continue;
-                if (op.kind == T_PHASE) {
-                    for (int t = 0; t < T; ++t)
+                for (int t = 0; t < T; ++t) {
+                    if ((t & op.tidmask) != op.tidval) continue;
+                    if (op.kind == T_PHASE) {
                         for (int s = 0; s < NR; ++s)
-                            if (((thr[t] | ro[s]) & op.lmask) == op.lval) x[(size_t)t * NR + s] *= cd(prm[0], prm[1]);
-                    continue;
-                }
-                if (op.slot >= rb) return 6;
-                const int K = op.slot;
-                for (int t = 0; t < T; ++t)
+                            if ((op.slotmask >> s) & 1u) x[(size_t)t * NR + s] *= cd(prm[0], prm[1]);
+                        continue;
+                    }
+                    if (op.slot >= rb) return 6;
+                    const int K = op.slot;
                     for (int s = 0; s < NR; ++s) {
                         if (s & (1 << K)) continue;
-                        if (((thr[t] | ro[s]) & op.lmask) != op.lval) continue;
+                        if (!((op.slotmask >> s) & 1u)) continue;
                         cd &a = x[(size_t)t * NR + s];
                         cd &bb = x[(size_t)t * NR + (s | (1 << K))];
+                        const cd a0 = a, b0 = bb;
                         if (op.kind == T_U) {
-                            const cd m0(prm[0], prm[1]), m1(prm[2], prm[3]), m2(prm[4], prm[5]), m3(prm[6], prm[7]);
-                            const cd a0 = a, b0 = bb;
-                            a = m0 * a0 + m1 * b0;
-                            bb = m2 * a0 + m3 * b0;
+                            a = cd(prm[0], prm[1]) * a0 + cd(prm[2], prm[3]) * b0;
+                            bb = cd(prm[4], prm[5]) * a0 + cd(prm[6], prm[7]) * b0;
+                        } else if (op.kind == T_UR) {
+                            a = prm[0] * a0 + prm[1] * b0;
+                            bb = prm[2] * a0 + prm[3] * b0;
                         } else if (op.kind == T_X) {
                             std::swap(a, bb);
                         } else {
                             return 7;
                         }
                     }
+                }
             }
         }
         // the last stage must leave the load mapping unless a final exchange follows
