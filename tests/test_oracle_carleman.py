@@ -1,0 +1,149 @@
+"""Pins of the classical Carleman / Taylor oracle against facts fixed by the
+paper and by the mathematics, not by the oracle itself.
+
+* lattice mass conservation: every column of A11 and A12 sums to zero
+  (sum w = 1, sum w e = 0, sum w e^2 = 1/3), periodic and bounce-back;
+* periodic momentum conservation;
+* the uniform rest equilibrium is a fixed point (A y0 = 0), so the Taylor
+  solution is known in closed form;
+* periodic A11 is block circulant: its spectrum is the union of the 3x3
+  Fourier symbols diag(exp(-2 pi i kappa e_q'/Nx)) C - I;
+* the spectral radius of the bounce-back rate matrix at nu = 2 against the
+  table of App. D (three significant figures), including mu(A22) = 2 mu(A11);
+* the Taylor recurrence equals forward substitution on L and the truncated
+  series sum_k (dt A)^k / k! applied N_t times;
+* the N_C = 2 truncation reproduces the nonlinear collide-then-stream ODE up to
+  O(A^3) in the perturbation amplitude A (reading of the A12 scale: Eq.
+  A12-kernel as printed); a doubled kernel or a sign slip would leave O(A^2);
+* the effective condition number kappa = lambda_L / sigma_min(L) of the
+  N_C = 1 QSVT run of Sec. III.E.1 (printed as about 800 with lambda_L = 8).
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+
+from oracle import carleman as oc
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "bounceback"])
+@pytest.mark.parametrize("nx,tau", [(4, 0.7), (8, 1.0), (16, 0.094)])
+def test_mass_conservation(nx, tau, boundary):
+    A11 = oc.a11(nx, tau, boundary).toarray()
+    A12 = oc.a12(nx, tau, boundary).toarray()
+    assert np.max(np.abs(A11.sum(0))) < 1e-13
+    assert np.max(np.abs(A12.sum(0))) < 1e-13
+
+
+@pytest.mark.parametrize("nx,tau", [(4, 0.7), (8, 1.3)])
+def test_periodic_momentum_conservation(nx, tau):
+    e = np.tile(oc.E, nx)
+    assert np.max(np.abs(e @ oc.a11(nx, tau).toarray())) < 1e-13
+    assert np.max(np.abs(e @ oc.a12(nx, tau).toarray())) < 1e-13
+
+
+def test_rest_equilibrium_is_fixed_point_and_taylor_closed_form():
+    nx, tau = 8, 0.9
+    A = oc.carleman_matrix(nx, tau, 2)
+    f0 = oc.initial_f1(nx, 0.0)
+    y0 = oc.carleman_vector(f0)
+    assert np.max(np.abs(A @ y0)) < 1e-14
+    nt, nk, n_m, n_k = 2, 2, 2, 2
+    L = oc.l_matrix(A, 0.1, nt, nk, n_m, n_k)
+    x = oc.forward_substitution(L, oc.l_rhs(y0, nt, nk, n_m, n_k), len(y0))
+    D = len(y0)
+    for m in range(4):
+        for k in range(4):
+            blk = x[(m * 4 + k) * D:(m * 4 + k + 1) * D]
+            want = y0 if (k == 0 or m >= nt) else np.zeros(D)
+            assert np.max(np.abs(blk - want)) < 1e-15
+
+
+@pytest.mark.parametrize("nx,tau", [(8, 0.8), (16, 1.2)])
+def test_periodic_spectrum_fourier(nx, tau):
+    ev = np.linalg.eigvals(oc.a11(nx, tau).toarray())
+    C = oc.collision_matrix(tau)
+    sym = []
+    for kap in range(nx):
+        Dk = np.diag(np.exp(-2j * np.pi * kap * oc.E / nx))
+        sym.extend(np.linalg.eigvals(Dk @ C - np.eye(3)))
+    sym = np.array(sym)
+    # every eigenvalue has a partner in the other set
+    d1 = np.min(np.abs(ev[:, None] - sym[None, :]), axis=1)
+    d2 = np.min(np.abs(sym[:, None] - ev[None, :]), axis=1)
+    assert max(d1.max(), d2.max()) < 1e-10
+
+
+# Table spectral-radius (App. D), nu = 2
+SPECTRAL_TABLE = [(4, 21.3, 42.7), (8, 10.7, 21.3), (16, 5.3, 10.7), (32, 2.7, 5.3), (64, 2.0, 4.0)]
+
+
+@pytest.mark.parametrize("nx,mu1,mu2", SPECTRAL_TABLE)
+def test_spectral_radius_table(nx, mu1, mu2):
+    tau = oc.tau_from_nu(nx, 2.0)
+    A11 = oc.a11(nx, tau, "bounceback").toarray()
+    m1 = np.max(np.abs(np.linalg.eigvals(A11)))
+    assert round(m1, 1) == pytest.approx(mu1, abs=0.051)
+    if nx <= 8:  # full second-order matrix, dense
+        A = oc.carleman_matrix(nx, tau, 2, "bounceback").toarray()
+        m2 = np.max(np.abs(np.linalg.eigvals(A)))
+    else:  # block-triangular: spectrum of A22 = pairwise sums of A11 eigenvalues
+        ev = np.linalg.eigvals(A11)
+        m2 = np.max(np.abs(ev[:, None] + ev[None, :]))
+    assert round(m2, 1) == pytest.approx(mu2, abs=0.051)
+
+
+def test_taylor_recurrence_equals_forward_substitution_and_series():
+    nx, tau, dt, nt, nk = 4, 0.8, 0.1, 3, 3
+    A = oc.carleman_matrix(nx, tau, 2)
+    y0 = oc.carleman_vector(oc.initial_f1(nx, 0.07, 0.01))
+    n_m, n_k = 2, 2
+    L = oc.l_matrix(A, dt, nt, nk, n_m, n_k)
+    b = oc.l_rhs(y0, nt, nk, n_m, n_k)
+    x_fs = oc.forward_substitution(L, b, len(y0))
+    x_rec = oc.taylor_solution_blocks(A, y0, dt, nt, nk, n_m, n_k)
+    assert np.max(np.abs(x_fs - x_rec)) < 1e-14
+    assert np.max(np.abs(L @ x_rec - b)) < 1e-13
+    # truncated series, from dense matrix powers
+    Ad = A.toarray()
+    T = sum(np.linalg.matrix_power(dt * Ad, k) / scipy.special.factorial(k) for k in range(nk + 1))
+    y = y0.copy()
+    for _ in range(nt):
+        y = T @ y
+    D = len(y0)
+    last = x_rec[-D:]
+    assert np.max(np.abs(last - y)) < 1e-13
+
+
+def test_second_order_truncation_error_is_cubic_in_amplitude():
+    nx, tau, T = 8, 1.0, 1.0
+    errs1, errs2 = [], []
+    amps = [0.01, 0.02, 0.04]
+    A1 = oc.carleman_matrix(nx, tau, 1)
+    A2 = oc.carleman_matrix(nx, tau, 2)
+    D = 3 * nx
+    for a in amps:
+        f0 = oc.initial_f1(nx, a)
+        ref = oc.rk4(f0, lambda f: oc.nonlinear_rhs(f, nx, tau), T, 0.002)
+        c1 = oc.expm_apply(A1, f0, T)
+        c2 = oc.expm_apply(A2, oc.carleman_vector(f0), T)[:D]
+        errs1.append(np.max(np.abs(oc.density(c1, nx) - oc.density(ref, nx))))
+        errs2.append(np.max(np.abs(oc.density(c2, nx) - oc.density(ref, nx))))
+    s1 = np.polyfit(np.log(amps), np.log(errs1), 1)[0]
+    s2 = np.polyfit(np.log(amps), np.log(errs2), 1)[0]
+    assert 1.8 < s1 < 2.2, (s1, errs1)
+    assert s2 > 2.7, (s2, errs2)
+    assert all(e2 < e1 for e1, e2 in zip(errs1, errs2))
+
+
+@pytest.mark.slow
+def test_kappa_first_order_qsvt_run():
+    """Sec. III.E.1: N_C = 1, Nx = 32, N_t = 32, N_K = 1, dt = 0.1, nu = 2,
+    bounce-back, lambda_L = 8: kappa about 800."""
+    nx, nt, nk, dt = 32, 32, 1, 0.1
+    tau = oc.tau_from_nu(nx, 2.0)
+    A = oc.a11(nx, tau, "bounceback")
+    n_m, n_k = 6, 1
+    L = oc.l_matrix(A, dt, nt, nk, n_m, n_k)
+    kappa = 8.0 / oc.sigma_min(L)
+    assert 700 < kappa < 900, kappa
