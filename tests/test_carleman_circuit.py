@@ -1,0 +1,188 @@
+"""The Carleman-LBM circuit checked on the FP64 reference simulator against the
+classical matrices of the oracle (block-encoding extraction, the method of
+App. B), the QSVT definition and the classical Taylor solution.
+
+Register order (documented by the generator, restated here independently):
+    q1 (2) alpha1 (n_a) q2 (2) alpha2 (n_a) ord (1) [k (n_k) m (n_m)] t label [s]
+so the system register is the lowest n_sys qubits and the ancillas sit above.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import carleman as oc
+from oracle import qsvt as oq
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+
+
+def x_reg_index(nx, ordv, a1, q1, a2=0, q2=0):
+    na = nx.bit_length() - 1
+    return q1 | (a1 << 2) | (q2 << (2 + na)) | (a2 << (4 + na)) | (ordv << (4 + 2 * na))
+
+
+def carleman_to_reg(nx):
+    """Register index of every entry of the oracle's Carleman vector
+    (f1 index 3 alpha + q, then f2 index (3 a1 + q1) D + 3 a2 + q2)."""
+    D = 3 * nx
+    out = np.zeros(D + D * D, dtype=np.int64)
+    for a in range(nx):
+        for q in range(3):
+            out[3 * a + q] = x_reg_index(nx, 0, a, q)
+    for i in range(D):
+        for j in range(D):
+            out[D + i * D + j] = x_reg_index(nx, 1, i // 3, i % 3, j // 3, j % 3)
+    return out
+
+
+def system_to_reg(nx, nt, nk, n_k, n_m):
+    """Register index (x | k << n_x | m << (n_x + n_k)) of every entry of the
+    oracle's L-system vector (block row m * 2^n_k + k, Carleman vector inside)."""
+    cr = carleman_to_reg(nx)
+    n_x = 2 * (nx.bit_length() - 1) + 5
+    blocks = []
+    for m in range(1 << n_m):
+        for k in range(1 << n_k):
+            blocks.append(cr | (k << n_x) | (m << (n_x + n_k)))
+    return np.concatenate(blocks)
+
+
+def apply_block(circ, lam, vec_reg, n_low):
+    """lambda <0_anc| U |vec, 0_anc> with the system on the lowest n_low qubits."""
+    psi = np.zeros(1 << circ.n, dtype=np.complex128)
+    psi[: 1 << n_low] = vec_reg
+    out = osv.run(circ, psi)
+    return lam * out[: 1 << n_low]
+
+
+@pytest.mark.parametrize("nx,tau", [(2, 0.8), (4, 1.0), (4, 0.6), (8, 1.3)])
+def test_ua_encodes_carleman_matrix(nx, tau):
+    circ, lam, L = cc.build_ua(nx, tau)
+    A = oc.carleman_matrix(nx, tau, 2).toarray()
+    idx = carleman_to_reg(nx)
+    n_x = L.n_x
+    rng = np.random.default_rng(nx)
+    phys = np.zeros(1 << n_x, bool)
+    phys[idx] = True
+    for trial in range(2):
+        y = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+        v = np.zeros(1 << n_x, dtype=np.complex128)
+        v[idx] = y
+        got = apply_block(circ, lam, v, n_x)
+        # physical rows carry A y, unphysical rows nothing
+        assert np.max(np.abs(got[idx] - A @ y)) < 1e-13
+        assert np.max(np.abs(got[~phys])) < 1e-13
+        # an input outside the physical subspace never reaches it
+        u = rng.standard_normal(1 << n_x) + 0j
+        u[idx] = 0
+        got_u = apply_block(circ, lam, u, n_x)
+        assert np.max(np.abs(got_u[idx])) < 1e-13
+
+
+@pytest.mark.parametrize("nx,tau,nk,nt", [(2, 1.0, 1, 1), (2, 0.7, 2, 2), (4, 0.9, 3, 1), (4, 1.2, 1, 2)])
+def test_ul_encodes_taylor_matrix(nx, tau, nk, nt):
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1)
+    enc = cc.build_ul(cfg, with_signal=False)
+    L = enc.layout
+    A = oc.carleman_matrix(nx, tau, 2)
+    Lm = oc.l_matrix(A, cfg.dt, nt, nk, L.n_m, L.n_k).toarray()
+    idx = system_to_reg(nx, nt, nk, L.n_k, L.n_m)
+    n_sys = L.n_sys
+    phys = np.zeros(1 << n_sys, bool)
+    phys[idx] = True
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+    v = np.zeros(1 << n_sys, dtype=np.complex128)
+    v[idx] = y
+    got = apply_block(enc.circuit, enc.lam, v, n_sys)
+    assert np.max(np.abs(got[idx] - Lm @ y)) < 1e-12
+    assert np.max(np.abs(got[~phys])) < 1e-12
+    u = rng.standard_normal(1 << n_sys) + 0j
+    u[idx] = 0
+    assert np.max(np.abs(apply_block(enc.circuit, enc.lam, u, n_sys)[idx])) < 1e-12
+
+
+def test_ul_dagger_inverts():
+    cfg = cc.CarlemanConfig(nx=2, tau=0.9, nk=2, nt=2)
+    enc = cc.build_ul(cfg, with_signal=False)
+    c = enc.circuit
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(1 << c.n) + 1j * rng.standard_normal(1 << c.n)
+    out = osv.run(c.dagger(), osv.run(c, psi))
+    assert np.max(np.abs(out - psi)) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["ua", "ul"])
+def test_lowering_to_elementary_gates_is_exact(which):
+    if which == "ua":
+        circ = cc.build_ua(2, 0.8)[0]
+    else:
+        circ = cc.build_ul(cc.CarlemanConfig(nx=2, tau=1.1, nk=2, nt=1)).circuit
+    low = cc.lower_to_elementary(circ)
+    kinds = {k for k in low.counts()}
+    assert kinds <= {"U", "X", "RY", "PHASE"}
+    for rec, _prm in low.iter_ops():  # R_Y only uncontrolled after lowering
+        if rec[0] == 3:
+            assert rec[4] == 0
+    rng = np.random.default_rng(11)
+    psi = rng.standard_normal(1 << circ.n) + 1j * rng.standard_normal(1 << circ.n)
+    assert np.max(np.abs(osv.run(low, psi) - osv.run(circ, psi))) < 1e-12
+
+
+def test_lt_conditions_cover_exactly():
+    reg = [0, 1, 2, 3]
+    for bound in range(0, 18):
+        conds = cc.lt(reg, bound)
+        for v in range(16):
+            hits = sum(all(((v >> q) & 1) == b for q, b in c.items()) for c in conds)
+            assert hits == (1 if v < bound else 0)
+
+
+@pytest.mark.parametrize("d", [1, 3, 5])
+def test_qsvt_ladder_is_singular_value_transform(d):
+    """Tiny instance: the signal = 0, ancilla = 0 block of the simulated ladder
+    applied to b equals (-i)^d Re p^{SV}(L^dagger / lambda_L) b with p from the QSP
+    definition, for arbitrary phases."""
+    cfg = cc.CarlemanConfig(nx=2, tau=0.9, nk=1, nt=1, dt=0.1, amp=0.1)
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    rng = np.random.default_rng(d)
+    phases = rng.uniform(-np.pi, np.pi, d + 1)
+    circ = cc.build_qsvt(enc, phases)
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k).toarray()
+    idx = system_to_reg(cfg.nx, cfg.nt, cfg.nk, L.n_k, L.n_m)
+    y0 = oc.carleman_vector(oc.initial_f1(cfg.nx, cfg.amp))
+    b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    b = b / np.linalg.norm(b)
+    want = (-1j) ** d * oq.sv_transform(Lm.conj().T / enc.lam,
+                                       lambda s: oq.qsp_poly(phases, s).real) @ b
+    psi = np.zeros(1 << circ.n, dtype=np.complex128)
+    psi[idx] = b
+    out = osv.run(circ, psi)
+    got = out[idx]  # ancillas and signal 0 are the high bits: idx already has them 0
+    assert np.max(np.abs(got - want)) < 1e-12
+    # nothing else of the system reaches the ancilla-zero block
+    n_sys = L.n_sys
+    mask = np.ones(1 << n_sys, bool)
+    mask[idx] = False
+    assert np.max(np.abs(out[: 1 << n_sys][mask])) < 1e-12
+
+
+def test_rhs_block_is_normalised_carleman_vector():
+    cfg = cc.CarlemanConfig(nx=4, tau=1.0, amp=0.07, u0=0.01)
+    L = cc.layout_for(cfg)
+    blk = cc.rhs_x_block(cfg, L)
+    y0 = oc.carleman_vector(oc.initial_f1(cfg.nx, cfg.amp, cfg.u0))
+    idx = carleman_to_reg(cfg.nx)
+    assert np.max(np.abs(blk[idx] - y0 / np.linalg.norm(y0))) < 1e-15
+    mask = np.ones(len(blk), bool)
+    mask[idx] = False
+    assert np.all(blk[mask] == 0)
+
+
+def test_qubit_counts_of_workloads():
+    assert cc.qubit_count(cc.CarlemanConfig(nx=8, nk=2, nt=2)) == 22
+    assert cc.qubit_count(cc.CarlemanConfig(nx=64, tau=0.8, nk=4, nt=8)) == 31
+    assert cc.qubit_count(cc.CarlemanConfig(nx=256, tau=0.8, nk=4, nt=4)) == 34
