@@ -46,7 +46,7 @@ def chebyshev_eval(coefs_odd, xs) -> np.ndarray:
 
 def sv_transform(M: np.ndarray, f) -> np.ndarray:
     """f^{SV}(M) = sum_i f(s_i) |w_i><v_i| for an odd function f (vectorised)."""
-    Wm, s, Vh = np.linalg.svd(M)
+    Wm, s, Vh = np.linalg.svd(M, full_matrices=False)
     return (Wm * f(s)[None, :]) @ Vh
 
 
@@ -62,3 +62,45 @@ def project_block(U: np.ndarray, n: int, anc_qubits, sys_qubits) -> np.ndarray:
         idx.append(i)
     idx = np.array(idx)
     return U[np.ix_(idx, idx)]
+
+
+def qsp_poly_batch(phases, xs) -> np.ndarray:
+    """p(x) for an array of x: the same 2x2 products as qsp_unitary, carried
+    for all x at once (the first row of the running product)."""
+    xs = np.asarray(xs, float)
+    s = np.sqrt(np.clip(1.0 - xs * xs, 0.0, None))
+    row0 = np.full(xs.shape, np.exp(1j * phases[0]), dtype=np.complex128)
+    row1 = np.zeros(xs.shape, dtype=np.complex128)
+    for p in phases[1:]:
+        # [row0, row1] @ [[x, i s], [i s, x]] @ diag(e^{ip}, e^{-ip})
+        n0 = (row0 * xs + row1 * 1j * s) * np.exp(1j * p)
+        n1 = (row0 * 1j * s + row1 * xs) * np.exp(-1j * p)
+        row0, row1 = n0, n1
+    return row0
+
+
+def odd_chebyshev_of_qsp(phases) -> np.ndarray:
+    """Coefficients of T_1, T_3, ..., T_d of Re p for odd d = len(phases) - 1,
+    by interpolation at d + 1 Gauss-Chebyshev nodes."""
+    d = len(phases) - 1
+    N = d + 1
+    x = np.cos(np.pi * (2 * np.arange(N) + 1) / (2 * N))
+    g = qsp_poly_batch(phases, x).real
+    js = np.arange(1, d + 1, 2)
+    return (2.0 / N) * (np.cos(np.outer(js, np.arccos(x))) @ g)
+
+
+def odd_sv_apply(matvec, rmatvec, coefs, b) -> np.ndarray:
+    """f^{SV}(M) b for f = sum_j coefs_j T_{2j+1}, using only products with M
+    (matvec) and M^dagger (rmatvec).  For odd n, T_n(s) = s q_n(s^2) with
+    q_1 = 1, q_{-1} = 1 and q_{n+2} = (4 s^2 - 2) q_n - q_{n-2}; hence
+    f^{SV}(M) b = M sum_j coefs_j q_{2j+1}(M^dagger M) b."""
+    def G(v):
+        return 4.0 * rmatvec(matvec(v)) - 2.0 * v
+    r_prev = np.array(b, dtype=np.complex128)   # q_{-1}
+    r = np.array(b, dtype=np.complex128)        # q_1
+    acc = coefs[0] * r
+    for c in coefs[1:]:
+        r_prev, r = r, G(r) - r_prev
+        acc = acc + c * r
+    return matvec(acc)

@@ -1,0 +1,135 @@
+"""QSP phases for the matrix-inversion polynomial of the QSVT solver (host setup,
+untimed).
+
+Target (Sec. II.D.5): an odd polynomial f of degree d with f(x) ~ c / x on
+[1/kappa, 1] and |f| <= 1/2 on [-1, 1].  It is the degree-d Chebyshev
+truncation of c (1 - exp(-(beta x)^2)) / x, an odd, entire function equal to
+c / x up to the relative factor exp(-(beta x)^2); beta is scanned so that the
+regularisation error at x = 1/kappa and the truncation error balance, and c
+puts the maximum of |f| at 1/2.
+
+Phases (W_x convention, d + 1 of them, symmetric phi_j = phi_{d-j}):
+    p(x) = <0| e^{i phi_0 Z} W(x) e^{i phi_1 Z} ... W(x) e^{i phi_d Z} |0>,
+    W(x) = exp(i arccos(x) X),  Re p = f.
+They are found by the fixed-point iteration of Dong, Lin, Ni and Wang
+("Infinite quantum signal processing", 2022) on the reduced phases
+psi = phi - (pi/4)(e_0 + e_d): psi <- psi + (F(psi) - c) / 2, where F maps
+reduced phases to the odd Chebyshev coefficients of Re p (in this
+convention the Jacobian of F at psi = 0 is -2 I).  The paper cites
+the optimisation method of Dong et al. (2021) for the same phases; any phases
+that realise f give the same circuit output, and the residual is checked.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _cheb_nodes(N: int) -> np.ndarray:
+    return np.cos(np.pi * (2 * np.arange(N) + 1) / (2 * N))
+
+
+def odd_chebyshev_coefficients(fun, d: int, N: int | None = None) -> np.ndarray:
+    """Coefficients c_j of T_{2j+1}, j = 0..(d-1)/2, of the Chebyshev
+    interpolant of fun at N Gauss-Chebyshev nodes (N >= d + 1)."""
+    if d % 2 == 0:
+        raise ValueError("degree must be odd")
+    N = N or 1 << max(4, math.ceil(math.log2(4 * (d + 1))))
+    x = _cheb_nodes(N)
+    th = np.arccos(x)
+    g = fun(x)
+    js = np.arange(1, d + 1, 2)
+    return (2.0 / N) * (np.cos(np.outer(js, th)) @ g)
+
+
+def chebyshev_odd_eval(coefs: np.ndarray, x) -> np.ndarray:
+    th = np.arccos(np.clip(np.asarray(x, float), -1.0, 1.0))
+    js = np.arange(1, 2 * len(coefs), 2)
+    return np.cos(np.multiply.outer(th, js)) @ coefs
+
+
+def inverse_polynomial(kappa: float, d: int, peak: float = 0.5, n_beta: int = 24):
+    """Odd Chebyshev coefficients of the degree-d approximation of c / x on
+    [1/kappa, 1].  Returns (coefs, c, max relative error on [1/kappa, 1])."""
+    if d % 2 == 0:
+        raise ValueError("degree must be odd")
+    xs = np.linspace(1.0 / kappa, 1.0, 4000)
+    best = None
+    for beta in kappa * np.linspace(1.0, 6.0, n_beta):
+        def f(x, beta=beta):
+            x = np.asarray(x, float)
+            out = np.empty_like(x)
+            small = np.abs(beta * x) < 1e-8
+            out[small] = beta * beta * x[small]
+            xb = x[~small]
+            out[~small] = -np.expm1(-(beta * xb) ** 2) / xb
+            return out
+        co = odd_chebyshev_coefficients(f, d)
+        dense = np.linspace(0.0, 1.0, 20001)
+        mx = np.max(np.abs(chebyshev_odd_eval(co, dense)))
+        scale = peak / mx
+        co = co * scale
+        err = np.max(np.abs(chebyshev_odd_eval(co, xs) * xs / scale - 1.0))
+        if best is None or err < best[2]:
+            best = (co, scale, err)
+    return best
+
+
+def qsp_real_part(phases: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Re <0|U(x)|0> for all x at once (row vector recursion)."""
+    x = np.asarray(x, float)
+    s = np.sqrt(np.clip(1.0 - x * x, 0.0, None))
+    e0 = np.exp(1j * phases[0])
+    r0 = np.full(x.shape, e0, dtype=np.complex128)
+    r1 = np.zeros(x.shape, dtype=np.complex128)
+    for p in phases[1:]:
+        a = x * r0 + 1j * s * r1
+        b = 1j * s * r0 + x * r1
+        ep = np.exp(1j * p)
+        r0 = a * ep
+        r1 = b * np.conj(ep)
+    return r0.real
+
+
+def full_phases(reduced: np.ndarray) -> np.ndarray:
+    """Symmetric d + 1 phases (d odd) from the reduced ones, with the pi/4 ends."""
+    phi = np.concatenate([reduced[::-1], reduced])
+    phi[0] += np.pi / 4
+    phi[-1] += np.pi / 4
+    return phi
+
+
+def solve_phases(coefs: np.ndarray, tol: float = 1e-13, max_iter: int = 500):
+    """Fixed-point iteration for the phases of Re p = sum_j coefs_j T_{2j+1}.
+    Returns (phases, iterations, final coefficient residual)."""
+    dt = len(coefs)
+    d = 2 * dt - 1
+    N = 2 * dt
+    x = _cheb_nodes(N)
+    th = np.arccos(x)
+    T = np.cos(np.outer(np.arange(1, d + 1, 2), th)) * (2.0 / N)
+    psi = np.zeros(dt)
+    res = np.inf
+    for it in range(1, max_iter + 1):
+        F = T @ qsp_real_part(full_phases(psi), x)
+        r = F - coefs
+        res = float(np.max(np.abs(r)))
+        if res < tol:
+            return full_phases(psi), it, res
+        psi = psi + 0.5 * r
+    raise RuntimeError(f"phase iteration did not converge (residual {res:.3e})")
+
+
+def inversion_phases(kappa: float, d: int):
+    """Phases of the degree-d inversion polynomial.  Returns (phases, c, info):
+    Re p(x) ~ c / x on [1/kappa, 1]."""
+    coefs, c, err = inverse_polynomial(kappa, d)
+    phases, it, res = solve_phases(coefs)
+    return phases, c, {"approx_rel_err": err, "iterations": it, "residual": res, "coefs": coefs}
+
+
+def qsvt_degree(kappa: float) -> int:
+    """The paper's working degree: d = 10 kappa + 1 (Sec. III.E), made odd."""
+    d = int(math.ceil(10.0 * kappa)) + 1
+    return d if d % 2 else d + 1

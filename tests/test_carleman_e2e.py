@@ -1,0 +1,84 @@
+"""End to end on the CPU: the QSVT circuit at the paper's working degree
+d = 10 kappa + 1, simulated by the FP64 reference simulator, against
+
+* the classical singular-value transform of the same phases applied to b
+  (recurrence with sparse L products; exact up to rounding);
+* the classical Taylor solution x = L^{-1} b in the final-time rows (the
+  polynomial approximates 1/x to a few 1e-3 relative, so the fidelity bar is
+  1 - F <= 1e-5);
+* lattice mass conservation: in the final-time rows sum f^(1) / sum f^(2) =
+  1 / M0 with M0 the initial mass (column sums of A11, A12, A22 vanish, so the
+  Taylor propagator keeps sum f^(1) = M0 and sum f^(2) = M0^2).
+"""
+import numpy as np
+import pytest
+
+from oracle import carleman as oc
+from oracle import qsvt as oq
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+from paper_2606_12770_amd.circuits import qsp
+from tests.test_carleman_circuit import carleman_to_reg, system_to_reg
+
+
+def classical_setup(cfg, L):
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    f0 = oc.initial_f1(cfg.nx, cfg.amp, cfg.u0, cfg.wavenumber)
+    y0 = oc.carleman_vector(f0)
+    b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    b = b / np.linalg.norm(b)
+    x = oc.forward_substitution(Lm, b, len(y0))
+    return Lm, b, x, f0
+
+
+@pytest.mark.parametrize("nx,nk,nt,tau", [(2, 1, 1, 0.9), pytest.param(4, 1, 1, 1.0, marks=pytest.mark.slow)])
+def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau):
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, amp=0.1)
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    Lm, b, x, f0 = classical_setup(cfg, L)
+    kappa = enc.lam / oc.sigma_min(Lm)
+    d = qsp.qsvt_degree(kappa)
+    phases, c, info = qsp.inversion_phases(kappa, d)
+    circ = cc.build_qsvt(enc, phases)
+
+    psi = np.zeros(1 << circ.n, dtype=np.complex128)
+    psi[: 1 << L.n_x] = cc.rhs_x_block(cfg, L)
+    out = osv.run(circ, psi)
+
+    idx = system_to_reg(cfg.nx, cfg.nt, cfg.nk, L.n_k, L.n_m)
+    M = (Lm.T / enc.lam).tocsr()      # L^dagger / lambda_L (real L)
+    MT = M.T.tocsr()
+    co = oq.odd_chebyshev_of_qsp(phases)
+    want = (-1j) ** d * oq.odd_sv_apply(lambda v: M @ v, lambda v: MT @ v, co, b)
+    got = out[idx]
+    assert np.max(np.abs(got - want)) < 1e-11
+
+    # post-selection: ancillas and signal 0, idle rows m >= N_t
+    mask, val = cc.postselect_condition(L)
+    P = osv.postselect(out, circ.n, mask, val)
+    assert P > 1e-4
+    D = len(oc.carleman_vector(f0))
+    R = (1 << L.n_m) * (1 << L.n_k)
+    fin = slice(R // 2 * D, R * D)
+    xf = x[fin]
+    gf = out[idx][fin]
+    F = abs(np.vdot(xf, gf)) ** 2 / (np.vdot(xf, xf).real * np.vdot(gf, gf).real)
+    assert 1.0 - F < 1e-5, (1.0 - F, d, kappa)
+
+    # mass ratio in every idle row
+    M0 = f0.sum()
+    Dl = 3 * cfg.nx
+    ratio_err = []
+    for r in range(R // 2):
+        blk = gf[r * D:(r + 1) * D]
+        s1 = blk[:Dl].sum()
+        s2 = blk[Dl:].sum()
+        ratio_err.append(abs(s1 / s2 * M0 - 1.0))
+    assert max(ratio_err) < 1e-3
+    # the unphysical part of the system register stays empty
+    n_sys = L.n_sys
+    rest = np.ones(1 << n_sys, bool)
+    rest[idx] = False
+    assert np.max(np.abs(out[: 1 << n_sys][rest])) < 1e-12
