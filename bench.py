@@ -52,6 +52,52 @@ def cpu_baseline(circ, budget_s: float):
                       f"{dt:.1f} s on {osv.threads()} OpenMP threads"}
 
 
+def copy_bandwidth(sv, n, reps=10):
+    """Best-of-reps device copy of a 2^n complex64 state (16-byte streaming
+    kernel), host-timed around the synchronous call: read + write bytes / s."""
+    a = sv.sv_alloc(n, sv.SV_C64)
+    b = sv.sv_alloc(n, sv.SV_C64)
+    sv.sv_copy(b, a)
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        sv.sv_copy(b, a)
+        best = min(best, time.perf_counter() - t0)
+    sv.sv_free(a)
+    sv.sv_free(b)
+    return 2.0 * (8 << n) / best / 1e9
+
+
+def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
+    """The QSVT ladder of one Carleman-LBM instance at degree d from b: gates/s
+    per (name, dtype, mode, elementary) variant, timed with HIP events."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    from paper_2606_12770_amd.circuits import qsp
+    cfg = cc.CarlemanConfig(**cfg_kw)
+    enc = cc.build_ul(cfg)
+    phases, _c, _info = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)
+    native = cc.build_qsvt(enc, phases)
+    rhs = cc.rhs_x_block(cfg, enc.layout)
+    out = {"qubits": enc.layout.n, "degree": d, "ops_native": len(native), "config": cfg_kw}
+    for name, dtype, mode, elementary in variants:
+        circ = cc.lower_to_elementary(native) if elementary else native
+        ops, params = circ.arrays()
+        plan = sv.sv_plan_create(circ.n, dtype, ops, params, mode)
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(circ.n, dtype)
+        sv.sv_set_amplitudes(st, rhs, 0)
+        sv.sv_plan_execute(plan, st, 1)
+        ms = sv.sv_plan_time(plan, st, reps) / reps
+        out[name] = {"gates": len(ops), "gates_per_s": len(ops) / (ms / 1e3), "ms": ms,
+                     "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
+                     "GBps_algorithmic": info["bytes_moved"] / (ms / 1e3) / 1e9}
+        log(f"carleman {enc.layout.n}q {name}: {out[name]['gates_per_s']:.0f} gates/s, {ms:.2f} ms, "
+            f"{info['n_launches']} launches")
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +110,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-carleman", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
@@ -134,6 +181,21 @@ def main():
             "kernel": "k_tile_pass<float,4>", "launches_per_step": launches,
             "tile_pass_launches_per_step": tile_launches, "avg_launch_us": avg_launch_ms * 1e3}
 
+    copy_gbs = copy_bandwidth(sv, n)
+    roof["frac_vs_copy"] = achieved / copy_gbs
+    log(f"copy bandwidth {copy_gbs:.0f} GB/s")
+
+    carleman = None
+    if not args.skip_carleman:
+        C64, C128, P, F = sv.SV_C64, sv.SV_C128, sv.SV_MODE_PLAIN, sv.SV_MODE_FUSED
+        carleman = {
+            "small_22q": carleman_ladder(sv, dict(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05), 13, [
+                ("plain_c128", C128, P, False), ("fused_c128", C128, F, False), ("fused_c64", C64, F, False),
+                ("plain_c128_elementary", C128, P, True), ("fused_c64_elementary", C64, F, True)]),
+            "grid64_31q": carleman_ladder(sv, dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02), 13, [
+                ("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1),
+        }
+
     cpu = None
     if not args.skip_cpu:
         log("cpu baseline ...")
@@ -160,6 +222,8 @@ def main():
         "fused_c128": {"gates_per_s": n_gates / (ms128 / 1e3), "ms_per_step": ms128,
                        "launches": info128["n_launches"]},
         "plain_fp64": plain,
+        "copy_GBps": copy_gbs,
+        "carleman_qsvt": carleman,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -291,3 +291,37 @@ def expm_apply(A, y0, t):
 
 def density(f1, nx):
     return f1.reshape(nx, Q).sum(1)
+
+
+# ---- matrix-free products for full-size checks --------------------------------
+
+def carleman_apply(nx, tau, y, boundary="periodic"):
+    """A y for the order-2 Carleman matrix without forming A22:
+    A11 y1 + A12 y2 on order 1 and, writing y2 as the D x D matrix Y with
+    Y[i, j] = y2[i D + j], (A11 (x) I + I (x) A11) y2 = vec(A11 Y + Y A11^T)."""
+    A11 = a11(nx, tau, boundary)
+    A12 = a12(nx, tau, boundary)
+    D = A11.shape[0]
+    y = np.asarray(y)
+    y1, Y = y[:D], y[D:].reshape(D, D)
+    out1 = A11 @ y1 + A12 @ y[D:]
+    out2 = (A11 @ Y) + (A11 @ Y.T).T
+    return np.concatenate([out1, out2.reshape(-1)])
+
+
+def l_apply(apply_a, x, dt, nt, nk, n_m, n_k, block):
+    """L x on the block layout of l_matrix, with A applied by apply_a."""
+    M, Kb = l_block_layout(nt, nk, n_m, n_k)
+    xb = np.asarray(x).reshape(M * Kb, block)
+    out = xb.astype(np.result_type(xb, float)).copy()
+    for m in range(M):
+        for k in range(Kb):
+            r = m * Kb + k
+            if m < nt:
+                if k < nk:
+                    out[r + 1] -= dt / (k + 1) * apply_a(xb[r])
+                if k <= nk:
+                    out[(m + 1) * Kb] -= xb[r]
+            elif r + 1 < M * Kb:
+                out[r + 1] -= xb[r]
+    return out.reshape(-1)

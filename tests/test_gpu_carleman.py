@@ -1,0 +1,190 @@
+"""The Carleman-LBM QSVT circuit on the GPU, through the C ABI.
+
+* Small plain method (N_x = 8, tau = 1, N_K = 2, N_t = 2, 22 qubits): the whole
+  ladder at d = 13 against the FP64 reference simulator, in the native gate IR
+  and lowered to single-qubit + multi-controlled X / phase gates, complex128
+  (per-gate and fused) and complex64 (fused).
+* The same instance at the working degree d = 10 kappa + 1: the post-selected
+  amplitudes against the classical singular-value transform of the same
+  phases, and the final-time rows against the classical Taylor solution.
+* Full-size workloads (31 and 34 qubits, complex64): one call of U_L on b with
+  the ancillas projected out must equal L b / lambda_L on every system
+  amplitude (the block-encoding property, exact at any size), with the
+  classical L b from matrix-free products.
+"""
+import numpy as np
+import pytest
+
+from oracle import carleman as oc
+from oracle import qsvt as oq
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+from paper_2606_12770_amd.circuits import qsp
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+C1 = dict(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05)
+C3 = dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02)
+C5 = dict(nx=256, tau=0.8, nk=4, nt=4, dt=0.1, amp=0.08, u0=0.02)
+
+
+def carleman_to_reg(nx):
+    na = nx.bit_length() - 1
+    a = np.arange(nx)
+    q = np.arange(3)
+    f1 = (q[None, :] | (a[:, None] << 2)).reshape(-1)             # index 3 a + q
+    i = np.arange(3 * nx)
+    ai, qi = i // 3, i % 3
+    first = qi | (ai << 2)
+    second = (qi << (2 + na)) | (ai << (4 + na))
+    f2 = (first[:, None] | second[None, :] | (1 << (4 + 2 * na))).reshape(-1)
+    return np.concatenate([f1, f2]).astype(np.int64)
+
+
+def system_to_reg(cfg, L):
+    cr = carleman_to_reg(cfg.nx)
+    out = []
+    for m in range(1 << L.n_m):
+        for k in range(1 << L.n_k):
+            out.append(cr | (k << L.n_x) | (m << (L.n_x + L.n_k)))
+    return np.concatenate(out)
+
+
+def infid(a, b):
+    return 1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+_cache = {}
+
+
+def c1_ladder(form):
+    if form not in _cache:
+        cfg = cc.CarlemanConfig(**C1)
+        enc = cc.build_ul(cfg)
+        phases, _c, _info = qsp.inversion_phases(1.2, 13)
+        circ = cc.build_qsvt(enc, phases)
+        if form == "elementary":
+            circ = cc.lower_to_elementary(circ)
+        psi0 = np.zeros(1 << circ.n, dtype=np.complex128)
+        psi0[: 1 << enc.layout.n_x] = cc.rhs_x_block(cfg, enc.layout)
+        print(f"oracle: C1 ladder d=13 {form}, {len(circ)} ops on {circ.n} qubits", flush=True)
+        _cache[form] = (circ, psi0, osv.run(circ, psi0))
+    return _cache[form]
+
+
+@pytest.mark.parametrize("form", ["native", "elementary"])
+@pytest.mark.parametrize("dtype,mode", [(1, 0), (1, 1), (0, 1)])
+def test_c1_ladder_matches_oracle(form, dtype, mode):
+    sv = require_gpu()
+    circ, psi0, want = c1_ladder(form)
+    st = sv.State(circ.n, dtype, psi0)
+    st.apply(circ, mode)
+    got = st.amplitudes()
+    st.close()
+    f = infid(want, got)
+    print(f"C1 d=13 {form} dtype={dtype} mode={mode}: infidelity {f:.2e} "
+          f"maxabs {np.max(np.abs(got - want)):.2e}", flush=True)
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+        assert f < 1e-12
+    else:
+        assert f < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_c1_working_degree_physics(dtype):
+    sv = require_gpu()
+    cfg = cc.CarlemanConfig(**C1)
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    kappa = enc.lam / oc.sigma_min(Lm)
+    d = qsp.qsvt_degree(kappa)
+    phases, _c, _info = qsp.inversion_phases(kappa, d)
+    circ = cc.build_qsvt(enc, phases)
+    print(f"C1 working degree: kappa={kappa:.1f} d={d} ops={len(circ)} dtype={dtype}", flush=True)
+
+    st = sv.State(L.n, dtype)
+    sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
+    plan = sv.Plan(L.n, dtype, circ)
+    plan.execute(st)
+    sys_amp = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)   # ancillas and signal 0
+    norm2 = st.prob()
+    mask, val = cc.postselect_condition(L)
+    P = sv.sv_postselect(st.h, mask, val, keep=True, renormalize=True)
+    post = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)
+    st.close()
+    plan.close()
+
+    f0 = oc.initial_f1(cfg.nx, cfg.amp)
+    y0 = oc.carleman_vector(f0)
+    b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    b /= np.linalg.norm(b)
+    M = (Lm.T / enc.lam).tocsr()
+    MT = M.T.tocsr()
+    co = oq.odd_chebyshev_of_qsp(phases)
+    want = (-1j) ** d * oq.odd_sv_apply(lambda v: M @ v, lambda v: MT @ v, co, b)
+    idx = system_to_reg(cfg, L)
+    got = sys_amp[idx]
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    f_tr = infid(want, got)
+    print(f"  norm drift {abs(norm2 - 1):.2e}  P_final {P:.4e}  rel max err vs transform {err:.2e}  "
+          f"infidelity vs transform {f_tr:.2e}", flush=True)
+    # Norm drift: a gate changes |psi|^2 by at most a couple of units in the last
+    # place of the working precision per application, so n_ops * 2^-(p-1) bounds
+    # a linear accumulation (p = 53 or 24).  In FP32 the drift is nearly a global
+    # scale: fp32(1/sqrt 2) is 1.7e-8 low and every amplitude crosses the ten
+    # label Hadamards of each call, which the scale-free infidelity ignores.
+    eps = 2.0 ** -52 if dtype == 1 else 2.0 ** -23
+    assert abs(norm2 - 1.0) < len(circ) * eps
+    assert f_tr < (1e-12 if dtype == 1 else 1e-6)
+    if dtype == 1:
+        assert err < 1e-9
+
+    x = oc.forward_substitution(Lm, b, len(y0))
+    D = len(y0)
+    R = (1 << L.n_m) * (1 << L.n_k)
+    fin = slice(R // 2 * D, R * D)
+    F = 1.0 - infid(x[fin], post[idx][fin])
+    print(f"  final-time rows: 1 - F vs Taylor solution {1 - F:.2e}", flush=True)
+    assert 1.0 - F < 1e-5
+    # post-selection left nothing outside the selected rows
+    keep = post[idx].copy()
+    keep[fin] = 0
+    assert np.max(np.abs(keep)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["C3", "C5"])
+def test_ul_block_encoding_full_size(name):
+    sv = require_gpu()
+    cfg = cc.CarlemanConfig(**(C3 if name == "C3" else C5))
+    enc = cc.build_ul(cfg, with_signal=(name == "C3"))
+    L = enc.layout
+    print(f"{name}: U_L on b, {L.n} qubits complex64, {len(enc.circuit)} ops", flush=True)
+    st = sv.State(L.n, sv.SV_C64)
+    b_blk = cc.rhs_x_block(cfg, L)
+    sv.sv_set_amplitudes(st.h, b_blk, 0)
+    plan = sv.Plan(L.n, sv.SV_C64, enc.circuit)
+    plan.execute(st)
+    norm2 = st.prob()
+    got = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys) * enc.lam
+    st.close()
+    plan.close()
+
+    idx = system_to_reg(cfg, L)
+    D = 3 * cfg.nx + (3 * cfg.nx) ** 2
+    b = np.zeros(len(idx))
+    y0 = oc.carleman_vector(oc.initial_f1(cfg.nx, cfg.amp, cfg.u0))
+    b[:D] = y0 / np.linalg.norm(y0)
+    want = oc.l_apply(lambda v: oc.carleman_apply(cfg.nx, cfg.tau, v), b, cfg.dt, cfg.nt, cfg.nk,
+                      L.n_m, L.n_k, D)
+    err = np.max(np.abs(got[idx] - want)) / np.max(np.abs(want))
+    rest = np.ones(1 << L.n_sys, bool)
+    rest[idx] = False
+    leak = np.max(np.abs(got[rest]))
+    print(f"  norm drift {abs(norm2 - 1):.2e}  rel max err {err:.2e}  unphysical {leak:.2e}", flush=True)
+    assert abs(norm2 - 1.0) < 1e-4
+    assert err < 1e-5
+    assert leak < 1e-5 * np.max(np.abs(want))

@@ -147,3 +147,16 @@ def test_kappa_first_order_qsvt_run():
     L = oc.l_matrix(A, dt, nt, nk, n_m, n_k)
     kappa = 8.0 / oc.sigma_min(L)
     assert 700 < kappa < 900, kappa
+
+
+@pytest.mark.parametrize("nx,tau", [(4, 0.8), (8, 1.1)])
+def test_matrix_free_products_match_explicit_matrices(nx, tau):
+    rng = np.random.default_rng(nx)
+    A = oc.carleman_matrix(nx, tau, 2)
+    y = rng.standard_normal(A.shape[0])
+    assert np.max(np.abs(oc.carleman_apply(nx, tau, y) - A @ y)) < 1e-12
+    nt, nk, n_m, n_k = 2, 2, 2, 2
+    Lm = oc.l_matrix(A, 0.1, nt, nk, n_m, n_k)
+    x = rng.standard_normal(Lm.shape[0])
+    got = oc.l_apply(lambda v: oc.carleman_apply(nx, tau, v), x, 0.1, nt, nk, n_m, n_k, A.shape[0])
+    assert np.max(np.abs(got - Lm @ x)) < 1e-12

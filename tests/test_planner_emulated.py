@@ -84,3 +84,21 @@ def test_wide_register_falls_back_to_plain_launch(emu):
     psi0 = random_state(n, 3)
     got, stats = run_emu(emu, c, psi0, 1, 10, 4)
     assert np.max(np.abs(got - osv.run(c, psi0))) < 1e-12
+
+
+@pytest.mark.parametrize("b,rb", [(10, 4), (12, 4), (13, 5)])
+@pytest.mark.parametrize("elementary", [False, True])
+def test_fused_plan_carleman_ladder(emu, b, rb, elementary):
+    """The QSVT ladder of a small Carleman-LBM instance through the fused planner."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    cfg = cc.CarlemanConfig(nx=2, tau=0.9, nk=2, nt=2, dt=0.1, amp=0.1)
+    enc = cc.build_ul(cfg)
+    rng = np.random.default_rng(b)
+    circ = cc.build_qsvt(enc, rng.uniform(-np.pi, np.pi, 4))
+    if elementary:
+        circ = cc.lower_to_elementary(circ)
+    psi0 = random_state(circ.n, b + rb)
+    want = osv.run(circ, psi0)
+    got, stats = run_emu(emu, circ, psi0, 1, b, rb)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[0] * 3 < len(circ)
