@@ -23,14 +23,6 @@ template <typename R> struct CTT;
 template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4; };
 template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
 
-// XOR-fold the higher bits of a local index into its lowest LOWB bits so that
-// threads strided by any power of two land in different LDS banks.
-template <int LOWB>
-__device__ __forceinline__ uint32_t lds_swizzle(uint32_t l)
-{
-    const uint32_t h = (l >> LOWB) ^ (l >> (2 * LOWB)) ^ (l >> (3 * LOWB)) ^ (l >> (4 * LOWB));
-    return l ^ (h & ((1u << LOWB) - 1u));
-}
 
 template <typename C, typename R>
 __device__ __forceinline__ C row2(R ar, R ai, R br, R bi, C a, C b)
@@ -73,13 +65,13 @@ __device__ __forceinline__ uint32_t apply_perms(uint32_t l, const TileOp *__rest
 // Register-level ops: slot s (with the target slot bit clear) is processed when
 // bit s of the uniform slotmask is set; the thread part of the condition has
 // already been applied by the caller.
-template <int K, int NR, typename C, typename R>
+template <int K, int NR, bool FULL, typename C, typename R>
 __device__ __forceinline__ void reg_u(C (&x)[NR], const R *m, uint32_t slotmask)
 {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
         if (s & (1 << K)) continue;
-        if (!((slotmask >> s) & 1u)) continue;
+        if (!FULL && !((slotmask >> s) & 1u)) continue;
         const int s1 = s | (1 << K);
         const C a = x[s], b = x[s1];
         x[s] = row2(m[0], m[1], m[2], m[3], a, b);
@@ -87,13 +79,13 @@ __device__ __forceinline__ void reg_u(C (&x)[NR], const R *m, uint32_t slotmask)
     }
 }
 
-template <int K, int NR, typename C, typename R>
+template <int K, int NR, bool FULL, typename C, typename R>
 __device__ __forceinline__ void reg_ur(C (&x)[NR], const R *m, uint32_t slotmask)
 {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
         if (s & (1 << K)) continue;
-        if (!((slotmask >> s) & 1u)) continue;
+        if (!FULL && !((slotmask >> s) & 1u)) continue;
         const int s1 = s | (1 << K);
         const C a = x[s], b = x[s1];
         C r0, r1;
@@ -106,13 +98,13 @@ __device__ __forceinline__ void reg_ur(C (&x)[NR], const R *m, uint32_t slotmask
     }
 }
 
-template <int K, int NR, typename C>
+template <int K, int NR, bool FULL, typename C>
 __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
 {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
         if (s & (1 << K)) continue;
-        if (!((slotmask >> s) & 1u)) continue;
+        if (!FULL && !((slotmask >> s) & 1u)) continue;
         const int s1 = s | (1 << K);
         const C a = x[s];
         x[s] = x[s1];
@@ -120,15 +112,22 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
     }
 }
 
-#define SV_SLOT_DISPATCH(FN, ...)                                   \
-    switch (op.slot) {                                              \
-    case 0: FN<0, NR>(__VA_ARGS__); break;                          \
-    case 1: FN<1, NR>(__VA_ARGS__); break;                          \
-    case 2: FN<2, NR>(__VA_ARGS__); break;                          \
-    case 3: FN<3, NR>(__VA_ARGS__); break;                          \
-    default:                                                        \
-        if constexpr (RB > 4) FN<(RB > 4 ? 4 : 0), NR>(__VA_ARGS__); \
-        break;                                                      \
+#define SV_SLOT_DISPATCH1(FN, F, ...)                                   \
+    switch (op.slot) {                                                  \
+    case 0: FN<0, NR, F>(__VA_ARGS__); break;                           \
+    case 1: FN<1, NR, F>(__VA_ARGS__); break;                           \
+    case 2: FN<2, NR, F>(__VA_ARGS__); break;                           \
+    case 3: FN<3, NR, F>(__VA_ARGS__); break;                           \
+    default:                                                            \
+        if constexpr (RB > 4) FN<(RB > 4 ? 4 : 0), NR, F>(__VA_ARGS__); \
+        break;                                                          \
+    }
+// ops whose condition holds on every register slot skip the per-slot tests
+#define SV_SLOT_DISPATCH(FN, ...)                                       \
+    if (op.slotmask == kAllSlots) {                                     \
+        SV_SLOT_DISPATCH1(FN, true, __VA_ARGS__)                        \
+    } else {                                                            \
+        SV_SLOT_DISPATCH1(FN, false, __VA_ARGS__)                       \
     }
 
 template <typename R, int RB>
@@ -139,31 +138,35 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int LOWB = CTT<R>::LOWB;
+    constexpr uint32_t kAllSlots = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
     extern __shared__ unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t nthr = pass->nthr;
-    const uint32_t ntile = pass->ntile;
 
-    // absolute index bits of this tile
+    // absolute index bits of this tile (uniform): bit runs of the tile counter
     const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
     uint64_t base = 0;
-    for (uint32_t j = 0; j < ntile; ++j) base |= ((tile >> j) & 1ull) << pass->tpos[j];
-
+    for (uint32_t r = 0; r < pass->n_tile_runs; ++r) {
+        const uint32_t sh = pass->tile_shift[r];
+        base |= ((tile >> (sh & 0xffu)) & pass->tile_mask[r]) << (sh >> 8);
+    }
     // load mapping: thread bits = local bits [0, nthr), slots = local bits [nthr, b)
     uint64_t gthr = 0;
-    for (uint32_t j = 0; j < nthr; ++j) gthr |= (uint64_t)((tid >> j) & 1u) << pass->spos[j];
-    const uint64_t gbase = base | gthr;
+    for (uint32_t r = 0; r < pass->n_gthr_runs; ++r) {
+        const uint32_t sh = pass->gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & pass->gthr_mask[r]) << (sh >> 8);
+    }
+    C *const pt = psi + (base | gthr);
 
     C x[NR];
 #pragma unroll
-    for (int s = 0; s < NR; ++s) x[s] = psi[gbase | pass->goff[s]];
+    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
 
-    // current mapping: local index of slot s = thr | ro[s] (disjoint bits); the
-    // LDS swizzle is GF(2)-linear, so swz(thr | ro[s]) = swz(thr) ^ swz(ro[s])
+    // current mapping: local index of slot s = thr | regoff[s] (disjoint bits);
+    // the LDS swizzle is GF(2)-linear, so its slot part comes precomputed
     uint32_t thr = tid;
-    const TileStage *S0 = stages + pass->stage_begin;
     const uint32_t se = pass->stage_end;
     for (uint32_t st = pass->stage_begin; st < se; ++st) {
         const TileStage &S = stages[st];
@@ -171,30 +174,39 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
             const TileStage &P = stages[st - 1];
             __syncthreads();
             if (S.perm_begin == S.perm_end) {
-                const uint32_t tw = lds_swizzle<LOWB>(thr);
+                const uint32_t tw = lds_swizzle(thr, LOWB);
 #pragma unroll
-                for (int s = 0; s < NR; ++s) lds[tw ^ lds_swizzle<LOWB>(P.regoff[s])] = x[s];
+                for (int s = 0; s < NR; ++s) lds[tw ^ P.swz[s]] = x[s];
             } else {
 #pragma unroll
                 for (int s = 0; s < NR; ++s) {
                     const uint32_t l = apply_perms(thr | P.regoff[s], ops, S.perm_begin, S.perm_end, base);
-                    lds[lds_swizzle<LOWB>(l)] = x[s];
+                    lds[lds_swizzle(l, LOWB)] = x[s];
                 }
             }
             __syncthreads();
             uint32_t t2 = 0;
-            for (uint32_t j = 0; j < nthr; ++j) t2 |= ((tid >> j) & 1u) << S.thrpos[j];
+            for (uint32_t r = 0; r < S.n_thr_runs; ++r) {
+                const uint32_t w = S.thr_run[r];
+                t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+            }
             thr = t2;
-            const uint32_t tr = lds_swizzle<LOWB>(thr);
+            const uint32_t tr = lds_swizzle(thr, LOWB);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ lds_swizzle<LOWB>(S.regoff[s])];
+            for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ S.swz[s]];
         }
+        // op records are prefetched one ahead; parameters sit at a fixed stride,
+        // so their loads do not wait for the record
+        TileOp nxt;
+        if (S.op_begin < S.op_end) nxt = ops[S.op_begin];
         for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
-            const TileOp op = ops[k];
+            const TileOp op = nxt;
+            if (k + 1 < S.op_end) nxt = ops[k + 1];
+            const R *__restrict__ pk = prm + (size_t)k * kParamStride;
             const bool tc = (tid & op.tidmask) == op.tidval;
             if (op.kind == T_PROJ) {
                 const bool zg = (base & op.gmask) == op.gval;
-                const R c = prm[op.param], sn = prm[op.param + 1];
+                const R c = pk[0], sn = pk[1];
                 const uint32_t sig_thread = op.a == 2 ? ((tid >> op.b) & 1u) : 0u;
                 const uint32_t sig_tile = op.a == 0 ? (uint32_t)((base >> op.b) & 1ull) : 0u;
 #pragma unroll
@@ -215,17 +227,17 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
             if (op.kind == T_U) {
                 R m[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) m[j] = prm[op.param + j];
+                for (int j = 0; j < 8; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_u, x, m, op.slotmask)
             } else if (op.kind == T_UR) {
                 R m[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) m[j] = prm[op.param + j];
+                for (int j = 0; j < 4; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_ur, x, m, op.slotmask)
             } else if (op.kind == T_X) {
                 SV_SLOT_DISPATCH(reg_x, x, op.slotmask)
             } else if (op.kind == T_PHASE) {
-                const R c = prm[op.param], sn = prm[op.param + 1];
+                const R c = pk[0], sn = pk[1];
 #pragma unroll
                 for (int s = 0; s < NR; ++s) {
                     if (!((op.slotmask >> s) & 1u)) continue;
@@ -243,24 +255,23 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
         const TileStage &L = stages[se - 1];
         __syncthreads();
         if (pass->fperm_begin == pass->fperm_end) {
-            const uint32_t tw = lds_swizzle<LOWB>(thr);
+            const uint32_t tw = lds_swizzle(thr, LOWB);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) lds[tw ^ lds_swizzle<LOWB>(L.regoff[s])] = x[s];
+            for (int s = 0; s < NR; ++s) lds[tw ^ L.swz[s]] = x[s];
         } else {
 #pragma unroll
             for (int s = 0; s < NR; ++s) {
                 const uint32_t l = apply_perms(thr | L.regoff[s], ops, pass->fperm_begin, pass->fperm_end, base);
-                lds[lds_swizzle<LOWB>(l)] = x[s];
+                lds[lds_swizzle(l, LOWB)] = x[s];
             }
         }
         __syncthreads();
-        const uint32_t tr = lds_swizzle<LOWB>(tid);
+        const uint32_t tr = lds_swizzle(tid, LOWB);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ lds_swizzle<LOWB>((uint32_t)s << nthr)];
+        for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ pass->swz0[s]];
     }
-    (void)S0;
 #pragma unroll
-    for (int s = 0; s < NR; ++s) psi[gbase | pass->goff[s]] = x[s];
+    for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
 }
 
 template <typename R, int RB>

@@ -64,10 +64,30 @@ static_assert(sizeof(TileOp) == 40, "TileOp layout");
 
 constexpr int kMaxRB = 5;
 constexpr int kMaxB = 14;
+constexpr int kMaxThrRuns = 8;
+constexpr int kMaxTileRuns = 16;
+constexpr int kParamStride = 8;  // reals of parameters reserved per tile op (op k at k * 8)
+
+// LDS placement of local index l: XOR-fold the higher bits into the lowest
+// `lowb` bits so that threads strided by any power of two hit different banks.
+// GF(2)-linear, so swz(a | b) = swz(a) ^ swz(b) for disjoint a, b: the planner
+// stores swz(register offset) per slot and the kernel XORs in swz(thread part).
+constexpr uint32_t lds_swizzle(uint32_t l, int lowb)
+{
+    const uint32_t h = (l >> lowb) ^ (l >> (2 * lowb)) ^ (l >> (3 * lowb)) ^ (l >> (4 * lowb));
+    return l ^ (h & ((1u << lowb) - 1u));
+}
+
+// A run of consecutive source bits moved as one block: out |= ((in >> src) & mask) << dst.
+// Thread-to-local runs pack (src, dst, mask) into one word: src | dst << 8 | mask << 16.
+constexpr uint32_t pack_run16(uint32_t src, uint32_t dst, uint32_t mask) { return src | (dst << 8) | (mask << 16); }
 
 struct TileStage {
     uint32_t op_begin, op_end;      // register-level ops of the stage
     uint32_t perm_begin, perm_end;  // permutations applied on entry to the stage
+    uint32_t n_thr_runs;            // thread bits -> local bits, as runs
+    uint32_t thr_run[kMaxThrRuns];
+    uint32_t swz[1 << kMaxRB];      // lds_swizzle(regoff[s])
     uint8_t thrpos[16];             // local bit index of thread bit j
     uint16_t regoff[1 << kMaxRB];   // local index offset of register slot s
 };
@@ -78,11 +98,35 @@ struct TilePass {
     uint8_t b, rb, nthr, ntile;
     uint8_t final_exchange;           // 1: exchange back to the load mapping before the store
     uint8_t pad[3];
+    uint32_t n_tile_runs;             // tile counter bits -> absolute index bits, as runs
+    uint32_t n_gthr_runs;             // thread bits -> absolute index bits (load mapping), as runs
+    uint32_t tile_shift[kMaxTileRuns];  // src | dst << 8
+    uint64_t tile_mask[kMaxTileRuns];
+    uint32_t gthr_shift[kMaxThrRuns];
+    uint32_t gthr_mask[kMaxThrRuns];
+    uint32_t swz0[1 << kMaxRB];       // lds_swizzle(s << nthr): load-mapping slots
     uint8_t spos[kMaxB];              // local bit -> qubit
     uint8_t pad2[2];
     uint8_t tpos[48];                 // tile bit -> qubit
     uint64_t goff[1 << kMaxRB];       // absolute index offset of load-mapping register slot s
 };
+
+// Runs of a bit map src bit j -> dst position pos[j] (pos ascending): each
+// maximal stretch with pos[j+1] = pos[j] + 1 becomes one (src, dst, width).
+template <typename F>
+inline int bit_runs(const uint8_t *pos, int count, F &&emit)
+{
+    int runs = 0;
+    int j = 0;
+    while (j < count) {
+        int w = 1;
+        while (j + w < count && pos[j + w] == pos[j] + w) ++w;
+        emit(j, (int)pos[j], w);
+        ++runs;
+        j += w;
+    }
+    return runs;
+}
 
 // ---------------------------------------------------------------------------
 // Plain per-gate launches.

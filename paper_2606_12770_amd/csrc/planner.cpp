@@ -195,6 +195,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
 
     const int nthr = b - rb;
     const int L0 = std::min(nthr, p->dtype == SV_C64 ? 5 : 4);
+    const int lowb = p->dtype == SV_C64 ? 4 : 3;  // LDS swizzle width (16 B banks groups)
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
 
@@ -237,6 +238,8 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
 
         // ---- lay out the pass ----
         TilePass P{};
+        P.n_tile_runs = 0;
+        P.n_gthr_runs = 0;
         P.b = (uint8_t)b;
         P.rb = (uint8_t)rb;
         P.nthr = (uint8_t)nthr;
@@ -259,7 +262,18 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             for (int k = 0; k < rb; ++k)
                 if ((s >> k) & 1) off |= 1ull << P.spos[nthr + k];
             P.goff[s] = off;
+            P.swz0[s] = lds_swizzle((uint32_t)s << nthr, lowb);
         }
+        P.n_tile_runs = (uint32_t)bit_runs(P.tpos, P.ntile, [&](int src, int dst, int w) {
+            const int r = (int)P.n_tile_runs++;
+            P.tile_shift[r] = (uint32_t)src | ((uint32_t)dst << 8);
+            P.tile_mask[r] = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+        });
+        P.n_gthr_runs = (uint32_t)bit_runs(P.spos, nthr, [&](int src, int dst, int w) {
+            const int r = (int)P.n_gthr_runs++;
+            P.gthr_shift[r] = (uint32_t)src | ((uint32_t)dst << 8);
+            P.gthr_mask[r] = (1u << w) - 1u;
+        });
         auto split = [&](uint64_t mask, uint64_t val, TileOp &t) {
             t.lmask = 0;
             t.lval = 0;
@@ -290,11 +304,25 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 for (int k = 0; k < rb; ++k)
                     if ((s >> k) & 1) off |= 1u << rs[k];
                 S.regoff[s] = (uint16_t)off;
+                S.swz[s] = lds_swizzle(off, lowb);
             }
+            S.n_thr_runs = 0;
+            bit_runs(S.thrpos, nthr, [&](int src, int dst, int w) {
+                S.thr_run[S.n_thr_runs++] = pack_run16((uint32_t)src, (uint32_t)dst, (1u << w) - 1u);
+            });
             p->stages.push_back(S);
         };
         auto is_reg_kind = [&](uint32_t k) { return k == SV_OP_U || k == SV_OP_X; };
         auto is_perm_kind = [&](uint32_t k) { return k == SV_OP_INC || k == SV_OP_DEC || k == SV_OP_SWAP; };
+        // parameters of the op about to be appended to tops live at a fixed stride
+        // (kParamStride reals per tops entry), so the kernel can fetch them without
+        // first reading the op record
+        auto put_params = [&](const double *v, int cnt) {
+            const size_t at = p->tops.size() * kParamStride;
+            if (p->tparams.size() < at + kParamStride) p->tparams.resize(at + kParamStride, 0.0);
+            for (int k = 0; k < cnt; ++k) p->tparams[at + k] = v[k];
+            return (uint32_t)at;
+        };
 
         P.stage_begin = (uint32_t)p->stages.size();
         // perms are collected in a side list and copied into tops when a stage opens
@@ -377,14 +405,16 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 if (o.kind == SV_OP_U) {
                     const bool real = o.m[1] == 0.0 && o.m[3] == 0.0 && o.m[5] == 0.0 && o.m[7] == 0.0;
                     t.kind = real ? T_UR : T_U;
-                    t.param = (uint32_t)p->tparams.size();
+                    double v[8];
                     if (real) {
-                        for (int k = 0; k < 8; k += 2) p->tparams.push_back(o.m[k]);
+                        for (int k = 0; k < 4; ++k) v[k] = o.m[2 * k];
                     } else {
-                        for (int k = 0; k < 8; ++k) p->tparams.push_back(o.m[k]);
+                        for (int k = 0; k < 8; ++k) v[k] = o.m[k];
                     }
+                    t.param = put_params(v, real ? 4 : 8);
                 } else {
                     t.kind = T_X;
+                    t.param = put_params(nullptr, 0);
                 }
                 p->tops.push_back(t);
                 continue;
@@ -415,9 +445,8 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 }
             }
             stage_split(t);
-            t.param = (uint32_t)p->tparams.size();
-            p->tparams.push_back(std::cos(o.m[0]));
-            p->tparams.push_back(std::sin(o.m[0]));
+            const double cs[2] = {std::cos(o.m[0]), std::sin(o.m[0])};
+            t.param = put_params(cs, 2);
             p->tops.push_back(t);
         }
         p->stages.back().op_end = (uint32_t)p->tops.size();
@@ -436,6 +465,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->info.n_stages += P.stage_end - P.stage_begin;
         p->info.bytes_moved += 2ull * (1ull << n) * esize;
     }
+    p->tparams.resize(p->tops.size() * kParamStride, 0.0);
     p->info.tile_pass_bytes = 2ull * (1ull << n) * esize;
     p->info.n_launches = p->steps.size();
     return SV_OK;

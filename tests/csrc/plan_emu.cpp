@@ -101,6 +101,56 @@ uint32_t perms(uint32_t l, const std::vector<TileOp> &ops, uint32_t pb, uint32_t
     return l;
 }
 
+int check_pass_fields(const sv_plan &p, uint32_t pi)
+{
+    const TilePass &P = p.passes[pi];
+    const int b = P.b, rb = P.rb, nthr = P.nthr, NR = 1 << rb, T = 1 << nthr;
+    const int lowb = p.dtype == SV_C64 ? 4 : 3;
+    // precomputed pass fields: run maps and swizzled slot offsets
+    for (int s = 0; s < NR; ++s)
+        if (P.swz0[s] != lds_swizzle((uint32_t)s << nthr, lowb)) return 20;
+    for (int t = 0; t < T; ++t) {
+        uint64_t g0 = 0, g1 = 0;
+        for (int j = 0; j < nthr; ++j) g0 |= (uint64_t)((t >> j) & 1) << P.spos[j];
+        for (uint32_t r = 0; r < P.n_gthr_runs; ++r)
+            g1 |= (uint64_t)(((uint32_t)t >> (P.gthr_shift[r] & 0xffu)) & P.gthr_mask[r]) << (P.gthr_shift[r] >> 8);
+        if (g0 != g1) return 21;
+    }
+    for (uint32_t st = P.stage_begin; st < P.stage_end; ++st) {
+        const TileStage &S = p.stages[st];
+        // the kernel reads the parameters of op k at k * kParamStride
+        for (uint32_t k = S.op_begin; k < S.op_end; ++k)
+            if (p.tops[k].param != k * (uint32_t)kParamStride || (k + 1) * kParamStride > p.tparams.size()) return 26;
+        for (int s = 0; s < NR; ++s)
+            if (S.swz[s] != lds_swizzle(S.regoff[s], lowb)) return 22;
+        for (int t = 0; t < T; ++t) {
+            uint32_t a = 0, c = 0;
+            for (int j = 0; j < nthr; ++j) a |= (uint32_t)((t >> j) & 1) << S.thrpos[j];
+            for (uint32_t r = 0; r < S.n_thr_runs; ++r) {
+                const uint32_t w = S.thr_run[r];
+                c |= (((uint32_t)t >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+            }
+            if (a != c) return 23;
+            // the kernel's XOR form of the LDS address equals the swizzle of the local index
+            for (int s = 0; s < NR; ++s) {
+                const uint32_t lx = lds_swizzle(a, lowb) ^ S.swz[s];
+                if (lx != lds_swizzle(a | S.regoff[s], lowb) || lx >= (1u << b)) return 24;
+            }
+        }
+    }
+    // tile runs on a sample of tile counters (all of them when few)
+    const uint64_t ntiles = 1ull << P.ntile;
+    const uint64_t step = ntiles > 4096 ? ntiles / 4096 + 1 : 1;
+    for (uint64_t tile = 0; tile < ntiles; tile += step) {
+        uint64_t base = 0, b2 = 0;
+        for (int j = 0; j < P.ntile; ++j) base |= ((tile >> j) & 1ull) << P.tpos[j];
+        for (uint32_t r = 0; r < P.n_tile_runs; ++r)
+            b2 |= ((tile >> (P.tile_shift[r] & 0xffu)) & P.tile_mask[r]) << (P.tile_shift[r] >> 8);
+        if (b2 != base) return 25;
+    }
+    return 0;
+}
+
 int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::vector<int> &wr)
 {
     const TilePass &P = p.passes[pi];
@@ -113,9 +163,20 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
     std::vector<int> filled((size_t)1 << b);
     std::vector<uint32_t> thr(T);
     std::vector<uint32_t> ro(NR);
+    const int lowb = p.dtype == SV_C64 ? 4 : 3;
+    {
+        const int rc = check_pass_fields(p, pi);
+        if (rc) return rc;
+    }
     for (uint64_t tile = 0; tile < (1ull << P.ntile); ++tile) {
         uint64_t base = 0;
         for (int j = 0; j < P.ntile; ++j) base |= ((tile >> j) & 1ull) << P.tpos[j];
+        {
+            uint64_t b2 = 0;
+            for (uint32_t r = 0; r < P.n_tile_runs; ++r)
+                b2 |= ((tile >> (P.tile_shift[r] & 0xffu)) & P.tile_mask[r]) << (P.tile_shift[r] >> 8);
+            if (b2 != base) return 25;
+        }
         auto gidx = [&](int t, int s) {
             uint64_t g = 0;
             for (int j = 0; j < nthr; ++j) g |= (uint64_t)((t >> j) & 1) << P.spos[j];
@@ -288,5 +349,21 @@ extern "C" int emu_plan_stats(int n, int dtype, const sv_op *ops, size_t n_ops, 
     stats[1] = p.info.n_tile_passes;
     stats[2] = p.info.n_stages;
     stats[3] = p.info.bytes_moved;
+    return 0;
+}
+
+// Plan only, then check the precomputed fields of every tile pass (any size).
+extern "C" int emu_check_fields(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params,
+                                int tile_qubits, int reg_qubits)
+{
+    sv_plan p;
+    p.n = n;
+    p.dtype = dtype;
+    sv_apply_opts o{SV_MODE_FUSED, tile_qubits, reg_qubits, 0};
+    std::string err;
+    int rc = build_plan(&p, ops, n_ops, params, o, err);
+    if (rc != SV_OK) return rc;
+    for (uint32_t pi = 0; pi < p.passes.size(); ++pi)
+        if ((rc = check_pass_fields(p, pi)) != 0) return 100 + rc;
     return 0;
 }

@@ -102,3 +102,17 @@ def test_fused_plan_carleman_ladder(emu, b, rb, elementary):
     got, stats = run_emu(emu, circ, psi0, 1, b, rb)
     assert np.max(np.abs(got - want)) < 1e-12
     assert stats[0] * 3 < len(circ)
+
+
+@pytest.mark.parametrize("dtype,b,rb", [(0, 12, 4), (0, 12, 5), (0, 13, 5), (1, 12, 4), (1, 11, 5)])
+def test_precomputed_pass_fields_at_benchmark_size(emu, dtype, b, rb):
+    """Run maps, swizzle tables and LDS addressing of every pass of the
+    28-qubit benchmark circuit (first 20 layers), checked without emulation."""
+    c = random_layered_circuit(28, 20, seed=0)
+    ops, params = c.arrays()
+    emu.emu_check_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int]
+    emu.emu_check_fields.restype = ctypes.c_int
+    rc = emu.emu_check_fields(28, dtype, ops.ctypes.data, len(ops),
+                              params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), b, rb)
+    assert rc == 0
