@@ -98,6 +98,49 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
     return out
 
 
+def batched_carleman(sv, count=64, d=3, reps=3):
+    """The batched workload: `count` seeded Carleman-LBM instances (21-28 qubits,
+    complex64) at QSVT degree d in one arena, geometry from the autotuner, one
+    graph-captured launch per level; against the same plans run one at a time."""
+    from paper_2606_12770_amd import autotune
+    from paper_2606_12770_amd.circuits import batch_workload, carleman_circuit as cc, qsp
+    cfgs = batch_workload.batch_configs(count)
+    phases = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)[0]
+    encs = [cc.build_ul(cfg) for cfg in cfgs]
+    circs = [cc.build_qsvt(e, phases) for e in encs]
+    states = sv.sv_alloc_batch([c.n for c in circs], sv.SV_C64)
+    (b, rb), tune_ms = autotune.tune_batch(circs, states, sv.SV_C64)
+    log(f"batch autotune: {tune_ms}")
+    plans = []
+    for c in circs:
+        ops, params = c.arrays()
+        plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, b, rb))
+    for st, cfg, e in zip(states, cfgs, encs):
+        sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
+    batch = sv.sv_batch_create(states, plans, True)
+    sv.sv_batch_execute(batch, 1)
+    ms_batch = sv.sv_batch_time(batch, reps) / reps
+    levels, gates = sv.sv_batch_levels(batch)
+    sv.sv_batch_free(batch)
+    ms_seq = 0.0
+    for p, st in zip(plans, states):
+        ms_seq += sv.sv_plan_time(p, st, reps) / reps
+    for p in plans:
+        sv.sv_plan_free(p)
+    for st in states:
+        sv.sv_free(st)
+    qubits = [c.n for c in circs]
+    out = {"instances": count, "degree": d, "qubits_min": min(qubits), "qubits_max": max(qubits),
+           "arena_GiB": sum(8 << q for q in qubits) / 2 ** 30, "gates": gates, "levels": levels,
+           "tile_qubits": b, "reg_qubits": rb, "autotune_ms": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
+           "batched_ms": ms_batch, "batched_gates_per_s": gates / (ms_batch / 1e3),
+           "one_at_a_time_ms": ms_seq, "one_at_a_time_gates_per_s": gates / (ms_seq / 1e3),
+           "speedup": ms_seq / ms_batch}
+    log(f"batch: {out['batched_gates_per_s']:.0f} gates/s batched vs {out['one_at_a_time_gates_per_s']:.0f} "
+        f"one at a time ({out['speedup']:.2f}x), {levels} levels, geometry {b}/{rb}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +237,7 @@ def main():
                 ("plain_c128_elementary", C128, P, True), ("fused_c64_elementary", C64, F, True)]),
             "grid64_31q": carleman_ladder(sv, dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02), 13, [
                 ("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1),
+            "batched_64": batched_carleman(sv),
         }
 
     cpu = None

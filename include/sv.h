@@ -168,6 +168,42 @@ int sv_copy(sv_state *dst, const sv_state *src);
 /* <a|b> = sum conj(a_i) b_i in FP64 (same qubit count; precisions may differ). */
 int sv_inner(const sv_state *a, const sv_state *b, double *re, double *im);
 
+/* ---- batches of independent circuits ---------------------------------------
+ * Many small circuits (for instance Carleman-LBM instances of different grid
+ * sizes, Taylor orders and step counts, hence different qubit counts) run
+ * together: launch k executes the k-th tile pass of every instance, as one
+ * grid over all their tiles, so small states share the device instead of
+ * running one after another. */
+
+/* Allocate `count` states of n_qubits[i] qubits, precision dtype, in one device
+ * arena (each state starts on a 2 MiB boundary), all on one stream (stream, or a
+ * library-created one when NULL), each initialised to |0...0>.  out[i] receives
+ * the states; free each with sv_free (the arena goes with the last one).  On an
+ * error no state is returned and nothing stays allocated. */
+int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_state **out);
+
+typedef struct sv_batch sv_batch;
+
+/* Bind plans[i] to states[i] for i < count.  Every plan must be fused (tile
+ * passes only), with one tile geometry and precision across the batch; the
+ * states must share a stream and be distinct.  use_graph != 0 captures the level
+ * launches in a HIP graph on first execution and replays it afterwards.  The
+ * batch keeps pointers to the plans' device tables and the states' memory: free
+ * the batch before them. */
+int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph, sv_batch **out);
+
+/* Run every instance's plan `repeat` times; returns when the work is done. */
+int sv_batch_execute(sv_batch *b, int repeat);
+
+/* As sv_batch_execute, bracketed by HIP events (graph capture, if any, happens
+ * before the timed region); *ms is the device time of all repeats. */
+int sv_batch_time(sv_batch *b, int repeat, double *ms);
+
+/* Number of launch levels and total IR ops of one execution. */
+int sv_batch_levels(const sv_batch *b, uint64_t *levels, uint64_t *gates);
+
+int sv_batch_free(sv_batch *b);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 const char *sv_strerror(int code);
 const char *sv_last_error(void);

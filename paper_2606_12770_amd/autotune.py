@@ -1,0 +1,85 @@
+"""Autotuner for the fused tile geometry (resident qubits b, register qubits RB).
+
+The candidates are planned through the C ABI and timed on the device with HIP
+events (sv_plan_time / sv_batch_time) on the caller's states, whose contents
+the timing runs overwrite: tune before loading the real input.  The fastest
+geometry is cached per (circuit digest, qubits, precision), so repeated
+circuits (the QSVT ladder of a configuration, the same batch) are tuned once
+per process.
+"""
+from __future__ import annotations
+
+import hashlib
+
+from . import sv
+
+CANDIDATES = ((12, 4), (11, 4), (10, 4), (12, 5), (13, 5))
+
+_cache: dict = {}
+
+
+def circuit_digest(circuits) -> str:
+    h = hashlib.sha1()
+    for c in circuits:
+        ops, params = c.arrays()
+        h.update(str(c.n).encode())
+        h.update(ops.tobytes())
+        h.update(params.tobytes())
+    return h.hexdigest()
+
+
+def _valid(n, b, rb):
+    return b <= n and 6 <= b - rb <= 8
+
+
+def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1):
+    """Fastest (b, rb) for one circuit on one state; returns ((b, rb), {geometry: ms})."""
+    key = ("plan", circuit_digest([circuit]), circuit.n, dtype)
+    if key in _cache:
+        return _cache[key]
+    ops, params = circuit.arrays()
+    times = {}
+    for b, rb in candidates:
+        if not _valid(circuit.n, b, rb):
+            continue
+        p = sv.sv_plan_create(circuit.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb)
+        try:
+            sv.sv_plan_execute(p, state, 1)
+            times[(b, rb)] = sv.sv_plan_time(p, state, repeat) / repeat
+        finally:
+            sv.sv_plan_free(p)
+    best = min(times, key=times.get)
+    _cache[key] = (best, times)
+    return _cache[key]
+
+
+def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_graph=True):
+    """Fastest common (b, rb) for a batch; returns ((b, rb), {geometry: ms})."""
+    key = ("batch", circuit_digest(circuits), dtype)
+    if key in _cache:
+        return _cache[key]
+    arrays = [c.arrays() for c in circuits]
+    nmin = min(c.n for c in circuits)
+    times = {}
+    for b, rb in candidates:
+        if not _valid(nmin, b, rb):
+            continue
+        plans = [sv.sv_plan_create(c.n, dtype, o, p, sv.SV_MODE_FUSED, b, rb)
+                 for c, (o, p) in zip(circuits, arrays)]
+        batch = None
+        try:
+            batch = sv.sv_batch_create(states, plans, use_graph)
+            sv.sv_batch_execute(batch, 1)
+            times[(b, rb)] = sv.sv_batch_time(batch, repeat) / repeat
+        except sv.SVError:
+            pass  # a geometry some instance cannot use (e.g. a per-gate step)
+        finally:
+            if batch is not None:
+                sv.sv_batch_free(batch)
+            for p in plans:
+                sv.sv_plan_free(p)
+    if not times:
+        raise RuntimeError("no candidate geometry fits every instance of the batch")
+    best = min(times, key=times.get)
+    _cache[key] = (best, times)
+    return _cache[key]

@@ -130,23 +130,24 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
         SV_SLOT_DISPATCH1(FN, false, __VA_ARGS__)                       \
     }
 
+// One tile of one pass: load, register stages with LDS exchanges, store.
+// The caller passes the tile counter; every thread of the workgroup calls this.
 template <typename R, int RB>
-__global__ void __launch_bounds__(256)
-k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
-            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
+__device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
+                                               const TilePass *__restrict__ pass,
+                                               const TileStage *__restrict__ stages,
+                                               const TileOp *__restrict__ ops, const R *__restrict__ prm,
+                                               uint64_t tile, typename CTT<R>::T *lds)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int LOWB = CTT<R>::LOWB;
     constexpr uint32_t kAllSlots = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
-    extern __shared__ unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t nthr = pass->nthr;
 
     // absolute index bits of this tile (uniform): bit runs of the tile counter
-    const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
     uint64_t base = 0;
     for (uint32_t r = 0; r < pass->n_tile_runs; ++r) {
         const uint32_t sh = pass->tile_shift[r];
@@ -275,6 +276,39 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 }
 
 template <typename R, int RB>
+__global__ void __launch_bounds__(256)
+k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
+            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
+{
+    using C = typename CTT<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
+}
+
+// Batched tile passes: one launch runs pass `level` of every instance of a
+// batch.  Work items are (instance, tile) pairs laid end to end by the prefix
+// sums item_begin[]; each workgroup strides over them (the grid is sized for
+// the device, not for the work), so instances of very different sizes share
+// one launch.  Instances of a launch share the geometry (b, RB) and precision.
+template <typename R, int RB>
+__global__ void __launch_bounds__(256)
+k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total_work)
+{
+    using C = typename CTT<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    uint32_t it = 0;
+    for (uint64_t w = blockIdx.x; w < total_work; w += gridDim.x) {
+        while (it + 1 < n_items && items[it + 1].item_begin <= w) ++it;  // w only grows
+        const BatchItem &B = items[it];
+        tile_pass_body<R, RB>(reinterpret_cast<C *>(B.psi), B.pass, B.stages, B.ops,
+                              reinterpret_cast<const R *>(B.prm), w - B.item_begin, lds);
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
+template <typename R, int RB>
 static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 {
     using C = typename CTT<R>::T;
@@ -289,6 +323,31 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
                        (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
                        (const TileOp *)p->d_tops, (const R *)p->d_tparams);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+template <typename R, int RB>
+static int launch_batch_t(int b, int nthr, const BatchItem *d_items, uint32_t n_items, uint64_t total,
+                          hipStream_t st)
+{
+    using C = typename CTT<R>::T;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t cap = (uint64_t)cus * 8;
+    const uint32_t grid = (uint32_t)(total < cap ? total : cap);
+    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(grid), dim3(1u << nthr), sizeof(C) << b, st, d_items, n_items,
+                       total);
+    return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+int launch_tile_batch(int dtype, int rb, int b, int nthr, const BatchItem *d_items, uint32_t n_items,
+                      uint64_t total_work, hipStream_t st)
+{
+    if (!n_items || !total_work) return SV_OK;
+    if (dtype == SV_C64)
+        return rb == 5 ? launch_batch_t<float, 5>(b, nthr, d_items, n_items, total_work, st)
+                       : launch_batch_t<float, 4>(b, nthr, d_items, n_items, total_work, st);
+    return rb == 5 ? launch_batch_t<double, 5>(b, nthr, d_items, n_items, total_work, st)
+                   : launch_batch_t<double, 4>(b, nthr, d_items, n_items, total_work, st);
 }
 
 int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
@@ -307,6 +366,10 @@ int tile_kernel_setup()
     (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipGetLastError();
     return SV_OK;
 }

@@ -143,6 +143,18 @@ struct Step {
     uint32_t index;
 };
 
+// One instance of a batched launch: its state, the tile pass it runs at this
+// level (device pointers into its plan) and the first work index it owns.
+struct BatchItem {
+    void *psi;
+    const TilePass *pass;
+    const TileStage *stages;
+    const TileOp *ops;
+    const void *prm;
+    uint64_t item_begin;
+};
+static_assert(sizeof(BatchItem) == 48, "BatchItem layout");
+
 }  // namespace svi
 
 

@@ -1,6 +1,7 @@
 // C ABI of libsv: argument validation, state and plan lifetime, execution.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -8,12 +9,35 @@
 #include <new>
 #include <set>
 #include <string>
+#include <vector>
 
 #include "sv_internal.h"
 
 namespace svi {
 int tile_kernel_setup();
-}
+
+struct Arena {
+    void *d_mem = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int refs = 0;
+};
+}  // namespace svi
+
+struct sv_batch {
+    int dtype = SV_C64;
+    int b = 0, rb = 0, nthr = 0;
+    hipStream_t stream = nullptr;
+    std::vector<uint32_t> n_items;      // per level
+    std::vector<uint64_t> total;        // per level
+    std::vector<svi::BatchItem *> d_items;
+    std::vector<sv_state *> states;
+    bool use_graph = false;
+    bool graph_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t gates = 0;
+};
 
 namespace {
 
@@ -252,9 +276,18 @@ int sv_free(sv_state *s)
     if (!s) return SV_OK;
     StateExt *e = ext(s);
     (void)hipStreamSynchronize(s->stream);
-    if (s->d_psi) (void)hipFree(s->d_psi);
+    if (s->arena) {
+        svi::Arena *a = s->arena;
+        if (--a->refs == 0) {
+            (void)hipFree(a->d_mem);
+            if (a->own_stream) (void)hipStreamDestroy(a->stream);
+            delete a;
+        }
+    } else {
+        if (s->d_psi) (void)hipFree(s->d_psi);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    }
     if (e->scratch.d_partial) (void)hipFree(e->scratch.d_partial);
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete e;
     return SV_OK;
 }
@@ -469,6 +502,243 @@ int sv_inner(const sv_state *a, const sv_state *b, double *re, double *im)
     HIP_TRY(hipStreamSynchronize(a->stream));
     if (re) *re = v[0];
     if (im) *im = v[1];
+    return SV_OK;
+}
+
+
+int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_state **out)
+{
+    if (count < 1 || !n_qubits || !out) return fail(SV_EINVAL, "count < 1 or NULL argument");
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "dtype must be SV_C64 or SV_C128");
+    for (int i = 0; i < count; ++i) {
+        out[i] = nullptr;
+        if (n_qubits[i] < 1 || n_qubits[i] > 36) return fail(SV_EINVAL, "n_qubits must be in [1, 36]");
+    }
+    const uint64_t align = 2ull << 20;  // 2 MiB: states start on large-page boundaries
+    std::vector<uint64_t> off(count);
+    uint64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        off[i] = total;
+        const uint64_t bytes = (uint64_t)esize(dtype) << n_qubits[i];
+        total += (bytes + align - 1) / align * align;
+    }
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (total + (64ull << 20) + (uint64_t)count * sizeof(double) * (2 * svi::kReduceBlocks + 2) > free_b)
+        return fail(SV_ENOMEM, "the batch does not fit in free device memory");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int rc = ensure_device_setup(dev);
+    if (rc != SV_OK) return rc;
+    svi::Arena *a = new (std::nothrow) svi::Arena();
+    if (!a) return fail(SV_ENOMEM, "host allocation failed");
+    if (hipMalloc(&a->d_mem, total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete a;
+        return fail(SV_ENOMEM, "hipMalloc of the arena failed");
+    }
+    if (stream) {
+        a->stream = (hipStream_t)stream;
+    } else if (hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(a->d_mem);
+        delete a;
+        return fail(SV_EDEVICE, "hipStreamCreateWithFlags failed");
+    } else {
+        a->own_stream = true;
+    }
+    for (int i = 0; i < count; ++i) {
+        StateExt *e = new (std::nothrow) StateExt();
+        if (e && hipMalloc((void **)&e->scratch.d_partial, sizeof(double) * (2 * svi::kReduceBlocks + 2)) != hipSuccess) {
+            delete e;
+            e = nullptr;
+        }
+        if (!e) {
+            if (i == 0) {  // no state holds the arena yet
+                (void)hipFree(a->d_mem);
+                if (a->own_stream) (void)hipStreamDestroy(a->stream);
+                delete a;
+            } else {       // the last sv_free releases the arena
+                for (int j = 0; j < i; ++j) {
+                    sv_free(out[j]);
+                    out[j] = nullptr;
+                }
+            }
+            return fail(SV_ENOMEM, "allocation of a batch state failed");
+        }
+        e->s.n = n_qubits[i];
+        e->s.dtype = dtype;
+        e->s.device = dev;
+        e->s.d_psi = (char *)a->d_mem + off[i];
+        e->s.stream = a->stream;
+        e->s.arena = a;
+        a->refs += 1;
+        out[i] = &e->s;
+        rc = svi::launch_init_basis(e->s.d_psi, e->s.n, dtype, a->stream);
+        if (rc != SV_OK) {
+            for (int j = 0; j <= i; ++j) {
+                sv_free(out[j]);
+                out[j] = nullptr;
+            }
+            return fail(rc, "state initialisation failed");
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(a->stream));
+    return SV_OK;
+}
+
+int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph, sv_batch **out)
+{
+    if (!states || !plans || !out || count == 0) return fail(SV_EINVAL, "NULL argument or empty batch");
+    *out = nullptr;
+    const sv_plan *p0 = plans[0];
+    size_t levels = 0;
+    for (size_t i = 0; i < count; ++i) {
+        int rc = check_plan_state(plans[i], states[i]);
+        if (rc != SV_OK) return rc;
+        const sv_plan *p = plans[i];
+        if (p->b == 0 || p->b != p0->b || p->rb != p0->rb || p->dtype != p0->dtype)
+            return fail(SV_EINVAL, "batched plans must be fused with one tile geometry and one precision");
+        for (const auto &st : p->steps)
+            if (st.type != 1) return fail(SV_EUNSUPPORTED, "batched plans must consist of tile passes only");
+        if (states[i]->stream != states[0]->stream) return fail(SV_EINVAL, "batched states must share a stream");
+        for (size_t j = 0; j < i; ++j)
+            if (states[j] == states[i]) return fail(SV_EINVAL, "a state appears twice in the batch");
+        levels = std::max(levels, p->steps.size());
+    }
+    sv_batch *B = new (std::nothrow) sv_batch();
+    if (!B) return fail(SV_ENOMEM, "host allocation failed");
+    B->dtype = p0->dtype;
+    B->b = p0->b;
+    B->rb = p0->rb;
+    B->nthr = p0->b - p0->rb;
+    B->stream = states[0]->stream;
+    B->use_graph = use_graph != 0;
+    B->states.assign(states, states + count);
+    for (size_t i = 0; i < count; ++i) B->gates += plans[i]->info.n_ops;
+    auto cleanup = [&]() {
+        for (auto *d : B->d_items) (void)hipFree(d);
+        delete B;
+    };
+    for (size_t lv = 0; lv < levels; ++lv) {
+        std::vector<svi::BatchItem> items;
+        uint64_t total = 0;
+        for (size_t i = 0; i < count; ++i) {
+            const sv_plan *p = plans[i];
+            if (lv >= p->steps.size()) continue;
+            const uint32_t pi = p->steps[lv].index;
+            svi::BatchItem it{};
+            it.psi = states[i]->d_psi;
+            it.pass = (const svi::TilePass *)p->d_passes + pi;
+            it.stages = (const svi::TileStage *)p->d_stages;
+            it.ops = (const svi::TileOp *)p->d_tops;
+            it.prm = p->d_tparams;
+            it.item_begin = total;
+            total += 1ull << p->passes[pi].ntile;
+            items.push_back(it);
+        }
+        svi::BatchItem *d = nullptr;
+        if (hipMalloc((void **)&d, items.size() * sizeof(svi::BatchItem)) != hipSuccess ||
+            hipMemcpy(d, items.data(), items.size() * sizeof(svi::BatchItem), hipMemcpyHostToDevice) != hipSuccess) {
+            if (d) (void)hipFree(d);
+            cleanup();
+            return fail(SV_ENOMEM, "upload of the batch tables failed");
+        }
+        B->d_items.push_back(d);
+        B->n_items.push_back((uint32_t)items.size());
+        B->total.push_back(total);
+    }
+    *out = B;
+    return SV_OK;
+}
+
+namespace {
+int batch_launch_all(sv_batch *B)
+{
+    for (size_t lv = 0; lv < B->d_items.size(); ++lv) {
+        int rc = svi::launch_tile_batch(B->dtype, B->rb, B->b, B->nthr, B->d_items[lv], B->n_items[lv], B->total[lv],
+                                        B->stream);
+        if (rc != SV_OK) return fail(rc, "batched launch failed");
+    }
+    return SV_OK;
+}
+
+int batch_run_once(sv_batch *B)
+{
+    if (!B->use_graph) return batch_launch_all(B);
+    if (!B->graph_ready) {
+        HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        int rc = batch_launch_all(B);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(B->stream, &g);
+        if (rc != SV_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        B->graph = g;
+        B->graph_ready = true;
+    }
+    HIP_TRY(hipGraphLaunch(B->exec, B->stream));
+    return SV_OK;
+}
+}  // namespace
+
+int sv_batch_execute(sv_batch *B, int repeat)
+{
+    if (!B || repeat < 0) return fail(SV_EINVAL, "NULL batch or repeat < 0");
+    for (int r = 0; r < repeat; ++r) {
+        int rc = batch_run_once(B);
+        if (rc != SV_OK) return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    return SV_OK;
+}
+
+int sv_batch_time(sv_batch *B, int repeat, double *ms)
+{
+    if (!B || !ms || repeat < 1) return fail(SV_EINVAL, "NULL argument or repeat < 1");
+    if (B->use_graph && !B->graph_ready) {  // capture outside the timed region
+        int rc = batch_run_once(B);
+        if (rc != SV_OK) return rc;
+        HIP_TRY(hipStreamSynchronize(B->stream));
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, B->stream));
+    int rc = SV_OK;
+    for (int r = 0; r < repeat && rc == SV_OK; ++r) rc = batch_run_once(B);
+    HIP_TRY(hipEventRecord(e1, B->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = f;
+    return rc;
+}
+
+int sv_batch_levels(const sv_batch *B, uint64_t *levels, uint64_t *gates)
+{
+    if (!B) return fail(SV_EINVAL, "NULL batch");
+    if (levels) *levels = B->d_items.size();
+    if (gates) *gates = B->gates;
+    return SV_OK;
+}
+
+int sv_batch_free(sv_batch *B)
+{
+    if (!B) return SV_OK;
+    (void)hipStreamSynchronize(B->stream);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (auto *d : B->d_items) (void)hipFree(d);
+    delete B;
     return SV_OK;
 }
 

@@ -5,6 +5,10 @@
 
 #include "plan_types.h"
 
+namespace svi {
+struct Arena;  // shared device allocation of states made by sv_alloc_batch
+}
+
 struct sv_state {
     int n = 0;
     int dtype = SV_C64;
@@ -12,6 +16,7 @@ struct sv_state {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
+    svi::Arena *arena = nullptr;  // non-null: d_psi lives in an arena, freed with its last state
 };
 
 namespace svi {
@@ -33,5 +38,9 @@ int launch_inner(const void *a, int dta, const void *b, int dtb, int n, double *
 int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t stream);
 
 constexpr int kReduceBlocks = 2048;
+
+// batched tile passes: items of one level, on `stream`
+int launch_tile_batch(int dtype, int rb, int b, int nthr, const BatchItem *d_items, uint32_t n_items,
+                      uint64_t total_work, hipStream_t stream);
 
 }  // namespace svi

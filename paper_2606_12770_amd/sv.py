@@ -24,6 +24,7 @@ EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
     "sv_plan_get_info", "sv_plan_execute", "sv_plan_execute_seq", "sv_plan_time", "sv_postselect",
     "sv_amplitudes", "sv_set_amplitudes", "sv_copy", "sv_inner", "sv_strerror", "sv_last_error",
+    "sv_alloc_batch", "sv_batch_create", "sv_batch_execute", "sv_batch_time", "sv_batch_levels", "sv_batch_free",
 ]
 
 
@@ -74,6 +75,12 @@ def load_library(path: str = LIB_PATH):
         "sv_set_amplitudes": [vp, ctypes.c_uint64, ctypes.c_uint64, dp],
         "sv_copy": [vp, vp],
         "sv_inner": [vp, vp, dp, dp],
+        "sv_alloc_batch": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, vp, pvp],
+        "sv_batch_create": [pvp, pvp, ctypes.c_size_t, ctypes.c_int, pvp],
+        "sv_batch_execute": [vp, ctypes.c_int],
+        "sv_batch_time": [vp, ctypes.c_int, dp],
+        "sv_batch_levels": [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+        "sv_batch_free": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -201,6 +208,46 @@ def sv_inner(a, b) -> complex:
     re, im = ctypes.c_double(), ctypes.c_double()
     _check(load_library().sv_inner(a, b, ctypes.byref(re), ctypes.byref(im)))
     return complex(re.value, im.value)
+
+
+def sv_alloc_batch(n_qubits, dtype: int = SV_C64, stream=None):
+    """States of the given qubit counts in one device arena; returns their handles."""
+    n = len(n_qubits)
+    arr = (ctypes.c_int * n)(*[int(q) for q in n_qubits])
+    out = (ctypes.c_void_p * n)()
+    _check(load_library().sv_alloc_batch(n, arr, dtype, stream, out))
+    return [ctypes.c_void_p(out[i]) for i in range(n)]
+
+
+def sv_batch_create(states, plans, use_graph: bool = True):
+    n = len(states)
+    if len(plans) != n:
+        raise ValueError("one plan per state")
+    sa = (ctypes.c_void_p * n)(*[s.value for s in states])
+    pa = (ctypes.c_void_p * n)(*[p.value for p in plans])
+    out = ctypes.c_void_p()
+    _check(load_library().sv_batch_create(sa, pa, n, int(use_graph), ctypes.byref(out)))
+    return out
+
+
+def sv_batch_execute(batch, repeat: int = 1):
+    _check(load_library().sv_batch_execute(batch, repeat))
+
+
+def sv_batch_time(batch, repeat: int = 1) -> float:
+    ms = ctypes.c_double()
+    _check(load_library().sv_batch_time(batch, repeat, ctypes.byref(ms)))
+    return ms.value
+
+
+def sv_batch_levels(batch):
+    lv, g = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().sv_batch_levels(batch, ctypes.byref(lv), ctypes.byref(g)))
+    return lv.value, g.value
+
+
+def sv_batch_free(batch):
+    _check(load_library().sv_batch_free(batch))
 
 
 def sv_strerror(code: int) -> str:

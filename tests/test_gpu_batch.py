@@ -1,0 +1,153 @@
+"""Batched execution of independent circuits of uneven size.
+
+* One launch per level over the tiles of every instance must give exactly the
+  states that running each plan on its own gives (same tile code, same
+  arithmetic: bit-identical), with and without HIP-graph capture.
+* Small Carleman-LBM instances in a batch against the FP64 reference simulator.
+* Graph replays, with the program's own eager work between them, match the
+  eager result after every replay.
+* Invalid batches are refused on the host.
+"""
+import numpy as np
+import pytest
+
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+from paper_2606_12770_amd.circuits import qsp
+from paper_2606_12770_amd.circuits.random_circuit import random_layered_circuit, random_mixed_circuit, random_state
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _plans(sv, circs, dtype, b=12, rb=4):
+    out = []
+    for c in circs:
+        ops, params = c.arrays()
+        out.append(sv.sv_plan_create(c.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb))
+    return out
+
+
+def _mixed_batch(seed):
+    rng = np.random.default_rng(seed)
+    ns = [14, 17, 20, 15, 18, 21, 16]
+    circs = [random_mixed_circuit(n, 150, seed=int(rng.integers(1 << 30)), max_ctrl=4) for n in ns]
+    circs[3] = random_layered_circuit(15, 6, seed=2)
+    inits = [random_state(n, 100 + i) for i, n in enumerate(ns)]
+    return circs, inits
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_one_at_a_time(dtype, use_graph):
+    sv = require_gpu()
+    circs, inits = _mixed_batch(dtype)
+    plans = _plans(sv, circs, dtype)
+    states = sv.sv_alloc_batch([c.n for c in circs], dtype)
+    for st, v in zip(states, inits):
+        sv.sv_set_amplitudes(st, v, 0)
+    batch = sv.sv_batch_create(states, plans, use_graph)
+    sv.sv_batch_execute(batch, 2)
+    got = [sv.sv_amplitudes(st) for st in states]
+    for i, (c, v, p) in enumerate(zip(circs, inits, plans)):
+        ref = sv.sv_alloc(c.n, dtype, v)
+        sv.sv_plan_execute(p, ref, 2)
+        want = sv.sv_amplitudes(ref)
+        sv.sv_free(ref)
+        print(f"instance {i}: n={c.n} dtype={dtype} graph={use_graph} maxabs={np.max(np.abs(got[i] - want)):.1e}",
+              flush=True)
+        assert np.array_equal(got[i], want)
+        if c.n <= 17:
+            oracle = osv.run(c, osv.run(c, v))
+            tol = 1e-12 if dtype == 1 else 1e-5
+            assert np.max(np.abs(got[i] - oracle)) < tol
+    levels, gates = sv.sv_batch_levels(batch)
+    assert gates == sum(len(c) for c in circs)
+    assert levels == max(sv.sv_plan_get_info(p)["n_launches"] for p in plans)
+    sv.sv_batch_free(batch)
+    for st in states:
+        sv.sv_free(st)
+    for p in plans:
+        sv.sv_plan_free(p)
+
+
+def test_batch_of_carleman_ladders_matches_oracle():
+    sv = require_gpu()
+    cfgs = [cc.CarlemanConfig(nx=2, tau=0.9, nk=1, nt=1, amp=0.1),
+            cc.CarlemanConfig(nx=2, tau=0.7, nk=2, nt=2, amp=0.05),
+            cc.CarlemanConfig(nx=4, tau=1.1, nk=1, nt=1, amp=0.08, wavenumber=2)]
+    phases = qsp.inversion_phases(2.0, 5)[0]
+    circs, inits = [], []
+    for cfg in cfgs:
+        enc = cc.build_ul(cfg)
+        circs.append(cc.build_qsvt(enc, phases))
+        v = np.zeros(1 << enc.layout.n, dtype=np.complex128)
+        v[: 1 << enc.layout.n_x] = cc.rhs_x_block(cfg, enc.layout)
+        inits.append(v)
+    plans = _plans(sv, circs, 1)
+    states = sv.sv_alloc_batch([c.n for c in circs], 1)
+    for st, v in zip(states, inits):
+        sv.sv_set_amplitudes(st, v, 0)
+    batch = sv.sv_batch_create(states, plans, True)
+    sv.sv_batch_execute(batch, 1)
+    for c, v, st in zip(circs, inits, states):
+        got = sv.sv_amplitudes(st)
+        want = osv.run(c, v)
+        print(f"carleman batch n={c.n}: maxabs {np.max(np.abs(got - want)):.1e}", flush=True)
+        assert np.max(np.abs(got - want)) < 1e-12
+    sv.sv_batch_free(batch)
+    for st in states:
+        sv.sv_free(st)
+    for p in plans:
+        sv.sv_plan_free(p)
+
+
+def test_graph_replays_match_eager_with_work_between():
+    sv = require_gpu()
+    circs, inits = _mixed_batch(5)
+    plans = _plans(sv, circs, 0)
+    g_states = sv.sv_alloc_batch([c.n for c in circs], 0)
+    e_states = sv.sv_alloc_batch([c.n for c in circs], 0)
+    for a, b_, v in zip(g_states, e_states, inits):
+        sv.sv_set_amplitudes(a, v, 0)
+        sv.sv_set_amplitudes(b_, v, 0)
+    gb = sv.sv_batch_create(g_states, plans, True)
+    eb = sv.sv_batch_create(e_states, plans, False)
+    for replay in range(4):
+        sv.sv_batch_execute(gb, 1)
+        sv.sv_batch_execute(eb, 1)
+        for a, b_ in zip(g_states, e_states):
+            # eager work of the program between replays: FP64 reductions, read-out
+            na = sv.sv_postselect(a, 0, 0, keep=False, renormalize=False)
+            nb = sv.sv_postselect(b_, 0, 0, keep=False, renormalize=False)
+            assert na == nb
+            assert np.array_equal(sv.sv_amplitudes(a), sv.sv_amplitudes(b_)), f"replay {replay} differs"
+    sv.sv_batch_free(gb)
+    sv.sv_batch_free(eb)
+    for st in g_states + e_states:
+        sv.sv_free(st)
+    for p in plans:
+        sv.sv_plan_free(p)
+
+
+def test_invalid_batches_are_refused():
+    sv = require_gpu()
+    c1 = random_mixed_circuit(14, 50, seed=1)
+    c2 = random_mixed_circuit(15, 50, seed=2)
+    o1, p1 = c1.arrays()
+    o2, p2 = c2.arrays()
+    pa = sv.sv_plan_create(14, 0, o1, p1, sv.SV_MODE_FUSED, 12, 4)
+    pb = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 11, 4)   # other geometry
+    pc = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_PLAIN)           # per-gate steps
+    st = sv.sv_alloc_batch([14, 15], 0)
+    for plans, code in (([pa, pb], sv.SV_EINVAL), ([pa, pc], sv.SV_EINVAL)):
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_batch_create(st, plans, False)
+        assert e.value.code == code
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_batch_create([st[0], st[0]], [pa, pa], False)
+    assert e.value.code == sv.SV_EINVAL
+    for s in st:
+        sv.sv_free(s)
+    for p in (pa, pb, pc):
+        sv.sv_plan_free(p)
