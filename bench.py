@@ -117,11 +117,15 @@ def batched_carleman(sv, count=64, d=3, reps=3):
         plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, b, rb))
     for st, cfg, e in zip(states, cfgs, encs):
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
-    batch = sv.sv_batch_create(states, plans, True)
+    batch = sv.sv_batch_create(states, plans, True, 0)
     sv.sv_batch_execute(batch, 1)
     ms_batch = sv.sv_batch_time(batch, reps) / reps
-    levels, gates = sv.sv_batch_levels(batch)
+    levels, groups, gates = sv.sv_batch_levels(batch)
     sv.sv_batch_free(batch)
+    one = sv.sv_batch_create(states, plans, True, (1 << 64) - 1)   # all instances level by level
+    sv.sv_batch_execute(one, 1)
+    ms_one_group = sv.sv_batch_time(one, reps) / reps
+    sv.sv_batch_free(one)
     ms_seq = 0.0
     for p, st in zip(plans, states):
         ms_seq += sv.sv_plan_time(p, st, reps) / reps
@@ -131,13 +135,15 @@ def batched_carleman(sv, count=64, d=3, reps=3):
         sv.sv_free(st)
     qubits = [c.n for c in circs]
     out = {"instances": count, "degree": d, "qubits_min": min(qubits), "qubits_max": max(qubits),
-           "arena_GiB": sum(8 << q for q in qubits) / 2 ** 30, "gates": gates, "levels": levels,
+           "arena_GiB": sum(8 << q for q in qubits) / 2 ** 30, "gates": gates, "launches": levels,
+           "groups": groups, "single_group_ms": ms_one_group,
            "tile_qubits": b, "reg_qubits": rb, "autotune_ms": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
            "batched_ms": ms_batch, "batched_gates_per_s": gates / (ms_batch / 1e3),
            "one_at_a_time_ms": ms_seq, "one_at_a_time_gates_per_s": gates / (ms_seq / 1e3),
            "speedup": ms_seq / ms_batch}
     log(f"batch: {out['batched_gates_per_s']:.0f} gates/s batched vs {out['one_at_a_time_gates_per_s']:.0f} "
-        f"one at a time ({out['speedup']:.2f}x), {levels} levels, geometry {b}/{rb}")
+        f"one at a time ({out['speedup']:.2f}x), {levels} launches in {groups} groups, geometry {b}/{rb}; "
+        f"single level-synchronous group {ms_one_group:.1f} ms")
     return out
 
 

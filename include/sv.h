@@ -186,11 +186,15 @@ typedef struct sv_batch sv_batch;
 
 /* Bind plans[i] to states[i] for i < count.  Every plan must be fused (tile
  * passes only), with one tile geometry and precision across the batch; the
- * states must share a stream and be distinct.  use_graph != 0 captures the level
- * launches in a HIP graph on first execution and replays it afterwards.  The
- * batch keeps pointers to the plans' device tables and the states' memory: free
- * the batch before them. */
-int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph, sv_batch **out);
+ * states must share a stream and be distinct.  Instances, ordered by size, are
+ * packed into groups of at most group_bytes of state (0: 192 MiB, about what
+ * the last-level cache holds; UINT64_MAX: one group); a group runs level by
+ * level, each level one launch over the tiles of all its instances.
+ * use_graph != 0 captures all launches in a HIP graph on first execution and
+ * replays it afterwards.  The batch keeps pointers to the plans' device tables
+ * and the states' memory: free the batch before them. */
+int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
+                    uint64_t group_bytes, sv_batch **out);
 
 /* Run every instance's plan `repeat` times; returns when the work is done. */
 int sv_batch_execute(sv_batch *b, int repeat);
@@ -199,8 +203,8 @@ int sv_batch_execute(sv_batch *b, int repeat);
  * before the timed region); *ms is the device time of all repeats. */
 int sv_batch_time(sv_batch *b, int repeat, double *ms);
 
-/* Number of launch levels and total IR ops of one execution. */
-int sv_batch_levels(const sv_batch *b, uint64_t *levels, uint64_t *gates);
+/* Launches and groups of one execution, and the total IR ops it applies. */
+int sv_batch_levels(const sv_batch *b, uint64_t *launches, uint64_t *groups, uint64_t *gates);
 
 int sv_batch_free(sv_batch *b);
 

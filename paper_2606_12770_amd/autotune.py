@@ -68,7 +68,7 @@ def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_gra
                  for c, (o, p) in zip(circuits, arrays)]
         batch = None
         try:
-            batch = sv.sv_batch_create(states, plans, use_graph)
+            batch = sv.sv_batch_create(states, plans, use_graph, 0)
             sv.sv_batch_execute(batch, 1)
             times[(b, rb)] = sv.sv_batch_time(batch, repeat) / repeat
         except sv.SVError:

@@ -287,25 +287,26 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
-// batch.  Work items are (instance, tile) pairs laid end to end by the prefix
-// sums item_begin[]; each workgroup strides over them (the grid is sized for
-// the device, not for the work), so instances of very different sizes share
-// one launch.  Instances of a launch share the geometry (b, RB) and precision.
+// group.  Work items are (instance, tile) pairs laid end to end by the prefix
+// sums item_begin[]; workgroup w finds its instance by binary search and runs
+// that tile, so instances of very different sizes share one launch.  Instances
+// of a launch share the geometry (b, RB) and precision.
 template <typename R, int RB>
 __global__ void __launch_bounds__(256)
-k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total_work)
+k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total)
 {
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
-    uint32_t it = 0;
-    for (uint64_t w = blockIdx.x; w < total_work; w += gridDim.x) {
-        while (it + 1 < n_items && items[it + 1].item_begin <= w) ++it;  // w only grows
-        const BatchItem &B = items[it];
-        tile_pass_body<R, RB>(reinterpret_cast<C *>(B.psi), B.pass, B.stages, B.ops,
-                              reinterpret_cast<const R *>(B.prm), w - B.item_begin, lds);
-        __syncthreads();  // the next tile reuses the LDS
+    const uint64_t w = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    if (w >= total) return;  // padding of the last grid row: the whole workgroup leaves together
+    uint32_t lo = 0, hi = n_items;  // last item with item_begin <= w
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
+    const BatchItem &B = items[lo];
+    tile_pass_body<R, RB>(reinterpret_cast<C *>(B.psi), B.pass, B.stages, B.ops, reinterpret_cast<const R *>(B.prm),
+                          w - B.item_begin, reinterpret_cast<C *>(smem_raw));
 }
 
 template <typename R, int RB>
@@ -330,12 +331,11 @@ static int launch_batch_t(int b, int nthr, const BatchItem *d_items, uint32_t n_
                           hipStream_t st)
 {
     using C = typename CTT<R>::T;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t cap = (uint64_t)cus * 8;
-    const uint32_t grid = (uint32_t)(total < cap ? total : cap);
-    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(grid), dim3(1u << nthr), sizeof(C) << b, st, d_items, n_items,
-                       total);
+    const uint32_t gx = total > 65536 ? 65536u : (uint32_t)total;
+    const uint64_t gy = (total + gx - 1) / gx;
+    if (gy > 65535) return SV_EUNSUPPORTED;
+    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << nthr), sizeof(C) << b, st, d_items,
+                       n_items, total);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 

@@ -132,6 +132,48 @@ struct PassBuild {
     std::vector<uint32_t> ops;
 };
 
+uint64_t touched_qubits(const OpInfo &o) { return o.z | o.x | o.g | (1ull << o.target); }
+
+// Fold an uncontrolled single-qubit matrix into the previous op on its qubit
+// when that op is also an uncontrolled single-qubit matrix on it: no op in
+// between touches the qubit, so the later gate commutes back to the earlier
+// one and the two become one matrix (later x earlier).
+std::vector<OpInfo> fold_single_qubit_runs(const std::vector<OpInfo> &in)
+{
+    std::vector<OpInfo> out;
+    out.reserve(in.size());
+    long last[64];
+    for (long &v : last) v = -1;
+    for (const OpInfo &o : in) {
+        if (o.kind == SV_OP_U && o.mask == 0) {
+            const long j = last[o.target];
+            if (j >= 0 && out[j].kind == SV_OP_U && out[j].mask == 0 && out[j].target == o.target) {
+                const double *a = o.m, *b = out[j].m;  // new = a . b (complex 2x2, row-major re/im pairs)
+                double r[8];
+                for (int i = 0; i < 2; ++i)
+                    for (int k = 0; k < 2; ++k) {
+                        double re = 0.0, im = 0.0;
+                        for (int l = 0; l < 2; ++l) {
+                            const double ar = a[2 * (2 * i + l)], ai = a[2 * (2 * i + l) + 1];
+                            const double br = b[2 * (2 * l + k)], bi = b[2 * (2 * l + k) + 1];
+                            re += ar * br - ai * bi;
+                            im += ar * bi + ai * br;
+                        }
+                        r[2 * (2 * i + k)] = re;
+                        r[2 * (2 * i + k) + 1] = im;
+                    }
+                std::memcpy(out[j].m, r, sizeof r);
+                continue;
+            }
+        }
+        out.push_back(o);
+        const uint64_t t = touched_qubits(o);
+        for (int q = 0; q < 64; ++q)
+            if ((t >> q) & 1ull) last[q] = (long)out.size() - 1;
+    }
+    return out;
+}
+
 }  // namespace
 
 int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params, const sv_apply_opts &opts,
@@ -192,6 +234,11 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->info.n_launches = p->steps.size();
         return SV_OK;
     }
+
+    // single-qubit runs are folded on the host before grouping (fused mode only:
+    // the per-gate path stays one launch per IR op)
+    info = fold_single_qubit_runs(info);
+    n_ops = info.size();
 
     const int nthr = b - rb;
     const int L0 = std::min(nthr, p->dtype == SV_C64 ? 5 : 4);

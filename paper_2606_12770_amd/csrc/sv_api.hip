@@ -37,6 +37,7 @@ struct sv_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t gates = 0;
+    size_t groups = 0;
 };
 
 namespace {
@@ -586,7 +587,8 @@ int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_s
     return SV_OK;
 }
 
-int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph, sv_batch **out)
+int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
+                    uint64_t group_bytes, sv_batch **out)
 {
     if (!states || !plans || !out || count == 0) return fail(SV_EINVAL, "NULL argument or empty batch");
     *out = nullptr;
@@ -619,10 +621,32 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
         for (auto *d : B->d_items) (void)hipFree(d);
         delete B;
     };
-    for (size_t lv = 0; lv < levels; ++lv) {
+    // Groups: instances sorted by state size are packed greedily into groups
+    // whose states together stay within group_bytes, so a group that fits the
+    // device's last-level cache keeps its states there across its levels; each
+    // group runs level by level, groups one after another.
+    if (group_bytes == 0) group_bytes = 192ull << 20;
+    std::vector<size_t> order(count);
+    for (size_t i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return states[a]->n < states[b]->n; });
+    std::vector<std::vector<size_t>> groups;
+    uint64_t acc = 0;
+    for (size_t i : order) {
+        const uint64_t bytes = (uint64_t)esize(states[i]->dtype) << states[i]->n;
+        if (groups.empty() || (acc + bytes > group_bytes && !groups.back().empty())) {
+            groups.emplace_back();
+            acc = 0;
+        }
+        groups.back().push_back(i);
+        acc += bytes;
+    }
+    for (const auto &grp : groups) {
+      size_t glevels = 0;
+      for (size_t i : grp) glevels = std::max(glevels, plans[i]->steps.size());
+      for (size_t lv = 0; lv < glevels; ++lv) {
         std::vector<svi::BatchItem> items;
         uint64_t total = 0;
-        for (size_t i = 0; i < count; ++i) {
+        for (size_t i : grp) {
             const sv_plan *p = plans[i];
             if (lv >= p->steps.size()) continue;
             const uint32_t pi = p->steps[lv].index;
@@ -646,7 +670,9 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
         B->d_items.push_back(d);
         B->n_items.push_back((uint32_t)items.size());
         B->total.push_back(total);
+      }
     }
+    B->groups = groups.size();
     *out = B;
     return SV_OK;
 }
@@ -723,10 +749,11 @@ int sv_batch_time(sv_batch *B, int repeat, double *ms)
     return rc;
 }
 
-int sv_batch_levels(const sv_batch *B, uint64_t *levels, uint64_t *gates)
+int sv_batch_levels(const sv_batch *B, uint64_t *launches, uint64_t *groups, uint64_t *gates)
 {
     if (!B) return fail(SV_EINVAL, "NULL batch");
-    if (levels) *levels = B->d_items.size();
+    if (launches) *launches = B->d_items.size();
+    if (groups) *groups = B->groups;
     if (gates) *gates = B->gates;
     return SV_OK;
 }

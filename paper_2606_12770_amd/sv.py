@@ -76,10 +76,10 @@ def load_library(path: str = LIB_PATH):
         "sv_copy": [vp, vp],
         "sv_inner": [vp, vp, dp, dp],
         "sv_alloc_batch": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, vp, pvp],
-        "sv_batch_create": [pvp, pvp, ctypes.c_size_t, ctypes.c_int, pvp],
+        "sv_batch_create": [pvp, pvp, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint64, pvp],
         "sv_batch_execute": [vp, ctypes.c_int],
         "sv_batch_time": [vp, ctypes.c_int, dp],
-        "sv_batch_levels": [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+        "sv_batch_levels": [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         "sv_batch_free": [vp],
     }
     for name, args in sig.items():
@@ -219,14 +219,14 @@ def sv_alloc_batch(n_qubits, dtype: int = SV_C64, stream=None):
     return [ctypes.c_void_p(out[i]) for i in range(n)]
 
 
-def sv_batch_create(states, plans, use_graph: bool = True):
+def sv_batch_create(states, plans, use_graph: bool = True, group_bytes: int = 0):
     n = len(states)
     if len(plans) != n:
         raise ValueError("one plan per state")
     sa = (ctypes.c_void_p * n)(*[s.value for s in states])
     pa = (ctypes.c_void_p * n)(*[p.value for p in plans])
     out = ctypes.c_void_p()
-    _check(load_library().sv_batch_create(sa, pa, n, int(use_graph), ctypes.byref(out)))
+    _check(load_library().sv_batch_create(sa, pa, n, int(use_graph), group_bytes, ctypes.byref(out)))
     return out
 
 
@@ -241,9 +241,10 @@ def sv_batch_time(batch, repeat: int = 1) -> float:
 
 
 def sv_batch_levels(batch):
-    lv, g = ctypes.c_uint64(), ctypes.c_uint64()
-    _check(load_library().sv_batch_levels(batch, ctypes.byref(lv), ctypes.byref(g)))
-    return lv.value, g.value
+    """(launches, groups, gates) of one execution."""
+    lv, gr, g = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().sv_batch_levels(batch, ctypes.byref(lv), ctypes.byref(gr), ctypes.byref(g)))
+    return lv.value, gr.value, g.value
 
 
 def sv_batch_free(batch):

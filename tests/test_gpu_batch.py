@@ -37,16 +37,19 @@ def _mixed_batch(seed):
     return circs, inits
 
 
+ONE_GROUP = (1 << 64) - 1
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_equals_one_at_a_time(dtype, use_graph):
+@pytest.mark.parametrize("use_graph,group_bytes", [(False, ONE_GROUP), (True, ONE_GROUP), (True, 0), (False, 1 << 22)])
+def test_batch_equals_one_at_a_time(dtype, use_graph, group_bytes):
     sv = require_gpu()
     circs, inits = _mixed_batch(dtype)
     plans = _plans(sv, circs, dtype)
     states = sv.sv_alloc_batch([c.n for c in circs], dtype)
     for st, v in zip(states, inits):
         sv.sv_set_amplitudes(st, v, 0)
-    batch = sv.sv_batch_create(states, plans, use_graph)
+    batch = sv.sv_batch_create(states, plans, use_graph, group_bytes)
     sv.sv_batch_execute(batch, 2)
     got = [sv.sv_amplitudes(st) for st in states]
     for i, (c, v, p) in enumerate(zip(circs, inits, plans)):
@@ -61,9 +64,13 @@ def test_batch_equals_one_at_a_time(dtype, use_graph):
             oracle = osv.run(c, osv.run(c, v))
             tol = 1e-12 if dtype == 1 else 1e-5
             assert np.max(np.abs(got[i] - oracle)) < tol
-    levels, gates = sv.sv_batch_levels(batch)
+    launches, groups, gates = sv.sv_batch_levels(batch)
     assert gates == sum(len(c) for c in circs)
-    assert levels == max(sv.sv_plan_get_info(p)["n_launches"] for p in plans)
+    passes = [sv.sv_plan_get_info(p)["n_launches"] for p in plans]
+    if group_bytes == ONE_GROUP:
+        assert groups == 1 and launches == max(passes)
+    else:
+        assert 1 <= groups <= len(circs) and max(passes) <= launches <= sum(passes)
     sv.sv_batch_free(batch)
     for st in states:
         sv.sv_free(st)
