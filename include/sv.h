@@ -90,7 +90,9 @@ typedef struct {
     int mode;          /* SV_MODE_PLAIN or SV_MODE_FUSED                                  */
     int tile_qubits;   /* fused: qubits resident per tile, 0 = automatic                   */
     int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic        */
-    int reserved;      /* must be 0                                                        */
+    int dense_min_ops; /* fused, complex64: a run of at least this many consecutive ops
+                          acting inside 5 qubits (targets and controls) becomes one dense
+                          32 x 32 block applied with FP32 matrix cores; 0 = never        */
 } sv_apply_opts;
 
 typedef struct sv_state sv_state;
@@ -105,6 +107,8 @@ typedef struct {
     uint64_t tile_pass_bytes; /* algorithmic HBM bytes of one tile pass              */
     int      tile_qubits;     /* b actually used (fused)                             */
     int      reg_qubits;      /* register qubits actually used (fused)               */
+    uint64_t n_dense_passes;  /* launches that apply a dense 5-qubit block           */
+    uint64_t n_dense_ops;     /* IR ops absorbed into dense blocks                   */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libsv.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["sv_api.hip", "kernels_plain.hip", "kernels_tile.hip", "planner.cpp"]
+SOURCES = ["sv_api.hip", "kernels_plain.hip", "kernels_tile.hip", "kernels_dense.hip", "planner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",

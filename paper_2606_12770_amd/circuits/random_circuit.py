@@ -95,3 +95,28 @@ def random_state(n: int, seed: int = 0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
     return v / np.linalg.norm(v)
+
+
+def random_dense_block_circuit(n: int, blocks: int, depth: int, seed: int = 0, between: int = 3) -> Circuit:
+    """Deep gate runs confined to five qubits at a time (the case dense block
+    fusion is for): per block, five distinct qubits; per layer a Haar U(2) on
+    each, a CX between two of them, a doubly controlled phase and a controlled
+    increment (or controlled swap) inside the block; `between` Haar gates on
+    random qubits separate the blocks."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    for _ in range(blocks):
+        blk = sorted(int(q) for q in rng.choice(n, 5, replace=False))
+        for _ in range(depth):
+            for q in blk:
+                c.u(q, haar_u2(rng))
+            a, b = (int(v) for v in rng.choice(blk, 2, replace=False))
+            c.x(b, [a])
+            c.phase(blk[0], float(rng.uniform(-3, 3)), {blk[1]: 1, blk[2]: 0})
+            if blk[2] != blk[1] + 1:
+                c.inc(blk[1], 1, {blk[3]: 1})
+            else:
+                c.swap(blk[1], blk[2], {blk[4]: 0})
+        for _ in range(between):
+            c.u(int(rng.integers(n)), haar_u2(rng))
+    return c

@@ -1,0 +1,116 @@
+// Dense 5-qubit block pass on FP32 matrix cores (complex64 states).
+//
+// A workgroup stages one tile of 2^12 amplitudes in LDS (five block qubits and
+// seven others, loaded through the coalesced tile mapping).  Each of the four
+// waves takes 32 groups (values of the seven other local qubits) and computes
+// Y = G X for their 32-amplitude columns as a real 32 x 64 by 64 x 32 product
+// per part:
+//   Y_re = [G_re | -G_im] [X_re; X_im],   Y_im = [G_im | G_re] [X_re; X_im],
+// with v_mfma_f32_32x32x2f32 (32 K-steps of 2 per part).  Operand layout of
+// that instruction: lane l holds A[l % 32][k = l / 32] and B[k = l / 32][l % 32];
+// result register t of lane l is D[8 (t / 4) + 4 (l / 32) + t % 4][l % 32].
+// Lane (c, h) = (l % 32, l / 32) therefore reads the amplitudes j = 2i + h of
+// group c and ends up holding rows 8 (t / 4) + 4 h + t % 4 of that group.
+#include <hip/hip_runtime.h>
+
+#include "sv_internal.h"
+
+namespace svi {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__global__ void __launch_bounds__(256)
+k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats)
+{
+    extern __shared__ unsigned char smem_raw[];
+    float2 *lds = reinterpret_cast<float2 *>(smem_raw);
+    const DensePass &D = *dp;
+    const TilePass &P = D.map;
+    const uint32_t tid = threadIdx.x;
+
+    const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    uint64_t base = 0;
+    for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
+        const uint32_t sh = P.tile_shift[r];
+        base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
+    }
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
+    float2 *const pt = psi + (base | gthr);
+
+    float2 x[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+    const uint32_t tw = lds_swizzle(tid, 4);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+
+    // A operands of this lane: row c of [G_re | -G_im] and of [G_im | G_re],
+    // columns 2 kk + h
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t c = lane & 31u, h = lane >> 5;
+    const float *G = mats + D.mat;
+    float a1[32], a2[32];
+#pragma unroll
+    for (int kk = 0; kk < 32; ++kk) {
+        const uint32_t q = 2u * kk + h;
+        if (kk < 16) {
+            a1[kk] = G[2 * (32 * c + q)];
+            a2[kk] = G[2 * (32 * c + q) + 1];
+        } else {
+            a1[kk] = -G[2 * (32 * c + q - 32) + 1];
+            a2[kk] = G[2 * (32 * c + q - 32)];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t g = wave * 32u + c;
+    uint32_t gl = 0;
+    for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+        const uint32_t w = D.grp_run[r];
+        gl |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+    }
+    float2 xb[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xb[i] = lds[lds_swizzle(gl | D.joff[2 * i + h], 4)];
+
+    v16f acc_re = {0.f}, acc_im = {0.f};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk].x, acc_re, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk].x, acc_im, 0, 0, 0);
+    }
+#pragma unroll
+    for (int kk = 16; kk < 32; ++kk) {
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk - 16].y, acc_re, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk - 16].y, acc_im, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const uint32_t i = 8u * (t / 4) + 4u * h + (t % 4);
+        lds[lds_swizzle(gl | D.joff[i], 4)] = make_float2(acc_re[t], acc_im[t]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) x[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) pt[P.goff[s]] = x[s];
+}
+
+int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
+{
+    if (p->dtype != SV_C64) return SV_EUNSUPPORTED;
+    const DensePass &D = p->dense[di];
+    const uint64_t tiles = 1ull << D.map.ntile;
+    const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
+    const uint32_t gy = (uint32_t)(tiles / gx);
+    hipLaunchKernelGGL(k_dense_pass, dim3(gx, gy), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                       (const DensePass *)p->d_dense + di, (const float *)p->d_dparams);
+    return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+}
+
+}  // namespace svi

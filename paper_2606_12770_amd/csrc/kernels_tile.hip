@@ -291,8 +291,11 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 // sums item_begin[]; workgroup w finds its instance by binary search and runs
 // that tile, so instances of very different sizes share one launch.  Instances
 // of a launch share the geometry (b, RB) and precision.
+// Five waves per SIMD as for the single-pass kernel (the LDS of a 2^12 complex64
+// tile allows five workgroups per CU); without the hint the instance lookup
+// costs the register headroom for the fifth wave.
 template <typename R, int RB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB == 4 && sizeof(R) == 4 ? 5 : 1, 8)))
 k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total)
 {
     using C = typename CTT<R>::T;

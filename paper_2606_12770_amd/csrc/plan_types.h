@@ -139,8 +139,22 @@ struct PlainOp {
 };
 
 struct Step {
-    int type;            // 0 = plain op, 1 = tile pass
+    int type;            // 0 = plain op, 1 = tile pass, 2 = dense block pass
     uint32_t index;
+};
+
+// Dense 5-qubit block: the 2^12 amplitudes of a tile (the five block qubits and
+// seven others) go through LDS; a group is one value of the seven other local
+// qubits, and every group's 32 amplitudes are multiplied by the block matrix.
+// `map` carries the load/store mapping (spos, tpos, runs, goff, swz0) of a tile
+// pass with b = 12 and 4 register qubits; its stage fields are unused.
+constexpr int kDenseK = 5;
+struct DensePass {
+    TilePass map;
+    uint32_t mat;                     // offset (reals) of the matrix: (row i, column j), re, im
+    uint32_t n_grp_runs;              // group index (7 bits) -> local offset, as pack_run16 runs
+    uint32_t grp_run[kMaxThrRuns];
+    uint32_t joff[1 << kDenseK];      // local offset of block value j (bit k of j -> block qubit k)
 };
 
 // One instance of a batched launch: its state, the tile pass it runs at this
@@ -169,7 +183,10 @@ struct sv_plan {
     std::vector<svi::TileStage> stages;
     std::vector<svi::TileOp> tops;
     std::vector<double> tparams;      // host copy (double); converted on upload
+    std::vector<svi::DensePass> dense;
+    std::vector<double> dparams;      // dense block matrices (double); converted on upload
     void *d_passes = nullptr, *d_stages = nullptr, *d_tops = nullptr, *d_tparams = nullptr;
+    void *d_dense = nullptr, *d_dparams = nullptr;
     int device = -1;
     sv_plan_info info{};
 };

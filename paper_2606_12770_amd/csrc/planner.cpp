@@ -11,6 +11,7 @@
 // the target of an X in both.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "plan_types.h"
@@ -174,6 +175,88 @@ std::vector<OpInfo> fold_single_qubit_runs(const std::vector<OpInfo> &in)
     return out;
 }
 
+// ---- dense 5-qubit blocks -------------------------------------------------
+// The block matrix of a run of ops whose qubits (targets and controls) lie in
+// blk[0..4] (ascending): column j is the run applied to the basis vector e_j,
+// bit k of the index standing for qubit blk[k].
+using cplx = std::complex<double>;
+
+void apply_small(std::vector<cplx> &v, const OpInfo &o, const int *blk)
+{
+    auto mapbits = [&](uint64_t m) {
+        uint32_t r = 0;
+        for (int k = 0; k < kDenseK; ++k)
+            if ((m >> blk[k]) & 1ull) r |= 1u << k;
+        return r;
+    };
+    auto pos = [&](int q) {
+        for (int k = 0; k < kDenseK; ++k)
+            if (blk[k] == q) return k;
+        return -1;
+    };
+    const uint32_t mask = mapbits(o.mask), val = mapbits(o.val);
+    const int N = 1 << kDenseK;
+    const std::vector<cplx> in = v;
+    switch (o.kind) {
+    case SV_OP_U: {
+        const int t = pos(o.target);
+        const cplx m00(o.m[0], o.m[1]), m01(o.m[2], o.m[3]), m10(o.m[4], o.m[5]), m11(o.m[6], o.m[7]);
+        for (int i = 0; i < N; ++i) {
+            if ((i >> t) & 1 || (i & mask) != val) continue;
+            const int i1 = i | (1 << t);
+            v[i] = m00 * in[i] + m01 * in[i1];
+            v[i1] = m10 * in[i] + m11 * in[i1];
+        }
+        break;
+    }
+    case SV_OP_X: {
+        const int t = pos(o.target);
+        for (int i = 0; i < N; ++i)
+            if (!((i >> t) & 1) && (i & mask) == val) std::swap(v[i], v[i | (1 << t)]);
+        break;
+    }
+    case SV_OP_PHASE: {
+        const int t = pos(o.target);
+        const cplx ph(std::cos(o.m[0]), std::sin(o.m[0]));
+        for (int i = 0; i < N; ++i)
+            if (((i >> t) & 1) && (i & mask) == val) v[i] *= ph;
+        break;
+    }
+    case SV_OP_PROJPHASE: {
+        const int t = pos(o.target);
+        for (int i = 0; i < N; ++i) {
+            const int z = (i & mask) == val, sb = (i >> t) & 1;
+            const double th = o.m[0] * (1 - 2 * (sb ^ z));
+            v[i] *= cplx(std::cos(th), std::sin(th));
+        }
+        break;
+    }
+    case SV_OP_INC:
+    case SV_OP_DEC: {
+        const int base = pos(o.target), w = (int)o.width;
+        const uint32_t rm = ((1u << w) - 1u) << base;
+        for (int i = 0; i < N; ++i) {
+            if ((i & mask) != val) continue;
+            uint32_t r = ((uint32_t)i & rm) >> base;
+            r = (o.kind == SV_OP_INC ? r + 1 : r - 1) & ((1u << w) - 1u);
+            v[((uint32_t)i & ~rm) | (r << base)] = in[i];
+        }
+        break;
+    }
+    case SV_OP_SWAP: {
+        const int a = pos(o.target), b = pos((int)o.width);
+        for (int i = 0; i < N; ++i) {
+            if ((i & mask) != val) continue;
+            const int j = ((((i >> a) ^ (i >> b)) & 1) ? i ^ ((1 << a) | (1 << b)) : i);
+            v[j] = in[i];
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
 }  // namespace
 
 int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params, const sv_apply_opts &opts,
@@ -222,6 +305,8 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     p->stages.clear();
     p->tops.clear();
     p->tparams.clear();
+    p->dense.clear();
+    p->dparams.clear();
 
     auto add_plain = [&](const OpInfo &o) {
         p->steps.push_back(Step{0, (uint32_t)p->plain.size()});
@@ -246,11 +331,133 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
 
+    // ---- dense 5-qubit runs (complex64): maximal runs of consecutive ops whose
+    // qubits fit in five, kept when at least dense_min_ops long ----
+    std::vector<int> dense_id(n_ops, -1);
+    std::vector<std::pair<size_t, size_t>> runs;
+    std::vector<uint64_t> run_support;
+    if (opts.dense_min_ops > 0 && p->dtype == SV_C64 && n >= 12) {
+        size_t ws = 0;
+        uint64_t S = 0;
+        auto close = [&](size_t end) {
+            if (end - ws >= (size_t)opts.dense_min_ops && S) {
+                for (size_t k = ws; k < end; ++k) dense_id[k] = (int)runs.size();
+                runs.emplace_back(ws, end);
+                run_support.push_back(S);
+            }
+        };
+        for (size_t i = 0; i < n_ops; ++i) {
+            const uint64_t T = touched_qubits(info[i]);
+            if (__builtin_popcountll(S | T) <= kDenseK) {
+                S |= T;
+                continue;
+            }
+            close(i);
+            ws = i;
+            S = __builtin_popcountll(T) <= kDenseK ? T : 0;
+            if (!S) ws = i + 1;  // an op wider than a block starts no run
+        }
+        close(n_ops);
+    }
+    auto emit_dense = [&](int rid) {
+        const uint64_t S = run_support[rid];
+        int blk[kDenseK];
+        {
+            uint64_t B = S;
+            for (int q = 0; q < n && __builtin_popcountll(B) < kDenseK; ++q) B |= 1ull << q;
+            int k = 0;
+            for (int q = 0; q < n; ++q)
+                if ((B >> q) & 1ull) blk[k++] = q;
+        }
+        uint64_t R = 0;
+        for (int k = 0; k < kDenseK; ++k) R |= 1ull << blk[k];
+        for (int q = 0; q < n && __builtin_popcountll(R) < 12; ++q) R |= 1ull << q;
+        DensePass D{};
+        TilePass &P = D.map;
+        P.b = 12;
+        P.rb = 4;
+        P.nthr = 8;
+        P.ntile = (uint8_t)(n - 12);
+        int lpos[64];
+        for (int q = 0; q < 64; ++q) lpos[q] = -1;
+        {
+            int k = 0, t = 0;
+            for (int q = 0; q < n; ++q) {
+                if ((R >> q) & 1ull) {
+                    P.spos[k] = (uint8_t)q;
+                    lpos[q] = k++;
+                } else {
+                    P.tpos[t++] = (uint8_t)q;
+                }
+            }
+        }
+        const int dl = 4;  // LDS swizzle width of complex64
+        for (int s2 = 0; s2 < 16; ++s2) {
+            uint64_t off = 0;
+            for (int k = 0; k < 4; ++k)
+                if ((s2 >> k) & 1) off |= 1ull << P.spos[8 + k];
+            P.goff[s2] = off;
+            P.swz0[s2] = lds_swizzle((uint32_t)s2 << 8, dl);
+        }
+        P.n_tile_runs = (uint32_t)bit_runs(P.tpos, P.ntile, [&](int src, int dst, int w) {
+            const int r = (int)P.n_tile_runs++;
+            P.tile_shift[r] = (uint32_t)src | ((uint32_t)dst << 8);
+            P.tile_mask[r] = (w >= 64) ? ~0ull : ((1ull << w) - 1ull);
+        });
+        P.n_gthr_runs = (uint32_t)bit_runs(P.spos, 8, [&](int src, int dst, int w) {
+            const int r = (int)P.n_gthr_runs++;
+            P.gthr_shift[r] = (uint32_t)src | ((uint32_t)dst << 8);
+            P.gthr_mask[r] = (1u << w) - 1u;
+        });
+        for (int j = 0; j < (1 << kDenseK); ++j) {
+            uint32_t off = 0;
+            for (int k = 0; k < kDenseK; ++k)
+                if ((j >> k) & 1) off |= 1u << lpos[blk[k]];
+            D.joff[j] = off;
+        }
+        uint8_t nb[8];
+        {
+            int c = 0;
+            for (int l = 0; l < 12; ++l) {
+                bool inblk = false;
+                for (int k = 0; k < kDenseK; ++k) inblk = inblk || lpos[blk[k]] == l;
+                if (!inblk) nb[c++] = (uint8_t)l;
+            }
+        }
+        D.n_grp_runs = 0;
+        bit_runs(nb, 7, [&](int src, int dst, int w) {
+            D.grp_run[D.n_grp_runs++] = pack_run16((uint32_t)src, (uint32_t)dst, (1u << w) - 1u);
+        });
+        // the block matrix, column by column
+        D.mat = (uint32_t)p->dparams.size();
+        p->dparams.resize(p->dparams.size() + 2 * 32 * 32, 0.0);
+        for (int j = 0; j < 32; ++j) {
+            std::vector<cplx> v(32, cplx(0.0, 0.0));
+            v[j] = 1.0;
+            for (size_t k = runs[rid].first; k < runs[rid].second; ++k) apply_small(v, info[k], blk);
+            for (int i = 0; i < 32; ++i) {
+                p->dparams[D.mat + 2 * (32 * i + j)] = v[i].real();
+                p->dparams[D.mat + 2 * (32 * i + j) + 1] = v[i].imag();
+            }
+        }
+        p->steps.push_back(Step{2, (uint32_t)p->dense.size()});
+        p->dense.push_back(D);
+        p->info.n_dense_passes += 1;
+        p->info.n_dense_ops += runs[rid].second - runs[rid].first;
+        p->info.bytes_moved += 2ull * (1ull << n) * esize;
+    };
+
     std::vector<char> done(n_ops, 0);
     size_t first = 0;
     while (true) {
         while (first < n_ops && done[first]) ++first;
         if (first >= n_ops) break;
+        if (dense_id[first] >= 0) {  // every earlier op is done: the block goes now
+            const int rid = dense_id[first];
+            emit_dense(rid);
+            for (size_t k = runs[rid].first; k < runs[rid].second; ++k) done[k] = 1;
+            continue;
+        }
         if (__builtin_popcountll(info[first].req | lowmask) > b) {
             // cannot be made resident: its own launch (all earlier ops are done)
             add_plain(info[first]);
@@ -266,6 +473,12 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             for (size_t j = first; j < wend; ++j) {
                 if (done[j]) continue;
                 const OpInfo &o = info[j];
+                if (dense_id[j] >= 0) {  // belongs to a dense block: never taken, blocks what it touches
+                    Z |= o.z;
+                    X |= o.x;
+                    G |= o.g;
+                    continue;
+                }
                 const bool ready = commutes_with_all(o, Z, X, G);
                 if (ready && (o.req & ~pb.S) == 0) {
                     done[j] = 1;

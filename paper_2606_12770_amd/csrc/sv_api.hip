@@ -166,6 +166,12 @@ int upload_plan(sv_plan *p)
     } else {
         rc = up(&p->d_tparams, p->tparams.empty() ? nullptr : p->tparams.data(), p->tparams.size() * sizeof(double));
     }
+    if (rc != SV_OK) return rc;
+    if (!p->dense.empty()) {
+        if ((rc = up(&p->d_dense, p->dense.data(), p->dense.size() * sizeof(svi::DensePass))) != SV_OK) return rc;
+        std::vector<float> f(p->dparams.begin(), p->dparams.end());
+        rc = up(&p->d_dparams, f.data(), f.size() * sizeof(float));
+    }
     return rc;
 }
 
@@ -175,14 +181,17 @@ void release_plan(sv_plan *p)
     if (p->d_stages) (void)hipFree(p->d_stages);
     if (p->d_tops) (void)hipFree(p->d_tops);
     if (p->d_tparams) (void)hipFree(p->d_tparams);
-    p->d_passes = p->d_stages = p->d_tops = p->d_tparams = nullptr;
+    if (p->d_dense) (void)hipFree(p->d_dense);
+    if (p->d_dparams) (void)hipFree(p->d_dparams);
+    p->d_passes = p->d_stages = p->d_tops = p->d_tparams = p->d_dense = p->d_dparams = nullptr;
 }
 
 int run_plan_once(const sv_plan *p, sv_state *s)
 {
     for (const auto &st : p->steps) {
-        int rc = st.type == 0 ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, s->stream)
-                              : svi::launch_tile_pass(p, st.index, s->d_psi, s->stream);
+        int rc = st.type == 0   ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, s->stream)
+                 : st.type == 1 ? svi::launch_tile_pass(p, st.index, s->d_psi, s->stream)
+                                : svi::launch_dense_pass(p, st.index, s->d_psi, s->stream);
         if (rc != SV_OK) return fail(rc, "kernel launch failed");
     }
     return SV_OK;
@@ -312,7 +321,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     o.mode = SV_MODE_FUSED;
     if (opts) o = *opts;
     if (o.mode != SV_MODE_PLAIN && o.mode != SV_MODE_FUSED) return fail(SV_EINVAL, "unknown mode");
-    if (o.reserved != 0) return fail(SV_EINVAL, "reserved option must be 0");
+    if (o.dense_min_ops < 0) return fail(SV_EINVAL, "dense_min_ops must be >= 0");
     int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
     if (rc != SV_OK) return rc;
     int dev = 0;

@@ -24,6 +24,7 @@ namespace svi {
 // kernels (launch wrappers), all on `stream`
 int launch_plain(const PlainOp &op, int n, int dtype, void *psi, hipStream_t stream);
 int launch_tile_pass(const sv_plan *p, uint32_t pass_index, void *psi, hipStream_t stream);
+int launch_dense_pass(const sv_plan *p, uint32_t dense_index, void *psi, hipStream_t stream);
 int launch_init_basis(void *psi, int n, int dtype, hipStream_t stream);
 int launch_from_c128(void *psi, int dtype, const void *d_src, uint64_t offset, uint64_t count,
                      hipStream_t stream);

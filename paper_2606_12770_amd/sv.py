@@ -36,13 +36,14 @@ class SVError(RuntimeError):
 
 class sv_apply_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("dense_min_ops", ctypes.c_int)]
 
 
 class sv_plan_info(ctypes.Structure):
     _fields_ = [("n_ops", ctypes.c_uint64), ("n_launches", ctypes.c_uint64), ("n_tile_passes", ctypes.c_uint64),
                 ("n_stages", ctypes.c_uint64), ("bytes_moved", ctypes.c_uint64), ("tile_pass_bytes", ctypes.c_uint64),
-                ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int)]
+                ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int), ("n_dense_passes", ctypes.c_uint64),
+                ("n_dense_ops", ctypes.c_uint64)]
 
 
 _lib = None
@@ -104,8 +105,8 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0):
-    return sv_apply_opts(mode, tile_qubits, reg_qubits, 0)
+def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
+    return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops)
 
 
 # ---- the C entry points under their own names -------------------------------
@@ -138,16 +139,16 @@ def _ops_params(ops, params):
     return ops, params
 
 
-def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0):
+def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops)
     _check(load_library().sv_apply_circuit(state, ops.ctypes.data, len(ops), _dp(params), len(params),
                                            ctypes.byref(o)))
 
 
-def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0):
+def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops)
     out = ctypes.c_void_p()
     _check(load_library().sv_plan_create(n_qubits, dtype, ops.ctypes.data, len(ops), _dp(params), len(params),
                                          ctypes.byref(o), ctypes.byref(out)))

@@ -303,15 +303,83 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
     return 0;
 }
 
+// Dense block pass: gather each tile through the load mapping, multiply every
+// group's 32 amplitudes by the block matrix (double precision), scatter back.
+// Checks: group and block offsets tile the 4096 local indices exactly once, and
+// every amplitude is read and written exactly once over the pass.
+int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std::vector<int> &wr)
+{
+    const DensePass &D = p.dense[di];
+    const TilePass &P = D.map;
+    const int n = p.n;
+    const uint64_t dim = 1ull << n;
+    if (P.b != 12 || P.nthr != 8 || P.rb != 4 || P.ntile != n - 12) return 30;
+    std::fill(rd.begin(), rd.end(), 0);
+    std::fill(wr.begin(), wr.end(), 0);
+    // group offsets from the runs, and the exact cover of the local indices
+    uint32_t goffl[128];
+    std::vector<int> cover(4096, 0);
+    for (int g = 0; g < 128; ++g) {
+        uint32_t o = 0;
+        for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+            const uint32_t w = D.grp_run[r];
+            o |= (((uint32_t)g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+        }
+        goffl[g] = o;
+        for (int j = 0; j < 32; ++j) {
+            const uint32_t l = o | D.joff[j];
+            if (l >= 4096 || (o & D.joff[j])) return 31;
+            cover[l]++;
+        }
+    }
+    for (int l = 0; l < 4096; ++l)
+        if (cover[l] != 1) return 32;
+    if (D.mat + 2048 > p.dparams.size()) return 33;
+    const double *G = p.dparams.data() + D.mat;
+    std::vector<cd> x(4096), y(4096);
+    for (uint64_t tile = 0; tile < (1ull << P.ntile); ++tile) {
+        uint64_t base = 0;
+        for (uint32_t r = 0; r < P.n_tile_runs; ++r)
+            base |= ((tile >> (P.tile_shift[r] & 0xffu)) & P.tile_mask[r]) << (P.tile_shift[r] >> 8);
+        auto gidx = [&](uint32_t l) {
+            uint64_t g = 0;
+            for (int k = 0; k < 12; ++k)
+                if ((l >> k) & 1u) g |= 1ull << P.spos[k];
+            return base | g;
+        };
+        for (uint32_t l = 0; l < 4096; ++l) {
+            const uint64_t g = gidx(l);
+            if (g >= dim) return 34;
+            rd[g]++;
+            x[l] = psi[g];
+        }
+        for (int g = 0; g < 128; ++g)
+            for (int i = 0; i < 32; ++i) {
+                cd acc(0.0, 0.0);
+                for (int j = 0; j < 32; ++j)
+                    acc += cd(G[2 * (32 * i + j)], G[2 * (32 * i + j) + 1]) * x[goffl[g] | D.joff[j]];
+                y[goffl[g] | D.joff[i]] = acc;
+            }
+        for (uint32_t l = 0; l < 4096; ++l) {
+            const uint64_t g = gidx(l);
+            wr[g]++;
+            psi[g] = y[l];
+        }
+    }
+    for (uint64_t i = 0; i < dim; ++i)
+        if (rd[i] != 1 || wr[i] != 1) return 35;
+    return 0;
+}
+
 }  // namespace
 
 extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode,
-                       int tile_qubits, int reg_qubits, double *psi_io, uint64_t *stats)
+                       int tile_qubits, int reg_qubits, double *psi_io, uint64_t *stats, int dense_min_ops)
 {
     sv_plan p;
     p.n = n;
     p.dtype = dtype;
-    sv_apply_opts o{mode, tile_qubits, reg_qubits, 0};
+    sv_apply_opts o{mode, tile_qubits, reg_qubits, dense_min_ops};
     std::string err;
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;
@@ -320,9 +388,12 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     for (const auto &st : p.steps) {
         if (st.type == 0) {
             emu_plain(p.plain[st.index], n, psi);
-        } else {
+        } else if (st.type == 1) {
             rc = emu_tile(p, st.index, psi, rd, wr);
             if (rc) return 100 + rc;
+        } else {
+            rc = emu_dense(p, st.index, psi, rd, wr);
+            if (rc) return 200 + rc;
         }
     }
     if (stats) {

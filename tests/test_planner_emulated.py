@@ -31,18 +31,18 @@ def emu():
     L = ctypes.CDLL(OUT)
     L.emu_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                           ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
+                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     L.emu_run.restype = ctypes.c_int
     return L
 
 
-def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0):
+def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0, dense_min_ops=0):
     ops, params = circ.arrays()
     psi = np.array(psi0, dtype=np.complex128, copy=True)
     stats = (ctypes.c_uint64 * 4)()
     dp = ctypes.POINTER(ctypes.c_double)
     rc = L.emu_run(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(dp), mode, b, rb,
-                   psi.ctypes.data_as(dp), stats)
+                   psi.ctypes.data_as(dp), stats, dense_min_ops)
     assert rc == 0, f"emulation check failed with code {rc}"
     return psi, list(stats)
 
@@ -116,3 +116,17 @@ def test_precomputed_pass_fields_at_benchmark_size(emu, dtype, b, rb):
     rc = emu.emu_check_fields(28, dtype, ops.ctypes.data, len(ops),
                               params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), b, rb)
     assert rc == 0
+
+
+@pytest.mark.parametrize("n,seed", [(12, 0), (14, 1), (16, 2)])
+def test_dense_blocks_match_oracle(emu, n, seed):
+    from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
+    c = random_dense_block_circuit(n, 4, 5, seed)
+    psi0 = random_state(n, seed)
+    want = osv.run(c, psi0)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=16)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[0] >= stats[1] + 4  # the four deep runs became dense passes
+    # without dense blocks the same plan path agrees too
+    got2, _ = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=0)
+    assert np.max(np.abs(got2 - want)) < 1e-12
