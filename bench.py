@@ -169,6 +169,43 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     return out
 
 
+def largest_state(sv, d=1, reps=1):
+    """N_x = 256, N_K = 4, N_t = 4 (tau 0.8, A 0.08, u0 0.02): the QSVT ladder at
+    degree d on 34 qubits in complex64 (128 GiB); FP64 norm drift and the
+    post-selection probability of the final-time rows."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc, qsp
+    cfg = cc.CarlemanConfig(nx=256, tau=0.8, nk=4, nt=4, dt=0.1, amp=0.08, u0=0.02)
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    import numpy as np
+    # d = 1: zero phases give Re p(x) = T_1(x) = x, one call of U_L^dagger
+    phases = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)[0] if d > 1 else np.zeros(2)
+    circ = cc.build_qsvt(enc, phases)
+    ops, params = circ.arrays()
+    plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED)
+    info = sv.sv_plan_get_info(plan)
+    st = sv.sv_alloc(L.n, sv.SV_C64)
+    sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
+    ms = sv.sv_plan_time(plan, st, reps) / reps
+    norm2 = sv.sv_postselect(st, 0, 0, keep=False, renormalize=False)
+    # ancillas and signal 0 (the block-encoded result); the final-time rows are
+    # reached only at degrees of a few times N_t (N_K + 1), so at d = 1 their
+    # probability is exactly 0
+    mask, val = cc.postselect_condition(L, final_time=False)
+    P = sv.sv_postselect(st, mask, val, keep=False, renormalize=False)
+    fmask, fval = cc.postselect_condition(L)
+    P_final = sv.sv_postselect(st, fmask, fval, keep=False, renormalize=False)
+    sv.sv_free(st)
+    sv.sv_plan_free(plan)
+    gb = info["bytes_moved"] / (ms / 1e3) / 1e9
+    out = {"qubits": L.n, "state_GiB": (8 << L.n) / 2 ** 30, "degree": d, "gates": len(circ), "ms": ms,
+           "gates_per_s": len(circ) / (ms / 1e3), "launches": info["n_launches"], "GBps_algorithmic": gb,
+           "norm_drift": abs(norm2 - 1.0), "postselect_prob_ancilla_zero": P, "postselect_prob_final_rows": P_final}
+    log(f"largest {L.n}q: {out['gates_per_s']:.0f} gates/s, {ms:.1f} ms, {gb:.0f} GB/s, norm drift "
+        f"{out['norm_drift']:.2e}, P {P:.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +305,7 @@ def main():
             "batched_64": batched_carleman(sv),
         }
         carleman["dense_block_microbench"] = dense_blocks(sv)
+        carleman["largest_34q"] = largest_state(sv)
 
     cpu = None
     if not args.skip_cpu:

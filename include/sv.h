@@ -190,13 +190,14 @@ typedef struct sv_batch sv_batch;
 
 /* Bind plans[i] to states[i] for i < count.  Every plan must be fused (tile
  * passes only), with one tile geometry and precision across the batch; the
- * states must share a stream and be distinct.  Instances, ordered by size, are
+ * states must be distinct and come from one sv_alloc_batch arena.  Instances, ordered by size, are
  * packed into groups of at most group_bytes of state (0: 192 MiB, about what
  * the last-level cache holds; UINT64_MAX: one group); a group runs level by
  * level, each level one launch over the tiles of all its instances.
  * use_graph != 0 captures all launches in a HIP graph on first execution and
- * replays it afterwards.  The batch keeps pointers to the plans' device tables
- * and the states' memory: free the batch before them. */
+ * replays it afterwards.  The batch keeps its own copy of the plans' tables
+ * (the plans may be freed) and points into the arena: free it before the
+ * states. */
 int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
                     uint64_t group_bytes, sv_batch **out);
 

@@ -24,6 +24,15 @@ template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4;
 template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
 
 
+// LDS element at byte offset `off` (the swizzle XOR is done on byte offsets:
+// shifting the uniform slot part happens in scalar registers, so each access
+// costs the one vector XOR with the thread part)
+template <typename C>
+__device__ __forceinline__ C &lds_at(C *lds, uint32_t off)
+{
+    return *reinterpret_cast<C *>(reinterpret_cast<unsigned char *>(lds) + off);
+}
+
 template <typename C, typename R>
 __device__ __forceinline__ C row2(R ar, R ai, R br, R bi, C a, C b)
 {
@@ -132,6 +141,9 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
 
 // One tile of one pass: load, register stages with LDS exchanges, store.
 // The caller passes the tile counter; every thread of the workgroup calls this.
+// Every pointer comes straight from kernel arguments (plus uniform offsets), so
+// the compiler knows the address spaces and reads the plan tables with scalar
+// loads; pointers read from memory would turn those into per-lane flat loads.
 template <typename R, int RB>
 __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
                                                const TilePass *__restrict__ pass,
@@ -175,9 +187,9 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
             const TileStage &P = stages[st - 1];
             __syncthreads();
             if (S.perm_begin == S.perm_end) {
-                const uint32_t tw = lds_swizzle(thr, LOWB);
+                const uint32_t tw = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
 #pragma unroll
-                for (int s = 0; s < NR; ++s) lds[tw ^ P.swz[s]] = x[s];
+                for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
             } else {
 #pragma unroll
                 for (int s = 0; s < NR; ++s) {
@@ -192,9 +204,9 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
                 t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
             }
             thr = t2;
-            const uint32_t tr = lds_swizzle(thr, LOWB);
+            const uint32_t tr = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ S.swz[s]];
+            for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (S.swz[s] * (uint32_t)sizeof(C)));
         }
         // op records are prefetched one ahead; parameters sit at a fixed stride,
         // so their loads do not wait for the record
@@ -256,9 +268,9 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
         const TileStage &L = stages[se - 1];
         __syncthreads();
         if (pass->fperm_begin == pass->fperm_end) {
-            const uint32_t tw = lds_swizzle(thr, LOWB);
+            const uint32_t tw = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) lds[tw ^ L.swz[s]] = x[s];
+            for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (L.swz[s] * (uint32_t)sizeof(C))) = x[s];
         } else {
 #pragma unroll
             for (int s = 0; s < NR; ++s) {
@@ -267,9 +279,9 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
             }
         }
         __syncthreads();
-        const uint32_t tr = lds_swizzle(tid, LOWB);
+        const uint32_t tr = lds_swizzle(tid, LOWB) * (uint32_t)sizeof(C);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) x[s] = lds[tr ^ pass->swz0[s]];
+        for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (pass->swz0[s] * (uint32_t)sizeof(C)));
     }
 #pragma unroll
     for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
@@ -287,16 +299,16 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
-// group.  Work items are (instance, tile) pairs laid end to end by the prefix
-// sums item_begin[]; workgroup w finds its instance by binary search and runs
-// that tile, so instances of very different sizes share one launch.  Instances
-// of a launch share the geometry (b, RB) and precision.
-// Five waves per SIMD as for the single-pass kernel (the LDS of a 2^12 complex64
-// tile allows five workgroups per CU); without the hint the instance lookup
-// costs the register headroom for the fifth wave.
+// group.  The batch owns one concatenated copy of its plans' tables (indices
+// rebased) and its states live in one arena, so an item is only offsets:
+// the state's first amplitude in the arena, its pass in the table and its first
+// work index.  Workgroup w finds its item by binary search over item_begin and
+// runs that tile.  Instances of a launch share the geometry (b, RB).
 template <typename R, int RB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB == 4 && sizeof(R) == 4 ? 5 : 1, 8)))
-k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total)
+__global__ void __launch_bounds__(256)
+k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict__ passes,
+             const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
+             const BatchItem *__restrict__ items, uint32_t n_items, uint64_t total)
 {
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
@@ -308,8 +320,8 @@ k_tile_batch(const BatchItem *__restrict__ items, uint32_t n_items, uint64_t tot
         if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
     const BatchItem &B = items[lo];
-    tile_pass_body<R, RB>(reinterpret_cast<C *>(B.psi), B.pass, B.stages, B.ops, reinterpret_cast<const R *>(B.prm),
-                          w - B.item_begin, reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
+                          reinterpret_cast<C *>(smem_raw));
 }
 
 template <typename R, int RB>
@@ -330,27 +342,28 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
 }
 
 template <typename R, int RB>
-static int launch_batch_t(int b, int nthr, const BatchItem *d_items, uint32_t n_items, uint64_t total,
+static int launch_batch_t(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total,
                           hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const uint32_t gx = total > 65536 ? 65536u : (uint32_t)total;
     const uint64_t gy = (total + gx - 1) / gx;
     if (gy > 65535) return SV_EUNSUPPORTED;
-    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << nthr), sizeof(C) << b, st, d_items,
-                       n_items, total);
+    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), sizeof(C) << T.b, st,
+                       (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages, (const TileOp *)T.ops,
+                       (const R *)T.prm, d_items, n_items, total);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
-int launch_tile_batch(int dtype, int rb, int b, int nthr, const BatchItem *d_items, uint32_t n_items,
-                      uint64_t total_work, hipStream_t st)
+int launch_tile_batch(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total_work,
+                      hipStream_t st)
 {
     if (!n_items || !total_work) return SV_OK;
-    if (dtype == SV_C64)
-        return rb == 5 ? launch_batch_t<float, 5>(b, nthr, d_items, n_items, total_work, st)
-                       : launch_batch_t<float, 4>(b, nthr, d_items, n_items, total_work, st);
-    return rb == 5 ? launch_batch_t<double, 5>(b, nthr, d_items, n_items, total_work, st)
-                   : launch_batch_t<double, 4>(b, nthr, d_items, n_items, total_work, st);
+    if (T.dtype == SV_C64)
+        return T.rb == 5 ? launch_batch_t<float, 5>(T, d_items, n_items, total_work, st)
+                         : launch_batch_t<float, 4>(T, d_items, n_items, total_work, st);
+    return T.rb == 5 ? launch_batch_t<double, 5>(T, d_items, n_items, total_work, st)
+                     : launch_batch_t<double, 4>(T, d_items, n_items, total_work, st);
 }
 
 int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)

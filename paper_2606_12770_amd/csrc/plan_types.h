@@ -157,17 +157,22 @@ struct DensePass {
     uint32_t joff[1 << kDenseK];      // local offset of block value j (bit k of j -> block qubit k)
 };
 
-// One instance of a batched launch: its state, the tile pass it runs at this
-// level (device pointers into its plan) and the first work index it owns.
+// One instance of a batched launch: where its state starts in the arena (in
+// amplitudes), the pass it runs at this level (index into the batch's
+// concatenated pass table) and the first work index it owns.
 struct BatchItem {
-    void *psi;
-    const TilePass *pass;
-    const TileStage *stages;
-    const TileOp *ops;
-    const void *prm;
+    uint64_t psi_off;
+    uint64_t pass_index;
     uint64_t item_begin;
 };
-static_assert(sizeof(BatchItem) == 48, "BatchItem layout");
+static_assert(sizeof(BatchItem) == 24, "BatchItem layout");
+
+// Device tables shared by all launches of a batch.
+struct BatchTables {
+    void *arena;
+    const void *passes, *stages, *ops, *prm;
+    int dtype, b, rb, nthr;
+};
 
 }  // namespace svi
 

@@ -25,8 +25,8 @@ struct Arena {
 }  // namespace svi
 
 struct sv_batch {
-    int dtype = SV_C64;
-    int b = 0, rb = 0, nthr = 0;
+    svi::BatchTables tables{};
+    std::vector<void *> d_tables;       // concatenated plan tables owned by the batch
     hipStream_t stream = nullptr;
     std::vector<uint32_t> n_items;      // per level
     std::vector<uint64_t> total;        // per level
@@ -602,7 +602,8 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
     if (!states || !plans || !out || count == 0) return fail(SV_EINVAL, "NULL argument or empty batch");
     *out = nullptr;
     const sv_plan *p0 = plans[0];
-    size_t levels = 0;
+    svi::Arena *arena = states[0] ? states[0]->arena : nullptr;
+    if (!arena) return fail(SV_EINVAL, "batched states must come from one sv_alloc_batch arena");
     for (size_t i = 0; i < count; ++i) {
         int rc = check_plan_state(plans[i], states[i]);
         if (rc != SV_OK) return rc;
@@ -611,25 +612,92 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
             return fail(SV_EINVAL, "batched plans must be fused with one tile geometry and one precision");
         for (const auto &st : p->steps)
             if (st.type != 1) return fail(SV_EUNSUPPORTED, "batched plans must consist of tile passes only");
-        if (states[i]->stream != states[0]->stream) return fail(SV_EINVAL, "batched states must share a stream");
+        if (states[i]->arena != arena) return fail(SV_EINVAL, "batched states must come from one sv_alloc_batch arena");
         for (size_t j = 0; j < i; ++j)
             if (states[j] == states[i]) return fail(SV_EINVAL, "a state appears twice in the batch");
-        levels = std::max(levels, p->steps.size());
     }
     sv_batch *B = new (std::nothrow) sv_batch();
     if (!B) return fail(SV_ENOMEM, "host allocation failed");
-    B->dtype = p0->dtype;
-    B->b = p0->b;
-    B->rb = p0->rb;
-    B->nthr = p0->b - p0->rb;
     B->stream = states[0]->stream;
     B->use_graph = use_graph != 0;
     B->states.assign(states, states + count);
     for (size_t i = 0; i < count; ++i) B->gates += plans[i]->info.n_ops;
+
+    // one copy of every distinct plan's tables, indices rebased
+    std::vector<svi::TilePass> passes;
+    std::vector<svi::TileStage> stages;
+    std::vector<svi::TileOp> tops;
+    std::vector<double> prm;
+    std::vector<const sv_plan *> seen;
+    std::vector<uint64_t> pass_base(count);
+    for (size_t i = 0; i < count; ++i) {
+        const sv_plan *p = plans[i];
+        size_t k = 0;
+        while (k < seen.size() && seen[k] != p) ++k;
+        if (k < seen.size()) {  // same plan as instance j: same tables
+            for (size_t j = 0; j < i; ++j)
+                if (plans[j] == p) pass_base[i] = pass_base[j];
+            continue;
+        }
+        seen.push_back(p);
+        const uint32_t so = (uint32_t)stages.size(), to = (uint32_t)tops.size();
+        pass_base[i] = passes.size();
+        for (svi::TilePass P : p->passes) {
+            P.stage_begin += so;
+            P.stage_end += so;
+            P.fperm_begin += to;
+            P.fperm_end += to;
+            passes.push_back(P);
+        }
+        for (svi::TileStage S : p->stages) {
+            S.op_begin += to;
+            S.op_end += to;
+            S.perm_begin += to;
+            S.perm_end += to;
+            stages.push_back(S);
+        }
+        for (svi::TileOp t : p->tops) {
+            t.param += to * (uint32_t)svi::kParamStride;
+            tops.push_back(t);
+        }
+        prm.insert(prm.end(), p->tparams.begin(), p->tparams.end());
+        prm.resize(tops.size() * svi::kParamStride, 0.0);
+    }
     auto cleanup = [&]() {
         for (auto *d : B->d_items) (void)hipFree(d);
+        for (void *d : B->d_tables) (void)hipFree(d);
         delete B;
     };
+    auto upload = [&](const void *src, size_t bytes) -> void * {
+        void *d = nullptr;
+        if (hipMalloc(&d, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        if (bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return nullptr;
+        }
+        B->d_tables.push_back(d);
+        return d;
+    };
+    svi::BatchTables &T = B->tables;
+    T.arena = arena->d_mem;
+    T.dtype = p0->dtype;
+    T.b = p0->b;
+    T.rb = p0->rb;
+    T.nthr = p0->b - p0->rb;
+    T.passes = upload(passes.data(), passes.size() * sizeof(svi::TilePass));
+    T.stages = upload(stages.data(), stages.size() * sizeof(svi::TileStage));
+    T.ops = upload(tops.data(), tops.size() * sizeof(svi::TileOp));
+    if (p0->dtype == SV_C64) {
+        std::vector<float> f(prm.begin(), prm.end());
+        T.prm = upload(f.data(), f.size() * sizeof(float));
+    } else {
+        T.prm = upload(prm.data(), prm.size() * sizeof(double));
+    }
+    if (!T.passes || !T.stages || !T.ops || !T.prm) {
+        cleanup();
+        return fail(SV_ENOMEM, "upload of the batch tables failed");
+    }
+
     // Groups: instances sorted by state size are packed greedily into groups
     // whose states together stay within group_bytes, so a group that fits the
     // device's last-level cache keeps its states there across its levels; each
@@ -649,37 +717,35 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
         groups.back().push_back(i);
         acc += bytes;
     }
+    const size_t es = esize(p0->dtype);
     for (const auto &grp : groups) {
-      size_t glevels = 0;
-      for (size_t i : grp) glevels = std::max(glevels, plans[i]->steps.size());
-      for (size_t lv = 0; lv < glevels; ++lv) {
-        std::vector<svi::BatchItem> items;
-        uint64_t total = 0;
-        for (size_t i : grp) {
-            const sv_plan *p = plans[i];
-            if (lv >= p->steps.size()) continue;
-            const uint32_t pi = p->steps[lv].index;
-            svi::BatchItem it{};
-            it.psi = states[i]->d_psi;
-            it.pass = (const svi::TilePass *)p->d_passes + pi;
-            it.stages = (const svi::TileStage *)p->d_stages;
-            it.ops = (const svi::TileOp *)p->d_tops;
-            it.prm = p->d_tparams;
-            it.item_begin = total;
-            total += 1ull << p->passes[pi].ntile;
-            items.push_back(it);
+        size_t glevels = 0;
+        for (size_t i : grp) glevels = std::max(glevels, plans[i]->steps.size());
+        for (size_t lv = 0; lv < glevels; ++lv) {
+            std::vector<svi::BatchItem> items;
+            uint64_t total = 0;
+            for (size_t i : grp) {
+                const sv_plan *p = plans[i];
+                if (lv >= p->steps.size()) continue;
+                const uint32_t pi = p->steps[lv].index;
+                svi::BatchItem it{};
+                it.psi_off = (uint64_t)((char *)states[i]->d_psi - (char *)arena->d_mem) / es;
+                it.pass_index = pass_base[i] + pi;
+                it.item_begin = total;
+                total += 1ull << p->passes[pi].ntile;
+                items.push_back(it);
+            }
+            svi::BatchItem *d = nullptr;
+            if (hipMalloc((void **)&d, items.size() * sizeof(svi::BatchItem)) != hipSuccess ||
+                hipMemcpy(d, items.data(), items.size() * sizeof(svi::BatchItem), hipMemcpyHostToDevice) != hipSuccess) {
+                if (d) (void)hipFree(d);
+                cleanup();
+                return fail(SV_ENOMEM, "upload of the batch tables failed");
+            }
+            B->d_items.push_back(d);
+            B->n_items.push_back((uint32_t)items.size());
+            B->total.push_back(total);
         }
-        svi::BatchItem *d = nullptr;
-        if (hipMalloc((void **)&d, items.size() * sizeof(svi::BatchItem)) != hipSuccess ||
-            hipMemcpy(d, items.data(), items.size() * sizeof(svi::BatchItem), hipMemcpyHostToDevice) != hipSuccess) {
-            if (d) (void)hipFree(d);
-            cleanup();
-            return fail(SV_ENOMEM, "upload of the batch tables failed");
-        }
-        B->d_items.push_back(d);
-        B->n_items.push_back((uint32_t)items.size());
-        B->total.push_back(total);
-      }
     }
     B->groups = groups.size();
     *out = B;
@@ -690,8 +756,7 @@ namespace {
 int batch_launch_all(sv_batch *B)
 {
     for (size_t lv = 0; lv < B->d_items.size(); ++lv) {
-        int rc = svi::launch_tile_batch(B->dtype, B->rb, B->b, B->nthr, B->d_items[lv], B->n_items[lv], B->total[lv],
-                                        B->stream);
+        int rc = svi::launch_tile_batch(B->tables, B->d_items[lv], B->n_items[lv], B->total[lv], B->stream);
         if (rc != SV_OK) return fail(rc, "batched launch failed");
     }
     return SV_OK;
@@ -774,6 +839,7 @@ int sv_batch_free(sv_batch *B)
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     for (auto *d : B->d_items) (void)hipFree(d);
+    for (void *d : B->d_tables) (void)hipFree(d);
     delete B;
     return SV_OK;
 }

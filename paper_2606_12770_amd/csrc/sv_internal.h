@@ -41,7 +41,7 @@ int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t
 constexpr int kReduceBlocks = 2048;
 
 // batched tile passes: items of one level, on `stream`
-int launch_tile_batch(int dtype, int rb, int b, int nthr, const BatchItem *d_items, uint32_t n_items,
-                      uint64_t total_work, hipStream_t stream);
+int launch_tile_batch(const BatchTables &tables, const BatchItem *d_items, uint32_t n_items, uint64_t total_work,
+                      hipStream_t stream);
 
 }  // namespace svi

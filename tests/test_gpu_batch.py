@@ -154,6 +154,17 @@ def test_invalid_batches_are_refused():
     with pytest.raises(sv.SVError) as e:
         sv.sv_batch_create([st[0], st[0]], [pa, pa], False)
     assert e.value.code == sv.SV_EINVAL
+    # states outside an arena, or from two arenas, are refused
+    lone = sv.sv_alloc(15, 0)
+    other = sv.sv_alloc_batch([15], 0)
+    pd = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 12, 4)
+    for pair in ([st[0], lone], [st[0], other[0]]):
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_batch_create(pair, [pa, pd], False)
+        assert e.value.code == sv.SV_EINVAL
+    sv.sv_plan_free(pd)
+    sv.sv_free(lone)
+    sv.sv_free(other[0])
     for s in st:
         sv.sv_free(s)
     for p in (pa, pb, pc):
