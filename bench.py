@@ -52,6 +52,24 @@ def cpu_baseline(circ, budget_s: float):
                       f"{dt:.1f} s on {osv.threads()} OpenMP threads"}
 
 
+def measured_traffic(kernel_name, qubits):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3 counter
+    summary (profiles/tile_pass_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by
+    the same counters on the copy kernel), or None when the summary is missing,
+    was taken at another size, or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tile_pass_traffic.json")
+    src = os.path.join(ROOT, "paper_2606_12770_amd", "csrc", "kernels_tile.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel_name or rec.get("qubits") != qubits or rec.get("kernels_tile_sha256") != digest:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def copy_bandwidth(sv, n, reps=10):
     """Best-of-reps device copy of a 2^n complex64 state (16-byte streaming
     kernel), host-timed around the synchronous call: read + write bytes / s."""
@@ -219,6 +237,8 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-carleman", action="store_true")
+    ap.add_argument("--sections", default="small,grid64,batch,dense,largest",
+                    help="comma list of the secondary workloads to run (empty: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
@@ -285,7 +305,7 @@ def main():
     avg_launch_ms = per_step_ms / launches
     achieved = info64["tile_pass_bytes"] / (avg_launch_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_tile_pass<float,4>", n),
             "kernel": "k_tile_pass<float,4>", "launches_per_step": launches,
             "tile_pass_launches_per_step": tile_launches, "avg_launch_us": avg_launch_ms * 1e3}
 
@@ -294,18 +314,24 @@ def main():
     log(f"copy bandwidth {copy_gbs:.0f} GB/s")
 
     carleman = None
-    if not args.skip_carleman:
+    sections = set(x for x in args.sections.split(",") if x) if not args.skip_carleman else set()
+    if sections:
         C64, C128, P, F = sv.SV_C64, sv.SV_C128, sv.SV_MODE_PLAIN, sv.SV_MODE_FUSED
-        carleman = {
-            "small_22q": carleman_ladder(sv, dict(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05), 13, [
+        carleman = {}
+        if "small" in sections:
+            carleman["small_22q"] = carleman_ladder(sv, dict(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05), 13, [
                 ("plain_c128", C128, P, False), ("fused_c128", C128, F, False), ("fused_c64", C64, F, False),
-                ("plain_c128_elementary", C128, P, True), ("fused_c64_elementary", C64, F, True)]),
-            "grid64_31q": carleman_ladder(sv, dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02), 13, [
-                ("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1),
-            "batched_64": batched_carleman(sv),
-        }
-        carleman["dense_block_microbench"] = dense_blocks(sv)
-        carleman["largest_34q"] = largest_state(sv)
+                ("plain_c128_elementary", C128, P, True), ("fused_c64_elementary", C64, F, True)])
+        if "grid64" in sections:
+            carleman["grid64_31q"] = carleman_ladder(
+                sv, dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02), 13,
+                [("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1)
+        if "batch" in sections:
+            carleman["batched_64"] = batched_carleman(sv)
+        if "dense" in sections:
+            carleman["dense_block_microbench"] = dense_blocks(sv)
+        if "largest" in sections:
+            carleman["largest_34q"] = largest_state(sv)
 
     cpu = None
     if not args.skip_cpu:
