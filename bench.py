@@ -314,7 +314,7 @@ def main():
     log(f"copy bandwidth {copy_gbs:.0f} GB/s")
 
     carleman = None
-    sections = set(x for x in args.sections.split(",") if x) if not args.skip_carleman else set()
+    sections = set(x for x in args.sections.strip("=").split(",") if x) if not args.skip_carleman else set()
     if sections:
         C64, C128, P, F = sv.SV_C64, sv.SV_C128, sv.SV_MODE_PLAIN, sv.SV_MODE_FUSED
         carleman = {}

@@ -63,6 +63,8 @@ def random_mixed_circuit(n: int, n_ops: int, seed: int = 0, max_ctrl: int = 4) -
             ctrl = {q: int(rng.integers(0, 2)) for q in qs[2:2 + nc]}
             c.swap(a, b, ctrl)
             continue
+        if kind == 7 and (n < 2 or max_ctrl < 1):
+            kind = 2  # a projector condition needs a qubit besides the signal: a phase instead
         if kind == 7:  # PROJPHASE
             s = qs[0]
             nm = int(rng.integers(1, min(max_ctrl, n - 1) + 1))

@@ -19,34 +19,18 @@ namespace svi {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// Persistent: a workgroup loads its matrix operands once (64 values per lane)
+// and then strides over tiles, so the 8 KiB block matrix is not fetched again
+// for every tile.
 __global__ void __launch_bounds__(256)
-k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats)
+k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats,
+             uint64_t n_tiles)
 {
     extern __shared__ unsigned char smem_raw[];
     float2 *lds = reinterpret_cast<float2 *>(smem_raw);
     const DensePass &D = *dp;
     const TilePass &P = D.map;
     const uint32_t tid = threadIdx.x;
-
-    const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    uint64_t base = 0;
-    for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
-        const uint32_t sh = P.tile_shift[r];
-        base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
-    }
-    uint64_t gthr = 0;
-    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
-        const uint32_t sh = P.gthr_shift[r];
-        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
-    }
-    float2 *const pt = psi + (base | gthr);
-
-    float2 x[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
-    const uint32_t tw = lds_swizzle(tid, 4);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
 
     // A operands of this lane: row c of [G_re | -G_im] and of [G_im | G_re],
     // columns 2 kk + h
@@ -65,40 +49,58 @@ k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const f
             a2[kk] = G[2 * (32 * c + q - 32)];
         }
     }
-    __syncthreads();
-
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
     const uint32_t g = wave * 32u + c;
     uint32_t gl = 0;
     for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
         const uint32_t w = D.grp_run[r];
         gl |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
     }
-    float2 xb[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) xb[i] = lds[lds_swizzle(gl | D.joff[2 * i + h], 4)];
+    const uint32_t tw = lds_swizzle(tid, 4);
 
-    v16f acc_re = {0.f}, acc_im = {0.f};
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
+            const uint32_t sh = P.tile_shift[r];
+            base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
+        }
+        float2 *const pt = psi + (base | gthr);
+        float2 x[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk].x, acc_re, 0, 0, 0);
-        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk].x, acc_im, 0, 0, 0);
+        for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+        __syncthreads();
+
+        float2 xb[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xb[i] = lds[lds_swizzle(gl | D.joff[2 * i + h], 4)];
+        v16f acc_re = {0.f}, acc_im = {0.f};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk].x, acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk].x, acc_im, 0, 0, 0);
+        }
+#pragma unroll
+        for (int kk = 16; kk < 32; ++kk) {
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk - 16].y, acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk - 16].y, acc_im, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            lds[lds_swizzle(gl | D.joff[8u * (t / 4) + 4u * h + (t % 4)], 4)] = make_float2(acc_re[t], acc_im[t]);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 16; ++s) x[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = x[s];
+        __syncthreads();  // the next tile overwrites the LDS
     }
-#pragma unroll
-    for (int kk = 16; kk < 32; ++kk) {
-        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[kk - 16].y, acc_re, 0, 0, 0);
-        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[kk], xb[kk - 16].y, acc_im, 0, 0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const uint32_t i = 8u * (t / 4) + 4u * h + (t % 4);
-        lds[lds_swizzle(gl | D.joff[i], 4)] = make_float2(acc_re[t], acc_im[t]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 16; ++s) x[s] = lds[tw ^ P.swz0[s]];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) pt[P.goff[s]] = x[s];
 }
 
 int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
@@ -106,10 +108,12 @@ int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
     if (p->dtype != SV_C64) return SV_EUNSUPPORTED;
     const DensePass &D = p->dense[di];
     const uint64_t tiles = 1ull << D.map.ntile;
-    const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
-    const uint32_t gy = (uint32_t)(tiles / gx);
-    hipLaunchKernelGGL(k_dense_pass, dim3(gx, gy), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
-                       (const DensePass *)p->d_dense + di, (const float *)p->d_dparams);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t cap = (uint64_t)cus * 2;  // resident workgroups per CU at this kernel's register use
+    const uint32_t grid = (uint32_t)(tiles < cap ? tiles : cap);
+    hipLaunchKernelGGL(k_dense_pass, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                       (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
