@@ -20,11 +20,17 @@ of that (row, column, label) contribution as sin(theta/2) = v / v_max; a final
 X on the target and Hadamards on the label project the sum.  Then
 <row, 0| U |x, 0> = sum_label v / (2^a v_max), so lambda = 2^a v_max.
 
-Periodic boundary (every workload here): streaming is a controlled increment
-or decrement of the site register modulo N_x; no wall flags are needed.
+Streaming.  Periodic walls: a controlled increment (e = +1) or decrement
+(e = -1) of the site register modulo N_x.  Bounce-back walls (Sec. II.A): on
+the pairs (alpha, q' in {0, 1}) streaming is one cycle of length 2 N_x,
+(0,0) -> (1,0) -> ... -> (N_x-1,0) -> (N_x-1,1) -> ... -> (0,1) -> (0,0), so with
+p = alpha + N_x q'_0 after reflecting alpha (alpha -> N_x - 1 - alpha, a bitwise
+NOT) where q' = 1, it is p -> p + 1 modulo 2 N_x: flip alpha where q' = 1,
+increment the contiguous register (alpha, q'_0) where q'_1 = 0, flip back.  The
+rest population q' = 2 does not move.  No wall flags are needed either way.
 
 Register order (qubit 0 = least significant index bit):
-    q1 (2)  alpha1 (n_a)  q2 (2)  alpha2 (n_a)  ord (1)     Carleman index x
+    alpha1 (n_a)  q1 (2)  alpha2 (n_a)  q2 (2)  ord (1)     Carleman index x
     k (n_k)  m (n_m)                                          Taylor / step block
     t (1)                                                     value target
     i1 (2)  case (2)  iL0 (1)                                 label
@@ -125,8 +131,12 @@ class CarlemanConfig:
     amp: float = 0.05    # density perturbation amplitude
     u0: float = 0.0      # uniform initial velocity
     wavenumber: int = 1  # rho0 = 1 + amp sin(2 pi wavenumber alpha / N_x)
+    boundary: str = "periodic"  # or "bounceback"
+    drho: float = 0.0    # > 0: the step initial condition rho0 = 1 +- drho/2 (left / right half), u = 0
 
     def __post_init__(self):
+        if self.boundary not in ("periodic", "bounceback"):
+            raise ValueError("boundary must be 'periodic' or 'bounceback'")
         if self.nx < 2 or self.nx & (self.nx - 1):
             raise ValueError("nx must be a power of two >= 2")
         if self.nt < 1 or self.nt & (self.nt - 1):
@@ -165,10 +175,10 @@ class Layout:
 
     def __post_init__(self):
         p = 0
-        self.q1 = _reg(p, 2); p += 2
         self.a1 = _reg(p, self.n_a); p += self.n_a
-        self.q2 = _reg(p, 2); p += 2
+        self.q1 = _reg(p, 2); p += 2
         self.a2 = _reg(p, self.n_a); p += self.n_a
+        self.q2 = _reg(p, 2); p += 2
         self.ord = p; p += 1
         if self.with_l:
             self.k = _reg(p, self.n_k); p += self.n_k
@@ -203,7 +213,7 @@ class Layout:
 
     def x_index(self, ordv: int, a1: int, q1: int, a2: int = 0, q2: int = 0) -> int:
         na = self.n_a
-        return q1 | (a1 << 2) | (q2 << (2 + na)) | (a2 << (4 + na)) | (ordv << (4 + 2 * na))
+        return a1 | (q1 << na) | (a2 << (na + 2)) | (q2 << (2 * na + 2)) | (ordv << (2 * na + 4))
 
 
 def layout_for(cfg: CarlemanConfig, with_signal: bool = True) -> Layout:
@@ -289,7 +299,25 @@ def a_vmax(tau: float) -> float:
     return max(abs(v) for v, _ in a_values(tau))
 
 
-def emit_a_oracle(c: Circuit, L: Layout, tau: float, ctrl: dict, value_rot) -> None:
+def emit_stream(c: Circuit, a: list[int], q: list[int], ctrl: dict, boundary: str) -> None:
+    """Move the population (alpha, q') by e_q' in place: alpha register a,
+    velocity register q (q' = 0 moves right, 1 left, 2 stays)."""
+    na = len(a)
+    if boundary == "periodic":
+        c.inc(a[0], na, _merge(ctrl, eq(q, 0)))
+        c.dec(a[0], na, _merge(ctrl, eq(q, 1)))
+        return
+    if q[0] != a[-1] + 1:
+        raise ValueError("bounce-back streaming needs q'_0 right above the site register")
+    left = _merge(ctrl, eq(q, 1))
+    for j in range(na):
+        c.x(a[j], left)
+    c.inc(a[0], na + 1, _merge(ctrl, {q[1]: 0}))
+    for j in range(na):
+        c.x(a[j], left)
+
+
+def emit_a_oracle(c: Circuit, L: Layout, tau: float, ctrl: dict, value_rot, boundary: str = "periodic") -> None:
     """The U_A oracle between the label Hadamards: subtractor, value encodings
     (value_rot(v, cond) emits the rotations of one table entry), index updates.
     ctrl is added to every gate."""
@@ -303,20 +331,17 @@ def emit_a_oracle(c: Circuit, L: Layout, tau: float, ctrl: dict, value_rot) -> N
     c0 = _merge(ctrl, eq(L.case, 0))
     c.swap(L.q1[0], L.i1[0], c0)
     c.swap(L.q1[1], L.i1[1], c0)
-    c.inc(L.a1[0], na, _merge(c0, eq(L.q1, 0)))
-    c.dec(L.a1[0], na, _merge(c0, eq(L.q1, 1)))
+    emit_stream(c, L.a1, L.q1, c0, boundary)
     # case 1: copy 2
     c1 = _merge(ctrl, eq(L.case, 1))
     c.swap(L.q2[0], L.i1[0], c1)
     c.swap(L.q2[1], L.i1[1], c1)
-    c.inc(L.a2[0], na, _merge(c1, eq(L.q2, 0)))
-    c.dec(L.a2[0], na, _merge(c1, eq(L.q2, 1)))
+    emit_stream(c, L.a2, L.q2, c1, boundary)
     # case 3: A12 lands in order 1 -> order 0
     c3 = _merge(ctrl, eq(L.case, 3))
     c.swap(L.q1[0], L.i1[0], c3)
     c.swap(L.q1[1], L.i1[1], c3)
-    c.inc(L.a1[0], na, _merge(c3, eq(L.q1, 0)))
-    c.dec(L.a1[0], na, _merge(c3, eq(L.q1, 1)))
+    emit_stream(c, L.a1, L.q1, c3, boundary)
     c.swap(L.i1[1], L.q2[0], c3)
     c.x(L.ord, c3)
 
@@ -327,7 +352,7 @@ def _ry_angle(v: float) -> float:
     return 2.0 * math.asin(max(-1.0, min(1.0, v)))
 
 
-def build_ua(nx: int, tau: float) -> tuple[Circuit, float, Layout]:
+def build_ua(nx: int, tau: float, boundary: str = "periodic") -> tuple[Circuit, float, Layout]:
     """Stand-alone block encoding of A (registers x, t, i1, case): returns the
     circuit, lambda_A = 16 v_max and the layout."""
     L = Layout(nx.bit_length() - 1, 0, 0, with_l=False, with_signal=False)
@@ -339,7 +364,7 @@ def build_ua(nx: int, tau: float) -> tuple[Circuit, float, Layout]:
     def rot(v, cond):
         c.ry(L.t, _ry_angle(v / vmax), cond)
 
-    emit_a_oracle(c, L, tau, {}, rot)
+    emit_a_oracle(c, L, tau, {}, rot, boundary)
     c.x(L.t)
     for q in L.label:
         c.h(q)
@@ -379,7 +404,7 @@ def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
             for mc in m_lt:
                 c.ry(L.t, ang, _merge(cond, eq(L.k, kv), mc))
 
-    emit_a_oracle(c, L, cfg.tau, ctrl, rot)
+    emit_a_oracle(c, L, cfg.tau, ctrl, rot, cfg.boundary)
     c.inc(L.k[0], L.n_k, ctrl)
 
     # diagonal +1
@@ -413,9 +438,13 @@ def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
 # ---- right-hand side and post-selection ------------------------------------------
 
 def initial_populations(cfg: CarlemanConfig) -> np.ndarray:
-    """f(0): equilibrium at rho0 = 1 + amp sin(2 pi wavenumber alpha / N_x), u = u0;
-    shape (N_x, 3)."""
+    """f(0): equilibrium at rho0 = 1 + amp sin(2 pi wavenumber alpha / N_x), u = u0,
+    or with drho > 0 the step of Sec. III.A (rho0 = 1 + drho/2 on the left half,
+    1 - drho/2 on the right, u = 0); shape (N_x, 3)."""
     a = np.arange(cfg.nx)
+    if cfg.drho > 0:
+        rho = np.where(a < cfg.nx // 2, 1.0 + cfg.drho / 2, 1.0 - cfg.drho / 2)
+        return equilibrium(rho, np.zeros(cfg.nx))
     rho = 1.0 + cfg.amp * np.sin(2.0 * np.pi * cfg.wavenumber * a / cfg.nx)
     return equilibrium(rho, np.full(cfg.nx, cfg.u0))
 

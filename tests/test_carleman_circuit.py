@@ -3,7 +3,7 @@ classical matrices of the oracle (block-encoding extraction, the method of
 App. B), the QSVT definition and the classical Taylor solution.
 
 Register order (documented by the generator, restated here independently):
-    q1 (2) alpha1 (n_a) q2 (2) alpha2 (n_a) ord (1) [k (n_k) m (n_m)] t label [s]
+    alpha1 (n_a) q1 (2) alpha2 (n_a) q2 (2) ord (1) [k (n_k) m (n_m)] t label [s]
 so the system register is the lowest n_sys qubits and the ancillas sit above.
 """
 import math
@@ -19,7 +19,7 @@ from paper_2606_12770_amd.circuits import carleman_circuit as cc
 
 def x_reg_index(nx, ordv, a1, q1, a2=0, q2=0):
     na = nx.bit_length() - 1
-    return q1 | (a1 << 2) | (q2 << (2 + na)) | (a2 << (4 + na)) | (ordv << (4 + 2 * na))
+    return a1 | (q1 << na) | (a2 << (na + 2)) | (q2 << (2 * na + 2)) | (ordv << (2 * na + 4))
 
 
 def carleman_to_reg(nx):
@@ -56,10 +56,11 @@ def apply_block(circ, lam, vec_reg, n_low):
     return lam * out[: 1 << n_low]
 
 
+@pytest.mark.parametrize("boundary", ["periodic", "bounceback"])
 @pytest.mark.parametrize("nx,tau", [(2, 0.8), (4, 1.0), (4, 0.6), (8, 1.3)])
-def test_ua_encodes_carleman_matrix(nx, tau):
-    circ, lam, L = cc.build_ua(nx, tau)
-    A = oc.carleman_matrix(nx, tau, 2).toarray()
+def test_ua_encodes_carleman_matrix(nx, tau, boundary):
+    circ, lam, L = cc.build_ua(nx, tau, boundary)
+    A = oc.carleman_matrix(nx, tau, 2, boundary).toarray()
     idx = carleman_to_reg(nx)
     n_x = L.n_x
     rng = np.random.default_rng(nx)
@@ -80,12 +81,14 @@ def test_ua_encodes_carleman_matrix(nx, tau):
         assert np.max(np.abs(got_u[idx])) < 1e-13
 
 
-@pytest.mark.parametrize("nx,tau,nk,nt", [(2, 1.0, 1, 1), (2, 0.7, 2, 2), (4, 0.9, 3, 1), (4, 1.2, 1, 2)])
-def test_ul_encodes_taylor_matrix(nx, tau, nk, nt):
-    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1)
+@pytest.mark.parametrize("nx,tau,nk,nt,boundary", [(2, 1.0, 1, 1, "periodic"), (2, 0.7, 2, 2, "periodic"),
+                                                     (4, 0.9, 3, 1, "periodic"), (4, 1.2, 1, 2, "periodic"),
+                                                     (4, 0.8, 2, 2, "bounceback"), (2, 0.094, 3, 4, "bounceback")])
+def test_ul_encodes_taylor_matrix(nx, tau, nk, nt, boundary):
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, boundary=boundary)
     enc = cc.build_ul(cfg, with_signal=False)
     L = enc.layout
-    A = oc.carleman_matrix(nx, tau, 2)
+    A = oc.carleman_matrix(nx, tau, 2, boundary)
     Lm = oc.l_matrix(A, cfg.dt, nt, nk, L.n_m, L.n_k).toarray()
     idx = system_to_reg(nx, nt, nk, L.n_k, L.n_m)
     n_sys = L.n_sys
@@ -180,6 +183,33 @@ def test_rhs_block_is_normalised_carleman_vector():
     mask = np.ones(len(blk), bool)
     mask[idx] = False
     assert np.all(blk[mask] == 0)
+
+
+def test_bounceback_streaming_is_the_wall_reflecting_cycle():
+    """The folded increment alone (no values): on (alpha, q' in {0, 1}) it is the
+    cycle (0,0) -> ... -> (N-1,0) -> (N-1,1) -> ... -> (0,1) -> (0,0); q' = 2 and
+    q' = 3 stay."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    for na in (1, 2, 3):
+        N = 1 << na
+        a = list(range(na))
+        q = [na, na + 1]
+        c = Circuit(na + 2)
+        cc.emit_stream(c, a, q, {}, "bounceback")
+        for alpha in range(N):
+            for qp in range(4):
+                psi = np.zeros(1 << (na + 2), dtype=np.complex128)
+                psi[alpha | (qp << na)] = 1.0
+                out = osv.run(c, psi)
+                j = int(np.argmax(np.abs(out)))
+                ga, gq = j & (N - 1), j >> na
+                if qp == 0:
+                    want = (alpha + 1, 0) if alpha < N - 1 else (N - 1, 1)
+                elif qp == 1:
+                    want = (alpha - 1, 1) if alpha > 0 else (0, 0)
+                else:
+                    want = (alpha, qp)
+                assert (ga, gq) == want and abs(out[j]) == 1.0
 
 
 def test_qubit_counts_of_workloads():

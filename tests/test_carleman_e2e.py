@@ -22,9 +22,10 @@ from tests.test_carleman_circuit import carleman_to_reg, system_to_reg
 
 
 def classical_setup(cfg, L):
-    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2)
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2, cfg.boundary)
     Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
-    f0 = oc.initial_f1(cfg.nx, cfg.amp, cfg.u0, cfg.wavenumber)
+    f0 = (oc.step_function_f1(cfg.nx, cfg.drho) if cfg.drho > 0
+          else oc.initial_f1(cfg.nx, cfg.amp, cfg.u0, cfg.wavenumber))
     y0 = oc.carleman_vector(f0)
     b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
     b = b / np.linalg.norm(b)
@@ -32,9 +33,13 @@ def classical_setup(cfg, L):
     return Lm, b, x, f0
 
 
-@pytest.mark.parametrize("nx,nk,nt,tau", [(2, 1, 1, 0.9), pytest.param(4, 1, 1, 1.0, marks=pytest.mark.slow)])
-def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau):
-    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, amp=0.1)
+@pytest.mark.parametrize("nx,nk,nt,tau,boundary,drho", [
+    (2, 1, 1, 0.9, "periodic", 0.0),
+    (2, 1, 1, 0.7, "bounceback", 0.4),
+    pytest.param(4, 1, 1, 1.0, "periodic", 0.0, marks=pytest.mark.slow),
+    pytest.param(4, 1, 1, 0.8, "bounceback", 0.6, marks=pytest.mark.slow)])
+def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho):
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, amp=0.1, boundary=boundary, drho=drho)
     enc = cc.build_ul(cfg)
     L = enc.layout
     Lm, b, x, f0 = classical_setup(cfg, L)

@@ -33,12 +33,12 @@ def carleman_to_reg(nx):
     na = nx.bit_length() - 1
     a = np.arange(nx)
     q = np.arange(3)
-    f1 = (q[None, :] | (a[:, None] << 2)).reshape(-1)             # index 3 a + q
+    f1 = (a[:, None] | (q[None, :] << na)).reshape(-1)             # index 3 a + q
     i = np.arange(3 * nx)
     ai, qi = i // 3, i % 3
-    first = qi | (ai << 2)
-    second = (qi << (2 + na)) | (ai << (4 + na))
-    f2 = (first[:, None] | second[None, :] | (1 << (4 + 2 * na))).reshape(-1)
+    first = ai | (qi << na)
+    second = (ai << (na + 2)) | (qi << (2 * na + 2))
+    f2 = (first[:, None] | second[None, :] | (1 << (2 * na + 4))).reshape(-1)
     return np.concatenate([f1, f2]).astype(np.int64)
 
 

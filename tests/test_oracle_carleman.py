@@ -160,3 +160,16 @@ def test_matrix_free_products_match_explicit_matrices(nx, tau):
     x = rng.standard_normal(Lm.shape[0])
     got = oc.l_apply(lambda v: oc.carleman_apply(nx, tau, v), x, 0.1, nt, nk, n_m, n_k, A.shape[0])
     assert np.max(np.abs(got - Lm @ x)) < 1e-12
+
+
+def test_kappa_second_order_qsvt_run():
+    """Sec. III.E.2: N_C = 2, Nx = 8, N_t = 4, N_K = 3, dt = 0.1, nu = 2 (tau =
+    0.094), bounce-back: kappa about 7100, with lambda_L = 2^5 L_max and
+    L_max = max(1, dt max|A_ij|) (max|A_ij| = 1/tau, an A12 entry)."""
+    nx, nt, nk, dt = 8, 4, 3, 0.1
+    tau = oc.tau_from_nu(nx, 2.0)
+    A = oc.carleman_matrix(nx, tau, 2, "bounceback")
+    L = oc.l_matrix(A, dt, nt, nk, 3, 2)
+    lam = 32.0 * max(1.0, dt * abs(A).max())
+    kappa = lam / oc.sigma_min(L)
+    assert 6900 < kappa < 7300, kappa
