@@ -15,6 +15,7 @@ cites):
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft as sfft
 
 
 def qsp_unitary(phases, x: float) -> np.ndarray:
@@ -81,13 +82,14 @@ def qsp_poly_batch(phases, xs) -> np.ndarray:
 
 def odd_chebyshev_of_qsp(phases) -> np.ndarray:
     """Coefficients of T_1, T_3, ..., T_d of Re p for odd d = len(phases) - 1,
-    by interpolation at d + 1 Gauss-Chebyshev nodes."""
+    by interpolation at the d + 1 Gauss-Chebyshev nodes x_k = cos theta_k:
+    c_n = (2 / N) sum_k Re p(x_k) cos(n theta_k), N = d + 1, which is a DCT-II
+    of the node values (the library transform keeps large d in memory)."""
     d = len(phases) - 1
     N = d + 1
     x = np.cos(np.pi * (2 * np.arange(N) + 1) / (2 * N))
     g = qsp_poly_batch(phases, x).real
-    js = np.arange(1, d + 1, 2)
-    return (2.0 / N) * (np.cos(np.outer(js, np.arccos(x))) @ g)
+    return (sfft.dct(g, type=2) / N)[1:d + 1:2]
 
 
 def odd_sv_apply(matvec, rmatvec, coefs, b) -> np.ndarray:

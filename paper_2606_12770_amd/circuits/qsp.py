@@ -24,23 +24,33 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.fft as sfft
 
 
 def _cheb_nodes(N: int) -> np.ndarray:
     return np.cos(np.pi * (2 * np.arange(N) + 1) / (2 * N))
 
 
+def _grid_size(d: int) -> int:
+    return 1 << max(4, math.ceil(math.log2(4 * (d + 1))))
+
+
 def odd_chebyshev_coefficients(fun, d: int, N: int | None = None) -> np.ndarray:
     """Coefficients c_j of T_{2j+1}, j = 0..(d-1)/2, of the Chebyshev
-    interpolant of fun at N Gauss-Chebyshev nodes (N >= d + 1)."""
+    interpolant of fun at N Gauss-Chebyshev nodes (N >= d + 1), by a DCT-II:
+    c_n = (2 / N) sum_k fun(x_k) cos(n theta_k), x_k = cos theta_k."""
     if d % 2 == 0:
         raise ValueError("degree must be odd")
-    N = N or 1 << max(4, math.ceil(math.log2(4 * (d + 1))))
-    x = _cheb_nodes(N)
-    th = np.arccos(x)
-    g = fun(x)
-    js = np.arange(1, d + 1, 2)
-    return (2.0 / N) * (np.cos(np.outer(js, th)) @ g)
+    N = N or _grid_size(d)
+    y = sfft.dct(fun(_cheb_nodes(N)), type=2) / N
+    return y[1:d + 1:2].copy()
+
+
+def odd_values_on_nodes(coefs: np.ndarray, N: int) -> np.ndarray:
+    """sum_j coefs_j T_{2j+1}(x_k) at the N Gauss-Chebyshev nodes x_k (DCT-III)."""
+    a = np.zeros(N)
+    a[1:2 * len(coefs):2] = coefs
+    return sfft.dct(a, type=3) / 2.0
 
 
 def chebyshev_odd_eval(coefs: np.ndarray, x) -> np.ndarray:
@@ -51,10 +61,15 @@ def chebyshev_odd_eval(coefs: np.ndarray, x) -> np.ndarray:
 
 def inverse_polynomial(kappa: float, d: int, peak: float = 0.5, n_beta: int = 24):
     """Odd Chebyshev coefficients of the degree-d approximation of c / x on
-    [1/kappa, 1].  Returns (coefs, c, max relative error on [1/kappa, 1])."""
+    [1/kappa, 1].  Returns (coefs, c, max relative error on [1/kappa, 1]).
+    Maximum and error are taken on a Gauss-Chebyshev grid of at least 16 (d + 1)
+    points (spacing near x = 0 about a tenth of the polynomial's oscillation
+    length 1/d)."""
     if d % 2 == 0:
         raise ValueError("degree must be odd")
-    xs = np.linspace(1.0 / kappa, 1.0, 4000)
+    N = max(1 << 15, 1 << math.ceil(math.log2(16 * (d + 1))))
+    x = _cheb_nodes(N)
+    inside = x >= 1.0 / kappa
     best = None
     for beta in kappa * np.linspace(1.0, 6.0, n_beta):
         def f(x, beta=beta):
@@ -65,19 +80,18 @@ def inverse_polynomial(kappa: float, d: int, peak: float = 0.5, n_beta: int = 24
             xb = x[~small]
             out[~small] = -np.expm1(-(beta * xb) ** 2) / xb
             return out
-        co = odd_chebyshev_coefficients(f, d)
-        dense = np.linspace(0.0, 1.0, 20001)
-        mx = np.max(np.abs(chebyshev_odd_eval(co, dense)))
-        scale = peak / mx
+        co = odd_chebyshev_coefficients(f, d, N)
+        vals = odd_values_on_nodes(co, N)
+        scale = peak / np.max(np.abs(vals))
         co = co * scale
-        err = np.max(np.abs(chebyshev_odd_eval(co, xs) * xs / scale - 1.0))
+        err = np.max(np.abs(vals[inside] * x[inside] - 1.0))
         if best is None or err < best[2]:
             best = (co, scale, err)
     return best
 
 
 def qsp_real_part(phases: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """Re <0|U(x)|0> for all x at once (row vector recursion)."""
+    """Re <0|U(x)|0> for all x at once (row vector recursion, O(d) per point)."""
     x = np.asarray(x, float)
     s = np.sqrt(np.clip(1.0 - x * x, 0.0, None))
     e0 = np.exp(1j * phases[0])
@@ -92,6 +106,53 @@ def qsp_real_part(phases: np.ndarray, x: np.ndarray) -> np.ndarray:
     return r0.real
 
 
+def qsp_chebyshev(phases: np.ndarray) -> np.ndarray:
+    """Chebyshev coefficients p_0..p_d (complex) of p(x) = <0|U(x)|0>.
+
+    With x = cos theta, W(x) = [[cos, i sin], [i sin, cos]](theta), so every
+    factor W e^{i phi_j Z} is a trigonometric polynomial of degree 1 in theta
+    and a product of m factors one of degree m.  The product is formed by
+    pairwise halving: a segment of degree m is held by its values at 4m
+    equispaced theta; two neighbours are resampled to 8m points (FFT, zero
+    padding, inverse FFT) and multiplied point by point.  O(d log^2 d) work;
+    every intermediate is a unitary matrix, so values stay bounded.  Finally
+    p(cos theta) = p_0 + sum_k p_k cos(k theta) gives p_k = 2 c_k (k >= 1)
+    from the Fourier coefficients c_k of the (even) function theta -> U_00."""
+    phases = np.asarray(phases, float)
+    d = len(phases) - 1
+    if d < 1:
+        return np.array([np.exp(1j * phases[0])])
+    S = 4
+    th = 2.0 * np.pi * np.arange(S) / S
+    c, s = np.cos(th), np.sin(th)
+    e = np.exp(1j * phases[1:])[:, None]
+    ec = np.conj(e)
+    M = np.empty((4, d, S), dtype=np.complex128)      # entries 00, 01, 10, 11
+    M[0] = c * e
+    M[1] = 1j * s * ec
+    M[2] = 1j * s * e
+    M[3] = c * ec
+    while M.shape[1] > 1:
+        if M.shape[1] % 2:
+            eye = np.zeros((4, 1, S), dtype=np.complex128)
+            eye[0] = eye[3] = 1.0
+            M = np.concatenate([M, eye], axis=1)
+        F = np.fft.fft(M, axis=-1)
+        G = np.zeros(M.shape[:2] + (2 * S,), dtype=np.complex128)
+        h = S // 2
+        G[..., :h] = F[..., :h]
+        G[..., -h:] = F[..., -h:]
+        V = np.fft.ifft(G, axis=-1) * 2.0
+        A, B = V[:, 0::2], V[:, 1::2]
+        M = np.stack([A[0] * B[0] + A[1] * B[2], A[0] * B[1] + A[1] * B[3],
+                      A[2] * B[0] + A[3] * B[2], A[2] * B[1] + A[3] * B[3]])
+        S *= 2
+    four = np.fft.fft(np.exp(1j * phases[0]) * M[0, 0]) / S
+    p = 2.0 * four[:d + 1]
+    p[0] = four[0]
+    return p
+
+
 def full_phases(reduced: np.ndarray) -> np.ndarray:
     """Symmetric d + 1 phases (d odd) from the reduced ones, with the pi/4 ends."""
     phi = np.concatenate([reduced[::-1], reduced])
@@ -104,15 +165,10 @@ def solve_phases(coefs: np.ndarray, tol: float = 1e-13, max_iter: int = 500):
     """Fixed-point iteration for the phases of Re p = sum_j coefs_j T_{2j+1}.
     Returns (phases, iterations, final coefficient residual)."""
     dt = len(coefs)
-    d = 2 * dt - 1
-    N = 2 * dt
-    x = _cheb_nodes(N)
-    th = np.arccos(x)
-    T = np.cos(np.outer(np.arange(1, d + 1, 2), th)) * (2.0 / N)
     psi = np.zeros(dt)
     res = np.inf
     for it in range(1, max_iter + 1):
-        F = T @ qsp_real_part(full_phases(psi), x)
+        F = qsp_chebyshev(full_phases(psi))[1::2].real
         r = F - coefs
         res = float(np.max(np.abs(r)))
         if res < tol:

@@ -4,9 +4,11 @@
   ladder at d = 13 against the FP64 reference simulator, in the native gate IR
   and lowered to single-qubit + multi-controlled X / phase gates, complex128
   (per-gate and fused) and complex64 (fused).
-* The same instance at the working degree d = 10 kappa + 1: the post-selected
-  amplitudes against the classical singular-value transform of the same
-  phases, and the final-time rows against the classical Taylor solution.
+* The same instance at the working degree d = 10 kappa + 1, with periodic
+  boundaries and with bounce-back walls (step initial condition): the
+  post-selected amplitudes against the classical singular-value transform of
+  the same phases, and the final-time rows against the classical Taylor
+  solution.
 * Full-size workloads (31 and 34 qubits, complex64): one call of U_L on b with
   the ancillas projected out must equal L b / lambda_L on every system
   amplitude (the block-encoding property, exact at any size), with the
@@ -92,19 +94,21 @@ def test_c1_ladder_matches_oracle(form, dtype, mode):
         assert f < 1e-6
 
 
+@pytest.mark.parametrize("boundary", ["periodic", "bounceback"])
 @pytest.mark.parametrize("dtype", [1, 0])
-def test_c1_working_degree_physics(dtype):
+def test_c1_working_degree_physics(dtype, boundary):
     sv = require_gpu()
-    cfg = cc.CarlemanConfig(**C1)
+    extra = dict(boundary="bounceback", drho=0.4) if boundary == "bounceback" else {}
+    cfg = cc.CarlemanConfig(**C1, **extra)
     enc = cc.build_ul(cfg)
     L = enc.layout
-    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2)
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2, cfg.boundary)
     Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
     kappa = enc.lam / oc.sigma_min(Lm)
     d = qsp.qsvt_degree(kappa)
     phases, _c, _info = qsp.inversion_phases(kappa, d)
     circ = cc.build_qsvt(enc, phases)
-    print(f"C1 working degree: kappa={kappa:.1f} d={d} ops={len(circ)} dtype={dtype}", flush=True)
+    print(f"C1 {boundary} working degree: kappa={kappa:.1f} d={d} ops={len(circ)} dtype={dtype}", flush=True)
 
     st = sv.State(L.n, dtype)
     sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
@@ -118,7 +122,7 @@ def test_c1_working_degree_physics(dtype):
     st.close()
     plan.close()
 
-    f0 = oc.initial_f1(cfg.nx, cfg.amp)
+    f0 = oc.step_function_f1(cfg.nx, cfg.drho) if cfg.drho > 0 else oc.initial_f1(cfg.nx, cfg.amp)
     y0 = oc.carleman_vector(f0)
     b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
     b /= np.linalg.norm(b)

@@ -64,3 +64,37 @@ def test_degree_rule():
     assert qsp.qsvt_degree(88.1) == 883
     assert qsp.qsvt_degree(100.0) == 1001
     assert qsp.qsvt_degree(100.0) % 2 == 1
+
+
+@pytest.mark.parametrize("d", [1, 3, 101, 1001])
+def test_fft_product_matches_oracle_matrix_products(d):
+    """The pairwise-halving FFT product of the QSP factors against the oracle's
+    plain 2x2 products at random points, for random phases."""
+    rng = np.random.default_rng(d)
+    ph = rng.uniform(-np.pi, np.pi, d + 1)
+    p = qsp.qsp_chebyshev(ph)
+    xs = rng.uniform(-1.0, 1.0, 7)
+    th = np.arccos(xs)
+    got = np.cos(np.multiply.outer(th, np.arange(d + 1))) @ p
+    want = oq.qsp_poly(ph, xs)
+    assert np.max(np.abs(got - want)) < 1e-13 * max(1, np.log2(d + 1))
+    # parity of a degree-d QSP polynomial: only T_k with k = d mod 2
+    assert np.max(np.abs(p[(d + 1) % 2::2])) < 1e-13
+
+
+def test_phase_solver_at_the_second_order_paper_degree():
+    """kappa = 7100 (the second-order run of Sec. III.E): d = 71001 phases in
+    seconds; at 64 sampled points the oracle's plain 2x2 products of those
+    phases give the target polynomial and c / x to the approximation error."""
+    kappa, d = 7100.0, 71001
+    coefs, c, err = qsp.inverse_polynomial(kappa, d)
+    assert err < 5e-3
+    phases, it, res = qsp.solve_phases(coefs)
+    assert len(phases) == d + 1 and res < 1e-12
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.uniform(1.0 / kappa, 1.0, 60), [1.0 / kappa, 2.0 / kappa, 0.5, 1.0]])
+    got = oq.qsp_poly_batch(phases, xs).real
+    want = oq.chebyshev_eval(coefs, xs)
+    # bound: (d + 1) / 2 coefficients each off by at most the residual
+    assert np.max(np.abs(got - want)) < (d + 1) / 2 * res + 1e-11
+    assert np.max(np.abs(got * xs / c - 1.0)) < 5e-3
