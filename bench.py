@@ -224,6 +224,64 @@ def largest_state(sv, d=1, reps=1):
     return out
 
 
+def paper_instance(sv, dtypes=("c64", "c128")):
+    """The second-order verification run of Sec. III.E at its printed degree
+    (N_x = 8, N_t = 4, N_K = 3, dt = 0.1, nu = 2, bounce-back, drho = 1.2,
+    kappa_QSVT = 7100, d = 71001): the whole ladder, one fused plan, timed once
+    per precision with HIP events; host setup (phases, ladder arrays, plan)
+    timed apart.  The two precisions are compared with each other (infidelity
+    of the system amplitudes with the ancillas and the signal at 0)."""
+    import numpy as np
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc, qsp
+    cfg, kappa_q, d = cc.paper_second_order_instance()
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    t0 = time.time()
+    coefs, c, err = qsp.inverse_polynomial(kappa_q, d)
+    phases, it, res = qsp.solve_phases(coefs)
+    t_phase = time.time() - t0
+    t0 = time.time()
+    ops, params = cc.build_qsvt_arrays(enc, phases)
+    t_arrays = time.time() - t0
+    log(f"paper instance: {L.n} qubits, d = {d}, {len(ops)} ops; phases {t_phase:.1f} s, arrays {t_arrays:.1f} s")
+    out = {"qubits": L.n, "degree": d, "kappa_qsvt": kappa_q, "ops_native": int(len(ops)),
+           "config": {"nx": cfg.nx, "nt": cfg.nt, "nk": cfg.nk, "dt": cfg.dt, "tau": cfg.tau,
+                      "boundary": cfg.boundary, "drho": cfg.drho},
+           "setup_s": {"phases": t_phase, "ladder_arrays": t_arrays},
+           "polynomial_rel_err": err, "phase_residual": res}
+    amps = {}
+    for name in dtypes:
+        dt = sv.SV_C64 if name == "c64" else sv.SV_C128
+        t0 = time.time()
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED)
+        t_plan = time.time() - t0
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(L.n, dt)
+        sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
+        t0 = time.time()
+        ms = sv.sv_plan_time(plan, st, 1)
+        wall = time.time() - t0
+        norm2 = sv.sv_postselect(st, 0, 0, keep=False, renormalize=False)
+        amps[name] = sv.sv_amplitudes(st, 0, 1 << L.n_sys)
+        fmask, fval = cc.postselect_condition(L)
+        P_final = sv.sv_postselect(st, fmask, fval, keep=False, renormalize=False)
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+        gb = info["bytes_moved"] / (ms / 1e3) / 1e9
+        out[name] = {"plan_s": t_plan, "gpu_ms": ms, "gpu_wall_s": wall, "gates_per_s": len(ops) / (ms / 1e3),
+                     "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
+                     "GBps_algorithmic": gb, "norm_drift": abs(norm2 - 1.0),
+                     "postselect_prob_final_rows": P_final}
+        log(f"paper instance {name}: plan {t_plan:.1f} s, GPU {ms / 1e3:.2f} s ({len(ops) / ms * 1e3:.3g} gates/s, "
+            f"{info['n_tile_passes']} passes, {gb:.0f} GB/s), norm drift {abs(norm2 - 1):.2e}, P_final {P_final:.3e}")
+    if "c64" in amps and "c128" in amps:
+        a, b = amps["c64"], amps["c128"]
+        out["infidelity_c64_vs_c128"] = float(1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
+        log(f"paper instance: infidelity c64 vs c128 {out['infidelity_c64_vs_c128']:.2e}")
+    out["context"] = "Sec. III.E reports about 53 h on one H100 for this run (its circuit: 27 qubits)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,7 +296,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-carleman", action="store_true")
     ap.add_argument("--sections", default="small,grid64,batch,dense,largest",
-                    help="comma list of the secondary workloads to run (empty: none)")
+                    help="comma list of the secondary workloads to run (empty: none); "
+                         "'paper' adds the full-degree second-order run (about 2 minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
@@ -332,6 +391,8 @@ def main():
             carleman["dense_block_microbench"] = dense_blocks(sv)
         if "largest" in sections:
             carleman["largest_34q"] = largest_state(sv)
+        if "paper" in sections:
+            carleman["paper_instance_23q"] = paper_instance(sv)
 
     cpu = None
     if not args.skip_cpu:

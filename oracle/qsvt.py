@@ -14,6 +14,8 @@ cites):
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 import scipy.fft as sfft
 
@@ -80,6 +82,19 @@ def qsp_poly_batch(phases, xs) -> np.ndarray:
     return row0
 
 
+def qsp_poly_points(phases, xs) -> np.ndarray:
+    """p(x) for an array of x by the same left-to-right 2x2 products as
+    qsp_poly_batch, in the oracle's C library (points in parallel)."""
+    from . import statevector as _sv
+    ph = np.ascontiguousarray(phases, dtype=np.float64)
+    xs = np.ascontiguousarray(xs, dtype=np.float64)
+    out = np.empty(len(xs), dtype=np.complex128)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _sv.lib().oracle_qsp_poly(ph.ctypes.data_as(dp), len(ph) - 1, xs.ctypes.data_as(dp), len(xs),
+                              out.ctypes.data_as(dp))
+    return out
+
+
 def odd_chebyshev_of_qsp(phases) -> np.ndarray:
     """Coefficients of T_1, T_3, ..., T_d of Re p for odd d = len(phases) - 1,
     by interpolation at the d + 1 Gauss-Chebyshev nodes x_k = cos theta_k:
@@ -88,7 +103,7 @@ def odd_chebyshev_of_qsp(phases) -> np.ndarray:
     d = len(phases) - 1
     N = d + 1
     x = np.cos(np.pi * (2 * np.arange(N) + 1) / (2 * N))
-    g = qsp_poly_batch(phases, x).real
+    g = qsp_poly_points(phases, x).real
     return (sfft.dct(g, type=2) / N)[1:d + 1:2]
 
 

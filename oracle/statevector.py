@@ -31,6 +31,8 @@ def lib():
         L.oracle_postselect.restype = ctypes.c_double
         L.oracle_inner.argtypes = [dp, dp, ctypes.c_int, dp]
         L.oracle_inner.restype = None
+        L.oracle_qsp_poly.argtypes = [dp, ctypes.c_uint64, dp, ctypes.c_uint64, dp]
+        L.oracle_qsp_poly.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
         _lib = L

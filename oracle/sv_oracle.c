@@ -233,3 +233,36 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * QSP polynomial p(x) = <0| e^{i phi_0 Z} W(x) e^{i phi_1 Z} ... W(x) e^{i phi_d Z} |0>
+ * with W(x) = [[x, i s], [i s, x]], s = sqrt(1 - x^2) (the W_x convention of
+ * the QSVT construction, Sec. II.D.5), at n_x points: the first row of the
+ * running product of the 2x2 matrices, left to right, one point per loop
+ * iteration.  phases has d + 1 entries; out holds n_x complex values.
+ */
+void oracle_qsp_poly(const double *phases, uint64_t d, const double *x, uint64_t n_x, double *out_d)
+{
+    cplx *out = (cplx *)out_d;
+    cplx *e = (cplx *)malloc((d + 1) * sizeof(cplx));
+    if (!e) {
+        for (uint64_t k = 0; k < n_x; ++k) out[k] = NAN;
+        return;
+    }
+    for (uint64_t j = 0; j <= d; ++j) e[j] = cexp(I * phases[j]);
+#pragma omp parallel for schedule(static)
+    for (int64_t kk = 0; kk < (int64_t)n_x; ++kk) {
+        const double xv = x[kk];
+        const double s = sqrt(fmax(0.0, 1.0 - xv * xv));
+        cplx r0 = e[0], r1 = 0.0;
+        for (uint64_t j = 1; j <= d; ++j) {
+            /* [r0, r1] . W(x) . diag(e^{i phi_j}, e^{-i phi_j}) */
+            const cplx n0 = (r0 * xv + r1 * (I * s)) * e[j];
+            const cplx n1 = (r0 * (I * s) + r1 * xv) * conj(e[j]);
+            r0 = n0;
+            r1 = n1;
+        }
+        out[kk] = r0;
+    }
+    free(e);
+}

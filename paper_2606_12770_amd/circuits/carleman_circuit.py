@@ -435,6 +435,21 @@ def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
     return LEncoding(c, 32.0 * lmax, lmax, vmax, L)
 
 
+def tau_from_nu(nx: int, nu: float) -> float:
+    """Relaxation time of the lattice units used in Sec. III (Eq. tau-nu):
+    tau = (N_x / 512) nu / c_s^2, c_s^2 = 1/3."""
+    return (nx / 512.0) * nu * 3.0
+
+
+def paper_second_order_instance() -> tuple[CarlemanConfig, float, int]:
+    """The second-order verification run of Sec. III.E: N_x = 8, N_t = 4,
+    N_K = 3, dt = 0.1, nu = 2, bounce-back walls, step drho = 1.2; returns
+    (config, kappa_QSVT = 7100, d = 71001) as printed there."""
+    cfg = CarlemanConfig(nx=8, tau=tau_from_nu(8, 2.0), nk=3, nt=4, dt=0.1,
+                         boundary="bounceback", drho=1.2)
+    return cfg, 7100.0, 71001
+
+
 # ---- right-hand side and post-selection ------------------------------------------
 
 def initial_populations(cfg: CarlemanConfig) -> np.ndarray:
@@ -529,6 +544,50 @@ def build_qsvt(enc: LEncoding, phases: np.ndarray, ul: Circuit | None = None,
     return c
 
 
+def build_qsvt_arrays(enc: LEncoding, phases: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """The ladder of build_qsvt as (ops, params) arrays, for degrees where a
+    per-op Python list would not fit: the U_L and U_L^dagger records are tiled
+    with numpy and every copy reads the same parameter block (parameter
+    offsets may alias); only the d + 1 projector phases get parameters of
+    their own.  The op sequence is the one build_qsvt emits."""
+    L = enc.layout
+    if L.s < 0:
+        raise ValueError("the layout has no signal qubit")
+    d = len(phases) - 1
+    if d < 1 or d % 2 == 0:
+        raise ValueError("the QSVT degree must be odd")
+    mask = 0
+    for q in L.ancillas:
+        mask |= 1 << q
+    head = Circuit(L.n)
+    head.h(L.s)
+    head.phase(L.s, np.pi)
+    tail = Circuit(L.n)
+    tail.h(L.s)
+    proj = Circuit(L.n)
+    proj.projphase(L.s, mask, 0, 0.0)
+    parts = [head.arrays(), tail.arrays(), enc.circuit.arrays(), enc.circuit.dagger().arrays()]
+    offs = np.cumsum([0] + [len(p) for _o, p in parts])
+    rebased = []
+    for (o, _p), off in zip(parts, offs):
+        o = o.copy()
+        o["param"] += np.uint64(off)
+        rebased.append(o)
+    (h_ops, t_ops, ul_ops, dg_ops) = rebased
+    ang_off = int(offs[-1])
+    params = np.concatenate([p for _o, p in parts] + [np.asarray(projector_angles(phases))])
+    pr = proj.arrays()[0]
+    unit = np.concatenate([pr, dg_ops, pr, ul_ops])
+    npair = (d - 1) // 2
+    ops = np.concatenate([h_ops, np.tile(unit, npair), pr, dg_ops, pr, t_ops])
+    # projector j sits at 1 + j (len(U) + 1) after the head
+    pos = len(h_ops) + np.arange(d + 1, dtype=np.int64) * (len(ul_ops) + 1)
+    if not np.all(ops["kind"][pos] == PROJPHASE):
+        raise AssertionError("projector positions")
+    ops["param"][pos] = ang_off + np.arange(d + 1, dtype=np.uint64)
+    return ops, params
+
+
 # ---- lowering to 1-qubit + multi-controlled X / phase gates ------------------------
 
 def lower_to_elementary(circ: Circuit) -> Circuit:
@@ -585,5 +644,6 @@ __all__ = [
     "CarlemanConfig", "Layout", "LEncoding", "collision_values", "kernel12", "equilibrium",
     "layout_for", "eq", "lt", "a_values", "a_vmax", "emit_a_oracle", "build_ua", "build_ul",
     "initial_populations", "rhs_x_block", "postselect_condition", "projector_angles", "build_qsvt",
+    "build_qsvt_arrays", "tau_from_nu", "paper_second_order_instance",
     "lower_to_elementary", "qubit_count", "U", "X", "PHASE",
 ]

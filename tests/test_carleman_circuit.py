@@ -216,3 +216,22 @@ def test_qubit_counts_of_workloads():
     assert cc.qubit_count(cc.CarlemanConfig(nx=8, nk=2, nt=2)) == 22
     assert cc.qubit_count(cc.CarlemanConfig(nx=64, tau=0.8, nk=4, nt=8)) == 31
     assert cc.qubit_count(cc.CarlemanConfig(nx=256, tau=0.8, nk=4, nt=4)) == 34
+
+
+@pytest.mark.parametrize("d", [1, 3, 9])
+def test_ladder_arrays_equal_the_ladder_circuit(d):
+    """The tiled ladder with shared parameter blocks is op for op, parameter
+    for parameter, the ladder build_qsvt emits."""
+    cfg = cc.CarlemanConfig(nx=4, tau=0.9, nk=1, nt=1, boundary="bounceback")
+    enc = cc.build_ul(cfg)
+    rng = np.random.default_rng(d)
+    ph = rng.uniform(-np.pi, np.pi, d + 1)
+    ref_ops, ref_prm = cc.build_qsvt(enc, ph).arrays()
+    ops, prm = cc.build_qsvt_arrays(enc, ph)
+    assert len(ops) == len(ref_ops)
+    for f in ("kind", "target", "width", "flags", "ctrl_mask", "ctrl_val"):
+        assert np.array_equal(ops[f], ref_ops[f]), f
+    npar = {0: 8, 2: 1, 3: 1, 7: 1}
+    for o, r in zip(ops, ref_ops):
+        k = npar.get(int(o["kind"]), 0)
+        assert np.array_equal(prm[o["param"]:o["param"] + k], ref_prm[r["param"]:r["param"] + k])

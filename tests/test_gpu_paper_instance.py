@@ -1,0 +1,108 @@
+"""The paper's second-order verification run at its full degree (Sec. III.E):
+N_x = 8, N_t = 4, N_K = 3, dt = 0.1, nu = 2 (tau = 0.09375), bounce-back
+walls, step initial condition drho = 1.2, kappa_QSVT = 7100 and d = 71001 as
+printed.  The ladder, 9.7 million native ops on 23 qubits, runs as one fused
+complex64 plan.
+
+Checks on the system amplitudes with the ancillas and the signal at 0:
+* against the oracle's singular-value transform of the same phases (its own
+  Chebyshev coefficients from plain 2x2 products of the phases): infidelity
+  below 1e-6, and the element-wise error after removing the one global factor
+  that FP32 Hadamards leave (fp32(1/sqrt 2) is 1.7e-8 low; the ladder holds
+  ten label Hadamards per call, 7.1e5 in all), which must itself stay inside
+  that bound;
+* the final-time rows against the classical N_K = 3 Taylor solution:
+  1 - F below 1e-5;
+* the density at T = 0.4 (amplitudes rescaled by |b| / (c lambda_L)): within
+  3e-3 of the exact second-order exponential and nearer to it than the linear
+  (N_C = 1) exponential, which differs from it by the printed 6.1e-3.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import carleman as oc
+from oracle import qsvt as oq
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+from paper_2606_12770_amd.circuits import qsp
+from tests.gpu_util import require_gpu
+from tests.test_gpu_carleman import infid, system_to_reg
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def test_second_order_run_at_full_degree():
+    sv = require_gpu()
+    cfg, kappa_q, d = cc.paper_second_order_instance()
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    log(f"paper instance: {L.n} qubits, U_L {len(enc.circuit)} ops, d = {d}")
+    coefs, c, err = qsp.inverse_polynomial(kappa_q, d)
+    phases, it, res = qsp.solve_phases(coefs)
+    log(f"phases: {it} iterations, residual {res:.1e}, approximation error {err:.1e}")
+    ops, params = cc.build_qsvt_arrays(enc, phases)
+    plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED)
+    info = sv.sv_plan_info(plan)
+    log(f"plan: {len(ops)} ops, {info.n_tile_passes} tile passes")
+    st = sv.State(L.n, sv.SV_C64)
+    sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
+    t0 = time.time()
+    sv.sv_plan_execute(plan, st.h, 1)
+    sys_amp = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)
+    norm2 = st.prob()
+    log(f"GPU ladder: {time.time() - t0:.1f} s, |psi|^2 = {norm2:.6f}")
+    st.close()
+    sv.sv_plan_free(plan)
+
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2, cfg.boundary)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    f0 = oc.step_function_f1(cfg.nx, cfg.drho)
+    y0 = oc.carleman_vector(f0)
+    braw = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    b = braw / np.linalg.norm(braw)
+    co = oq.odd_chebyshev_of_qsp(phases)
+    M = (Lm.T / enc.lam).tocsr()
+    MT = M.T.tocsr()
+    want = (-1j) ** d * oq.odd_sv_apply(lambda v: M @ v, lambda v: MT @ v, co, b)
+    log("oracle transform done")
+    idx = system_to_reg(cfg, L)
+    got = sys_amp[idx]
+    f_tr = infid(want, got)
+    s = np.vdot(got, want) / np.vdot(got, got)
+    err = np.max(np.abs(s * got - want)) / np.max(np.abs(want))
+    n_h = 10 * d
+    log(f"vs transform: infidelity {f_tr:.2e}, global factor |s| - 1 = {abs(s) - 1:.2e} "
+        f"(bound {n_h * 2.0 ** -24:.1e}), rel max err after it {err:.2e}")
+    assert f_tr < 1e-6
+    assert abs(abs(s) - 1.0) < n_h * 2.0 ** -24
+    assert err < 1e-3
+
+    x = oc.forward_substitution(Lm, b, len(y0))
+    D = len(y0)
+    R = (1 << L.n_m) * (1 << L.n_k)
+    fin = slice(R // 2 * D, R * D)
+    one_minus_f = infid(x[fin], got[fin])
+    rest = np.ones(1 << L.n_sys, bool)
+    rest[idx] = False
+    leak = np.max(np.abs(sys_amp[rest]))
+    log(f"final-time rows: 1 - F vs Taylor {one_minus_f:.2e}; unphysical max {leak:.1e}")
+    assert one_minus_f < 1e-5
+    assert leak < 1e-6 * np.max(np.abs(got))
+
+    # density at T = N_t dt from the first final-time row
+    r0 = R // 2 * D
+    f1 = (s * got * (-1j) ** (-d)).real[r0:r0 + 3 * cfg.nx] * np.linalg.norm(braw) / (c * enc.lam)
+    rho_q = oc.density(f1, cfg.nx)
+    T = cfg.nt * cfg.dt
+    rho2 = oc.density(oc.expm_apply(A, y0, T)[:3 * cfg.nx], cfg.nx)
+    rho1 = oc.density(oc.expm_apply(oc.carleman_matrix(cfg.nx, cfg.tau, 1, cfg.boundary), f0, T), cfg.nx)
+    e2 = np.max(np.abs(rho_q - rho2))
+    e12 = np.max(np.abs(rho1 - rho2))
+    log(f"density at T = {T}: |rho_QSVT - rho_2| = {e2:.2e}, |rho_1 - rho_2| = {e12:.2e}")
+    assert e2 < 3e-3
+    assert e2 < e12
