@@ -2,11 +2,9 @@
 untimed).
 
 Target (Sec. II.D.5): an odd polynomial f of degree d with f(x) ~ c / x on
-[1/kappa, 1] and |f| <= 1/2 on [-1, 1].  It is the degree-d Chebyshev
-truncation of c (1 - exp(-(beta x)^2)) / x, an odd, entire function equal to
-c / x up to the relative factor exp(-(beta x)^2); beta is scanned so that the
-regularisation error at x = 1/kappa and the truncation error balance, and c
-puts the maximum of |f| at 1/2.
+[1/kappa, 1] and |f| <= 1/2 on [-1, 1]: the closed-form polynomial of least
+maximal relative error (inverse_polynomial), relative error about
+2 exp(-d / kappa), and c puts the maximum of |f| at 1/2.
 
 Phases (W_x convention, d + 1 of them, symmetric phi_j = phi_{d-j}):
     p(x) = <0| e^{i phi_0 Z} W(x) e^{i phi_1 Z} ... W(x) e^{i phi_d Z} |0>,
@@ -59,35 +57,57 @@ def chebyshev_odd_eval(coefs: np.ndarray, x) -> np.ndarray:
     return np.cos(np.multiply.outer(th, js)) @ coefs
 
 
-def inverse_polynomial(kappa: float, d: int, peak: float = 0.5, n_beta: int = 24):
+def _chebyshev_t_outside(n: int, half_gap: np.ndarray, above: bool) -> np.ndarray:
+    """T_n(y) for y = 1 + 2 h (above, h >= 0) or y = 1 - 2 h (inside, 0 <= h <= 1),
+    given h, through the half-angle forms arccosh y = 2 asinh(sqrt h) and
+    arccos y = 2 asin(sqrt h), which stay accurate for y next to 1."""
+    r = np.sqrt(np.maximum(half_gap, 0.0))
+    if above:
+        return np.cosh(2.0 * n * np.arcsinh(r))
+    return np.cos(2.0 * n * np.arcsin(np.minimum(r, 1.0)))
+
+
+def inverse_polynomial(kappa: float, d: int, peak: float = 0.5):
     """Odd Chebyshev coefficients of the degree-d approximation of c / x on
     [1/kappa, 1].  Returns (coefs, c, max relative error on [1/kappa, 1]).
-    Maximum and error are taken on a Gauss-Chebyshev grid of at least 16 (d + 1)
-    points (spacing near x = 0 about a tenth of the polynomial's oscillation
-    length 1/d)."""
+
+    The polynomial (Sec. II.D.5 asks for p ~ 1/x on [1/kappa, 1]; the degree
+    bound the paper adopts, Eq. d-star, is the one of the polynomial with the
+    least maximal relative error) is, with a = 1/kappa, n = (d + 1)/2 and
+    g(x) = (1 + a^2 - 2 x^2) / (1 - a^2),
+        P(x) = (1 - T_n(g(x)) / T_n(g(0))) / x,
+    odd and of degree 2n - 1 = d.  On [a, 1], g maps into [-1, 1], so
+    |x P(x) - 1| <= 1 / T_n(g(0)) ~ 2 exp(-d / kappa).  Below a, g > 1 and P
+    falls under 1/x (singular values under 1/kappa are under-inverted).
+    Coefficients come from the values at a Gauss-Chebyshev grid of at least
+    16 (d + 1) points (exact for a degree-d polynomial); c scales the grid
+    maximum of |P| on [-1, 1] to `peak`."""
     if d % 2 == 0:
         raise ValueError("degree must be odd")
+    if kappa <= 1.0:
+        raise ValueError("kappa must exceed 1")
+    n = (d + 1) // 2
+    a = 1.0 / kappa
     N = max(1 << 15, 1 << math.ceil(math.log2(16 * (d + 1))))
     x = _cheb_nodes(N)
-    inside = x >= 1.0 / kappa
-    best = None
-    for beta in kappa * np.linspace(1.0, 6.0, n_beta):
-        def f(x, beta=beta):
-            x = np.asarray(x, float)
-            out = np.empty_like(x)
-            small = np.abs(beta * x) < 1e-8
-            out[small] = beta * beta * x[small]
-            xb = x[~small]
-            out[~small] = -np.expm1(-(beta * xb) ** 2) / xb
-            return out
-        co = odd_chebyshev_coefficients(f, d, N)
-        vals = odd_values_on_nodes(co, N)
-        scale = peak / np.max(np.abs(vals))
-        co = co * scale
-        err = np.max(np.abs(vals[inside] * x[inside] - 1.0))
-        if best is None or err < best[2]:
-            best = (co, scale, err)
-    return best
+    ax = np.abs(x)
+    one_m_a2 = (1.0 - a) * (1.0 + a)
+    # g - 1 = 2 (a^2 - x^2) / (1 - a^2),  1 - g = 2 (x^2 - a^2) / (1 - a^2),  1 + g = 2 (1 - x^2) / (1 - a^2)
+    low = ax < a
+    Tg = np.empty(N)
+    Tg[low] = _chebyshev_t_outside(n, (a - ax[low]) * (a + ax[low]) / one_m_a2, True)
+    mid = ~low & (ax * ax <= 0.5 * (1.0 + a * a))     # g >= 0: angle from the y = 1 end
+    Tg[mid] = _chebyshev_t_outside(n, (ax[mid] - a) * (ax[mid] + a) / one_m_a2, False)
+    top = ~low & ~mid                                   # g < 0: T_n(-y) = (-1)^n T_n(y), y next to 1
+    Tg[top] = (-1.0) ** n * _chebyshev_t_outside(n, (1.0 - ax[top]) * (1.0 + ax[top]) / one_m_a2, False)
+    Tg0 = float(_chebyshev_t_outside(n, np.array([a * a / one_m_a2]), True)[0])
+    P = (1.0 - Tg / Tg0) / ax * np.sign(x)
+    co = (sfft.dct(P, type=2) / N)[1:d + 1:2]
+    vals = odd_values_on_nodes(co, N)
+    scale = peak / np.max(np.abs(vals))
+    inside = x >= a
+    err = float(np.max(np.abs(vals[inside] * x[inside] - 1.0)))
+    return co * scale, scale, err
 
 
 def qsp_real_part(phases: np.ndarray, x: np.ndarray) -> np.ndarray:

@@ -13,9 +13,11 @@ Checks on the system amplitudes with the ancillas and the signal at 0:
   that bound;
 * the final-time rows against the classical N_K = 3 Taylor solution:
   1 - F below 1e-5;
-* the density at T = 0.4 (amplitudes rescaled by |b| / (c lambda_L)): within
-  3e-3 of the exact second-order exponential and nearer to it than the linear
-  (N_C = 1) exponential, which differs from it by the printed 6.1e-3.
+* the density at T = 0.4 (amplitudes rescaled by |b| / (c lambda_L)): off the
+  exact second-order exponential by at most the Taylor solution's own error
+  plus twice the polynomial's relative error times max rho, so far nearer to
+  it than the linear (N_C = 1) exponential, which differs by the printed
+  6.1e-3.
 """
 import time
 
@@ -42,13 +44,13 @@ def test_second_order_run_at_full_degree():
     enc = cc.build_ul(cfg)
     L = enc.layout
     log(f"paper instance: {L.n} qubits, U_L {len(enc.circuit)} ops, d = {d}")
-    coefs, c, err = qsp.inverse_polynomial(kappa_q, d)
+    coefs, c, poly_err = qsp.inverse_polynomial(kappa_q, d)
     phases, it, res = qsp.solve_phases(coefs)
-    log(f"phases: {it} iterations, residual {res:.1e}, approximation error {err:.1e}")
+    log(f"phases: {it} iterations, residual {res:.1e}, approximation error {poly_err:.1e}")
     ops, params = cc.build_qsvt_arrays(enc, phases)
     plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED)
-    info = sv.sv_plan_info(plan)
-    log(f"plan: {len(ops)} ops, {info.n_tile_passes} tile passes")
+    info = sv.sv_plan_get_info(plan)
+    log(f"plan: {len(ops)} ops, {info['n_tile_passes']} tile passes")
     st = sv.State(L.n, sv.SV_C64)
     sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
     t0 = time.time()
@@ -101,8 +103,12 @@ def test_second_order_run_at_full_degree():
     T = cfg.nt * cfg.dt
     rho2 = oc.density(oc.expm_apply(A, y0, T)[:3 * cfg.nx], cfg.nx)
     rho1 = oc.density(oc.expm_apply(oc.carleman_matrix(cfg.nx, cfg.tau, 1, cfg.boundary), f0, T), cfg.nx)
+    rho_t = oc.density(x[r0:r0 + 3 * cfg.nx] * np.linalg.norm(braw), cfg.nx)
     e2 = np.max(np.abs(rho_q - rho2))
+    et = np.max(np.abs(rho_t - rho2))
     e12 = np.max(np.abs(rho1 - rho2))
-    log(f"density at T = {T}: |rho_QSVT - rho_2| = {e2:.2e}, |rho_1 - rho_2| = {e12:.2e}")
-    assert e2 < 3e-3
-    assert e2 < e12
+    bound = et + 2.0 * poly_err * np.max(np.abs(rho2))
+    log(f"density at T = {T}: |rho_QSVT - rho_2| = {e2:.2e} (bound {bound:.2e}; Taylor alone {et:.2e}), "
+        f"|rho_1 - rho_2| = {e12:.2e}")
+    assert e2 < bound
+    assert e2 < e12 / 10
