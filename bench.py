@@ -282,6 +282,47 @@ def paper_instance(sv, dtypes=("c64", "c128")):
     return out
 
 
+def first_order_scan(sv, dtypes=("c64", "c128")):
+    """The first-order degree scan of Sec. III.E (N_C = 1, N_x = 32, N_t = 32,
+    N_K = 1, 19 qubits): its longest ladder, kappa_QSVT = 1000 and d = 15001,
+    one fused plan per precision timed with HIP events; host setup apart."""
+    import numpy as np
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc, qsp
+    cfg, runs = cc.paper_first_order_instance()
+    kq, d = max(runs, key=lambda r: r[1])
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    t0 = time.time()
+    coefs, c, err = qsp.inverse_polynomial(kq, d)
+    phases = qsp.solve_phases(coefs)[0]
+    ops, params = cc.build_qsvt_arrays(enc, phases)
+    t_setup = time.time() - t0
+    out = {"qubits": L.n, "degree": d, "kappa_qsvt": kq, "ops_native": int(len(ops)), "setup_s": t_setup,
+           "config": {"nx": cfg.nx, "nt": cfg.nt, "nk": cfg.nk, "dt": cfg.dt, "tau": cfg.tau, "order": 1,
+                      "boundary": cfg.boundary, "drho": cfg.drho}}
+    amps = {}
+    for name in dtypes:
+        dt = sv.SV_C64 if name == "c64" else sv.SV_C128
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED)
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(L.n, dt)
+        sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
+        ms = sv.sv_plan_time(plan, st, 1)
+        amps[name] = sv.sv_amplitudes(st, 0, 1 << L.n_sys)
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+        gb = info["bytes_moved"] / (ms / 1e3) / 1e9
+        out[name] = {"gpu_ms": ms, "gates_per_s": len(ops) / (ms / 1e3), "tile_passes": info["n_tile_passes"],
+                     "launches": info["n_launches"], "GBps_algorithmic": gb,
+                     "avg_launch_us": ms * 1e3 / max(1, info["n_launches"])}
+        log(f"first-order scan {name}: d {d}, {len(ops)} ops, {ms:.0f} ms, {len(ops) / ms * 1e3:.3g} gates/s, "
+            f"{info['n_launches']} launches ({ms * 1e3 / max(1, info['n_launches']):.1f} us each), {gb:.0f} GB/s")
+    if "c64" in amps and "c128" in amps:
+        a, b = amps["c64"], amps["c128"]
+        out["infidelity_c64_vs_c128"] = float(1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,7 +338,8 @@ def main():
     ap.add_argument("--skip-carleman", action="store_true")
     ap.add_argument("--sections", default="small,grid64,batch,dense,largest",
                     help="comma list of the secondary workloads to run (empty: none); "
-                         "'paper' adds the full-degree second-order run (about 2 minutes)")
+                         "'paper' adds the full-degree second-order run (about 2 minutes), "
+                         "'first_order' the longest ladder of the first-order degree scan")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
@@ -393,6 +435,8 @@ def main():
             carleman["largest_34q"] = largest_state(sv)
         if "paper" in sections:
             carleman["paper_instance_23q"] = paper_instance(sv)
+        if "first_order" in sections:
+            carleman["first_order_19q"] = first_order_scan(sv)
 
     cpu = None
     if not args.skip_cpu:

@@ -133,8 +133,11 @@ class CarlemanConfig:
     wavenumber: int = 1  # rho0 = 1 + amp sin(2 pi wavenumber alpha / N_x)
     boundary: str = "periodic"  # or "bounceback"
     drho: float = 0.0    # > 0: the step initial condition rho0 = 1 +- drho/2 (left / right half), u = 0
+    order: int = 2       # Carleman truncation order N_C (1: the linear A11 system, 2: with A12, A22)
 
     def __post_init__(self):
+        if self.order not in (1, 2):
+            raise ValueError("order (N_C) must be 1 or 2")
         if self.boundary not in ("periodic", "bounceback"):
             raise ValueError("boundary must be 'periodic' or 'bounceback'")
         if self.nx < 2 or self.nx & (self.nx - 1):
@@ -159,6 +162,7 @@ class Layout:
     n_m: int
     with_l: bool = True        # k, m and iL0 present (U_L); False for U_A alone
     with_signal: bool = True
+    order: int = 2             # N_C: 1 has no second copy, no ord qubit and no case register
     q1: list = field(default_factory=list)
     a1: list = field(default_factory=list)
     q2: list = field(default_factory=list)
@@ -177,15 +181,17 @@ class Layout:
         p = 0
         self.a1 = _reg(p, self.n_a); p += self.n_a
         self.q1 = _reg(p, 2); p += 2
-        self.a2 = _reg(p, self.n_a); p += self.n_a
-        self.q2 = _reg(p, 2); p += 2
-        self.ord = p; p += 1
+        if self.order == 2:
+            self.a2 = _reg(p, self.n_a); p += self.n_a
+            self.q2 = _reg(p, 2); p += 2
+            self.ord = p; p += 1
         if self.with_l:
             self.k = _reg(p, self.n_k); p += self.n_k
             self.m = _reg(p, self.n_m); p += self.n_m
         self.t = p; p += 1
         self.i1 = _reg(p, 2); p += 2
-        self.case = _reg(p, 2); p += 2
+        if self.order == 2:
+            self.case = _reg(p, 2); p += 2
         if self.with_l:
             self.il0 = p; p += 1
         if self.with_signal:
@@ -195,7 +201,7 @@ class Layout:
     @property
     def n_x(self) -> int:
         """Width of the Carleman index register."""
-        return 2 * self.n_a + 5
+        return 2 * self.n_a + 5 if self.order == 2 else self.n_a + 2
 
     @property
     def n_sys(self) -> int:
@@ -213,6 +219,10 @@ class Layout:
 
     def x_index(self, ordv: int, a1: int, q1: int, a2: int = 0, q2: int = 0) -> int:
         na = self.n_a
+        if self.order == 1:
+            if ordv or a2 or q2:
+                raise ValueError("the first-order layout holds f^(1) only")
+            return a1 | (q1 << na)
         return a1 | (q1 << na) | (a2 << (na + 2)) | (q2 << (2 * na + 2)) | (ordv << (2 * na + 4))
 
 
@@ -222,7 +232,9 @@ def layout_for(cfg: CarlemanConfig, with_signal: bool = True) -> Layout:
     n_m = int(math.log2(cfg.nt)) + 1
     if n_k > 3:
         raise ValueError("Taylor order N_K <= 7 (three k qubits) is supported")
-    return Layout(n_a, n_k, n_m, True, with_signal)
+    if cfg.order == 1 and n_k > 1:
+        raise ValueError("the first-order encoding parks k in one label bit: N_K = 1 only")
+    return Layout(n_a, n_k, n_m, True, with_signal, cfg.order)
 
 
 # ---- conditions ---------------------------------------------------------------
@@ -295,8 +307,23 @@ def a_values(tau: float) -> list[tuple[float, dict]]:
     return out
 
 
-def a_vmax(tau: float) -> float:
-    return max(abs(v) for v, _ in a_values(tau))
+def a_values_first_order(tau: float) -> list[tuple[float, dict]]:
+    """The value table of the first-order U_A (label i1 only): C[q', q] on
+    i1 = q' in {0, 1, 2}, and -1 (the subtracted identity) on i1 = 3."""
+    C = collision_values(tau)
+    out = []
+    for qp in range(3):
+        for q in range(3):
+            v = C[qp, q]
+            if v != 0.0:
+                out.append((v, lambda L, qp=qp, q=q: _merge(eq(L.i1, qp), eq(L.q1, q))))
+    out.append((-1.0, lambda L: eq(L.i1, 3)))
+    return out
+
+
+def a_vmax(tau: float, order: int = 2) -> float:
+    table = a_values(tau) if order == 2 else a_values_first_order(tau)
+    return max(abs(v) for v, _ in table)
 
 
 def emit_stream(c: Circuit, a: list[int], q: list[int], ctrl: dict, boundary: str) -> None:
@@ -317,10 +344,47 @@ def emit_stream(c: Circuit, a: list[int], q: list[int], ctrl: dict, boundary: st
         c.x(a[j], left)
 
 
+def emit_swap_if_three(c: Circuit, a: list[int], b: list[int], ctrl: dict) -> None:
+    """Exchange the 2-bit registers a and b where either holds 3, leave them
+    where neither does: (3, v) <-> (v, 3).  Bit 0 is exchanged where both
+    high bits are 1 ((3, 2) <-> (2, 3)), bit 1 where both low bits are 1
+    ((3, 1) <-> (1, 3)), and (3, 0) <-> (0, 3), which flips all four bits, by
+    a flip of a_0 in the coordinates a_1 ^= a_0, b_1 ^= b_0, b_0 ^= a_0 where
+    they read (0, 0, 1): the only two states with a_1 = a_0, b_1 = b_0 and
+    b_0 != a_0."""
+    c.swap(a[0], b[0], _merge(ctrl, {a[1]: 1, b[1]: 1}))
+    c.swap(a[1], b[1], _merge(ctrl, {a[0]: 1, b[0]: 1}))
+    c.x(a[1], {a[0]: 1})
+    c.x(b[1], {b[0]: 1})
+    c.x(b[0], {a[0]: 1})
+    c.x(a[0], _merge(ctrl, {a[1]: 0, b[1]: 0, b[0]: 1}))
+    c.x(b[0], {a[0]: 1})
+    c.x(b[1], {b[0]: 1})
+    c.x(a[1], {a[0]: 1})
+
+
+def emit_a1_oracle(c: Circuit, L: Layout, tau: float, ctrl: dict, value_rot, boundary: str) -> None:
+    """First-order U_A oracle (A = A11, Eq. A11-elements): label i1 = q' in
+    {0, 1, 2} takes (alpha, q) to (alpha + e_q', q') with value C[q', q];
+    i1 = 3 keeps (alpha, q) with value -1.  Index update: exchange q1 and i1,
+    stream (a population with q1 = 3, the identity label, does not move),
+    then exchange them back where either holds 3, so the identity label
+    returns q to q1 (and an unphysical q = 3 ends in q1 = 3 again)."""
+    for v, cond in a_values_first_order(tau):
+        value_rot(v, _merge(ctrl, cond(L)))
+    c.swap(L.q1[0], L.i1[0], ctrl)
+    c.swap(L.q1[1], L.i1[1], ctrl)
+    emit_stream(c, L.a1, L.q1, ctrl, boundary)
+    emit_swap_if_three(c, L.q1, L.i1, ctrl)
+
+
 def emit_a_oracle(c: Circuit, L: Layout, tau: float, ctrl: dict, value_rot, boundary: str = "periodic") -> None:
     """The U_A oracle between the label Hadamards: subtractor, value encodings
     (value_rot(v, cond) emits the rotations of one table entry), index updates.
     ctrl is added to every gate."""
+    if L.order == 1:
+        emit_a1_oracle(c, L, tau, ctrl, value_rot, boundary)
+        return
     na = L.n_a
     sub = _merge(ctrl, eq(L.case, 3), {L.ord: 1})
     for j in range(na):  # alpha2 -= alpha1: subtract 2^j where alpha1_j = 1
@@ -352,12 +416,13 @@ def _ry_angle(v: float) -> float:
     return 2.0 * math.asin(max(-1.0, min(1.0, v)))
 
 
-def build_ua(nx: int, tau: float, boundary: str = "periodic") -> tuple[Circuit, float, Layout]:
-    """Stand-alone block encoding of A (registers x, t, i1, case): returns the
-    circuit, lambda_A = 16 v_max and the layout."""
-    L = Layout(nx.bit_length() - 1, 0, 0, with_l=False, with_signal=False)
+def build_ua(nx: int, tau: float, boundary: str = "periodic", order: int = 2) -> tuple[Circuit, float, Layout]:
+    """Stand-alone block encoding of A (registers x, t, i1 and, at order 2,
+    case): returns the circuit, lambda_A = 2^(label width) v_max (16 v_max at
+    order 2, 4 v_max at order 1) and the layout."""
+    L = Layout(nx.bit_length() - 1, 0, 0, with_l=False, with_signal=False, order=order)
     c = Circuit(L.n)
-    vmax = a_vmax(tau)
+    vmax = a_vmax(tau, order)
     for q in L.label:
         c.h(q)
 
@@ -368,7 +433,7 @@ def build_ua(nx: int, tau: float, boundary: str = "periodic") -> tuple[Circuit, 
     c.x(L.t)
     for q in L.label:
         c.h(q)
-    return c, 16.0 * vmax, L
+    return c, float(1 << len(L.label)) * vmax, L
 
 
 # ---- U_L -------------------------------------------------------------------------
@@ -385,10 +450,12 @@ class LEncoding:
 def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
     L = layout_for(cfg, with_signal)
     c = Circuit(L.n)
-    vmax = a_vmax(cfg.tau)
+    vmax = a_vmax(cfg.tau, cfg.order)
     lmax = max(1.0, cfg.dt * vmax)
-    lab = L.label                     # i1 (2), case (2), iL0
+    lab = L.label                     # i1 (2), case (2, order 2 only), iL0
     ia = L.i1 + L.case                # the U_A part of the label
+    wa = len(ia)
+    top = 1 << wa                     # iL0 = 1
     m_lt = lt(L.m, cfg.nt)
     m_top = L.m[-1]
 
@@ -408,21 +475,21 @@ def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
     c.inc(L.k[0], L.n_k, ctrl)
 
     # diagonal +1
-    c.ry(L.t, _ry_angle(1.0 / lmax), eq(lab, 31))
+    c.ry(L.t, _ry_angle(1.0 / lmax), eq(lab, 2 * top - 1))
 
     # step coupling: (m, k <= N_K) -> (m + 1, 0) for m < N_t, k parked in the label
     ang = _ry_angle(-1.0 / lmax)
     for mc in m_lt:
         for kc in lt(L.k, cfg.nk + 1):
-            c.ry(L.t, ang, _merge(eq(lab, 16), mc, kc))
-    park = _merge({L.il0: 1}, {ia[j]: 0 for j in range(L.n_k, 4)})
+            c.ry(L.t, ang, _merge(eq(lab, top), mc, kc))
+    park = _merge({L.il0: 1}, {ia[j]: 0 for j in range(L.n_k, wa)})
     for mc in m_lt:
         for j in range(L.n_k):
             c.swap(L.k[j], ia[j], _merge(park, mc))
     c.inc(L.m[0], L.n_m, park)
 
     # idle rows m >= N_t: (k, m) -> next, nothing from the last row
-    term = _merge(eq(lab, 24), {m_top: 1})
+    term = _merge(eq(lab, top | (top >> 1)), {m_top: 1})
     c.ry(L.t, ang, term)
     last = _merge(term, eq(L.k + L.m, (1 << (L.n_k + L.n_m)) - 1))
     c.ry(L.t, -ang, last)
@@ -432,7 +499,7 @@ def build_ul(cfg: CarlemanConfig, with_signal: bool = True) -> LEncoding:
     c.x(L.t)
     for q in lab:
         c.h(q)
-    return LEncoding(c, 32.0 * lmax, lmax, vmax, L)
+    return LEncoding(c, float(1 << len(lab)) * lmax, lmax, vmax, L)
 
 
 def tau_from_nu(nx: int, nu: float) -> float:
@@ -448,6 +515,18 @@ def paper_second_order_instance() -> tuple[CarlemanConfig, float, int]:
     cfg = CarlemanConfig(nx=8, tau=tau_from_nu(8, 2.0), nk=3, nt=4, dt=0.1,
                          boundary="bounceback", drho=1.2)
     return cfg, 7100.0, 71001
+
+
+def paper_first_order_instance() -> tuple[CarlemanConfig, list[tuple[float, int]]]:
+    """The first-order degree scan of Sec. III.E: N_C = 1, N_x = 32,
+    N_t = 32, N_K = 1, dt = 0.1, nu = 2, bounce-back walls, rho in
+    [0.8, 1.2] (drho = 0.4); kappa(L) is about 800 with lambda_L = 8.  Returns
+    (config, [(kappa_QSVT, d)]) for kappa_QSVT in {400, 1000} and
+    d = r kappa_QSVT + 1, r in {5, 10, 15}."""
+    cfg = CarlemanConfig(nx=32, tau=tau_from_nu(32, 2.0), nk=1, nt=32, dt=0.1,
+                         boundary="bounceback", drho=0.4, order=1)
+    runs = [(kq, int(r * kq) + 1) for kq in (400.0, 1000.0) for r in (5, 10, 15)]
+    return cfg, runs
 
 
 # ---- right-hand side and post-selection ------------------------------------------
@@ -472,6 +551,8 @@ def rhs_x_block(cfg: CarlemanConfig, L: Layout) -> np.ndarray:
     for a in range(cfg.nx):
         for q in range(3):
             out[L.x_index(0, a, q)] = f[a, q]
+    if L.order == 1:
+        return out / np.linalg.norm(out)
     # order 1: f(a1, q1) f(a2, q2)
     na = L.n_a
     idx = np.zeros((cfg.nx, 3, cfg.nx, 3), dtype=np.int64)
@@ -644,6 +725,7 @@ __all__ = [
     "CarlemanConfig", "Layout", "LEncoding", "collision_values", "kernel12", "equilibrium",
     "layout_for", "eq", "lt", "a_values", "a_vmax", "emit_a_oracle", "build_ua", "build_ul",
     "initial_populations", "rhs_x_block", "postselect_condition", "projector_angles", "build_qsvt",
-    "build_qsvt_arrays", "tau_from_nu", "paper_second_order_instance",
+    "build_qsvt_arrays", "tau_from_nu", "paper_second_order_instance", "paper_first_order_instance",
+    "emit_swap_if_three", "a_values_first_order",
     "lower_to_elementary", "qubit_count", "U", "X", "PHASE",
 ]

@@ -22,10 +22,14 @@ def x_reg_index(nx, ordv, a1, q1, a2=0, q2=0):
     return a1 | (q1 << na) | (a2 << (na + 2)) | (q2 << (2 * na + 2)) | (ordv << (2 * na + 4))
 
 
-def carleman_to_reg(nx):
+def carleman_to_reg(nx, order=2):
     """Register index of every entry of the oracle's Carleman vector
-    (f1 index 3 alpha + q, then f2 index (3 a1 + q1) D + 3 a2 + q2)."""
+    (f1 index 3 alpha + q, then f2 index (3 a1 + q1) D + 3 a2 + q2); at
+    order 1 only f1, with x = alpha | q << n_a."""
     D = 3 * nx
+    if order == 1:
+        na = nx.bit_length() - 1
+        return np.array([a | (q << na) for a in range(nx) for q in range(3)], dtype=np.int64)
     out = np.zeros(D + D * D, dtype=np.int64)
     for a in range(nx):
         for q in range(3):
@@ -36,11 +40,11 @@ def carleman_to_reg(nx):
     return out
 
 
-def system_to_reg(nx, nt, nk, n_k, n_m):
+def system_to_reg(nx, nt, nk, n_k, n_m, order=2):
     """Register index (x | k << n_x | m << (n_x + n_k)) of every entry of the
     oracle's L-system vector (block row m * 2^n_k + k, Carleman vector inside)."""
-    cr = carleman_to_reg(nx)
-    n_x = 2 * (nx.bit_length() - 1) + 5
+    cr = carleman_to_reg(nx, order)
+    n_x = 2 * (nx.bit_length() - 1) + 5 if order == 2 else (nx.bit_length() - 1) + 2
     blocks = []
     for m in range(1 << n_m):
         for k in range(1 << n_k):
@@ -235,3 +239,68 @@ def test_ladder_arrays_equal_the_ladder_circuit(d):
     for o, r in zip(ops, ref_ops):
         k = npar.get(int(o["kind"]), 0)
         assert np.array_equal(prm[o["param"]:o["param"] + k], ref_prm[r["param"]:r["param"] + k])
+
+
+def test_swap_if_three_is_the_stated_permutation():
+    """Brute force over all 16 values of two 2-bit registers (and a control
+    that is off): (3, v) <-> (v, 3), everything else fixed."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    c = Circuit(5)
+    cc.emit_swap_if_three(c, [0, 1], [2, 3], {4: 1})
+    for ctl in (0, 1):
+        for a in range(4):
+            for b in range(4):
+                psi = np.zeros(32, dtype=np.complex128)
+                psi[a | (b << 2) | (ctl << 4)] = 1.0
+                out = osv.run(c, psi)
+                j = int(np.argmax(np.abs(out)))
+                want = (b, a) if ctl and (a == 3 or b == 3) else (a, b)
+                assert abs(out[j]) == 1.0 and j == want[0] | (want[1] << 2) | (ctl << 4), (ctl, a, b, j)
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "bounceback"])
+@pytest.mark.parametrize("nx,tau", [(2, 0.8), (4, 1.0), (8, 0.375), (8, 1.3)])
+def test_first_order_ua_encodes_a11(nx, tau, boundary):
+    circ, lam, L = cc.build_ua(nx, tau, boundary, order=1)
+    assert L.n_x == (nx.bit_length() - 1) + 2 and len(L.label) == 2
+    A = oc.carleman_matrix(nx, tau, 1, boundary).toarray()
+    idx = carleman_to_reg(nx, 1)
+    phys = np.zeros(1 << L.n_x, bool)
+    phys[idx] = True
+    rng = np.random.default_rng(nx)
+    y = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+    v = np.zeros(1 << L.n_x, dtype=np.complex128)
+    v[idx] = y
+    got = apply_block(circ, lam, v, L.n_x)
+    assert np.max(np.abs(got[idx] - A @ y)) < 1e-13
+    assert np.max(np.abs(got[~phys])) < 1e-13
+    u = rng.standard_normal(1 << L.n_x) + 0j
+    u[idx] = 0
+    assert np.max(np.abs(apply_block(circ, lam, u, L.n_x)[idx])) < 1e-13
+
+
+@pytest.mark.parametrize("nx,tau,nt,boundary", [(2, 0.9, 1, "periodic"), (4, 0.375, 4, "bounceback"),
+                                                (8, 0.6, 2, "periodic"), (8, 0.375, 8, "bounceback")])
+def test_first_order_ul_encodes_taylor_matrix(nx, tau, nt, boundary):
+    """N_C = 1, N_K = 1: lambda_L = 8 L_max (three label qubits, Sec. III.E)."""
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=1, nt=nt, dt=0.1, boundary=boundary, order=1)
+    enc = cc.build_ul(cfg, with_signal=False)
+    L = enc.layout
+    assert enc.lam == 8.0 * enc.lmax
+    A = oc.carleman_matrix(nx, tau, 1, boundary)
+    Lm = oc.l_matrix(A, cfg.dt, nt, 1, L.n_m, L.n_k).toarray()
+    idx = system_to_reg(nx, nt, 1, L.n_k, L.n_m, order=1)
+    phys = np.zeros(1 << L.n_sys, bool)
+    phys[idx] = True
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+    v = np.zeros(1 << L.n_sys, dtype=np.complex128)
+    v[idx] = y
+    got = apply_block(enc.circuit, enc.lam, v, L.n_sys)
+    assert np.max(np.abs(got[idx] - Lm @ y)) < 1e-12
+    assert np.max(np.abs(got[~phys])) < 1e-12
+
+
+def test_first_order_refuses_higher_taylor_orders():
+    with pytest.raises(ValueError):
+        cc.build_ul(cc.CarlemanConfig(nx=4, tau=0.9, nk=2, nt=2, order=1))

@@ -22,24 +22,26 @@ from tests.test_carleman_circuit import carleman_to_reg, system_to_reg
 
 
 def classical_setup(cfg, L):
-    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2, cfg.boundary)
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, cfg.order, cfg.boundary)
     Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
     f0 = (oc.step_function_f1(cfg.nx, cfg.drho) if cfg.drho > 0
           else oc.initial_f1(cfg.nx, cfg.amp, cfg.u0, cfg.wavenumber))
-    y0 = oc.carleman_vector(f0)
+    y0 = oc.carleman_vector(f0, cfg.order)
     b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
     b = b / np.linalg.norm(b)
     x = oc.forward_substitution(Lm, b, len(y0))
     return Lm, b, x, f0
 
 
-@pytest.mark.parametrize("nx,nk,nt,tau,boundary,drho", [
-    (2, 1, 1, 0.9, "periodic", 0.0),
-    (2, 1, 1, 0.7, "bounceback", 0.4),
-    pytest.param(4, 1, 1, 1.0, "periodic", 0.0, marks=pytest.mark.slow),
-    pytest.param(4, 1, 1, 0.8, "bounceback", 0.6, marks=pytest.mark.slow)])
-def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho):
-    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, amp=0.1, boundary=boundary, drho=drho)
+@pytest.mark.parametrize("nx,nk,nt,tau,boundary,drho,order", [
+    (2, 1, 1, 0.9, "periodic", 0.0, 2),
+    (2, 1, 1, 0.7, "bounceback", 0.4, 2),
+    (8, 1, 4, 0.375, "bounceback", 0.4, 1),
+    pytest.param(4, 1, 1, 1.0, "periodic", 0.0, 2, marks=pytest.mark.slow),
+    pytest.param(4, 1, 1, 0.8, "bounceback", 0.6, 2, marks=pytest.mark.slow)])
+def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho, order):
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=0.1, amp=0.1, boundary=boundary, drho=drho,
+                            order=order)
     enc = cc.build_ul(cfg)
     L = enc.layout
     Lm, b, x, f0 = classical_setup(cfg, L)
@@ -52,7 +54,7 @@ def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho):
     psi[: 1 << L.n_x] = cc.rhs_x_block(cfg, L)
     out = osv.run(circ, psi)
 
-    idx = system_to_reg(cfg.nx, cfg.nt, cfg.nk, L.n_k, L.n_m)
+    idx = system_to_reg(cfg.nx, cfg.nt, cfg.nk, L.n_k, L.n_m, order)
     M = (Lm.T / enc.lam).tocsr()      # L^dagger / lambda_L (real L)
     MT = M.T.tocsr()
     co = oq.odd_chebyshev_of_qsp(phases)
@@ -64,7 +66,7 @@ def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho):
     mask, val = cc.postselect_condition(L)
     P = osv.postselect(out, circ.n, mask, val)
     assert P > 1e-4
-    D = len(oc.carleman_vector(f0))
+    D = len(oc.carleman_vector(f0, order))
     R = (1 << L.n_m) * (1 << L.n_k)
     fin = slice(R // 2 * D, R * D)
     xf = x[fin]
@@ -72,15 +74,17 @@ def test_qsvt_solution_matches_taylor_solution(nx, nk, nt, tau, boundary, drho):
     F = abs(np.vdot(xf, gf)) ** 2 / (np.vdot(xf, xf).real * np.vdot(gf, gf).real)
     assert 1.0 - F < 1e-5, (1.0 - F, d, kappa)
 
-    # mass ratio in every idle row
+    # mass ratio in every idle row (order 2: sum f^(1) / sum f^(2) = 1 / M0;
+    # order 1: the idle rows are copies of one vector, equal masses)
     M0 = f0.sum()
     Dl = 3 * cfg.nx
     ratio_err = []
     for r in range(R // 2):
         blk = gf[r * D:(r + 1) * D]
-        s1 = blk[:Dl].sum()
-        s2 = blk[Dl:].sum()
-        ratio_err.append(abs(s1 / s2 * M0 - 1.0))
+        if order == 2:
+            ratio_err.append(abs(blk[:Dl].sum() / blk[Dl:].sum() * M0 - 1.0))
+        else:
+            ratio_err.append(abs(blk.sum() / gf[:D].sum() - 1.0))
     assert max(ratio_err) < 1e-3
     # the unphysical part of the system register stays empty
     n_sys = L.n_sys

@@ -1,0 +1,91 @@
+"""The first-order (N_C = 1) degree scan of Sec. III.E on the GPU: N_x = 32,
+N_t = 32, N_K = 1, dt = 0.1, nu = 2, bounce-back walls, rho in [0.8, 1.2];
+19 qubits, lambda_L = 8, kappa about 800.  Six ladders: kappa_QSVT in
+{400, 1000} (under- and overshoot) times d / kappa_QSVT in {5, 10, 15}, run
+as fused complex128 plans.
+
+For every run the system amplitudes with the ancillas and the signal at 0 must
+equal the oracle's singular-value transform of the same phases (relative max
+error 1e-9), and the final-time density and velocity are compared with the
+classical solution of the same L system.  What the figure shows must hold:
+at kappa_QSVT = 1000 the residual falls with d and reaches the 1e-4 level at
+d = 10 kappa_QSVT (velocity below 1e-4); at kappa_QSVT = 400 it also falls
+with d but stays far above, since singular values under 1/400 lie outside
+the polynomial's design interval.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import carleman as oc
+from oracle import qsvt as oq
+from paper_2606_12770_amd.circuits import carleman_circuit as cc
+from paper_2606_12770_amd.circuits import qsp
+from tests.gpu_util import require_gpu
+from tests.test_carleman_circuit import system_to_reg
+
+pytestmark = pytest.mark.gpu
+
+E = np.array([1.0, -1.0, 0.0])
+
+
+def velocity(f, nx):
+    F = f.reshape(nx, 3)
+    return (F * E).sum(1) / F.sum(1)
+
+
+def test_first_order_degree_scan():
+    sv = require_gpu()
+    cfg, runs = cc.paper_first_order_instance()
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    nx = cfg.nx
+    A = oc.carleman_matrix(nx, cfg.tau, 1, cfg.boundary)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    f0 = oc.step_function_f1(nx, cfg.drho)
+    y0 = oc.carleman_vector(f0, 1)
+    braw = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    nb = np.linalg.norm(braw)
+    b = braw / nb
+    x = oc.forward_substitution(Lm, b, len(y0)) * nb
+    D = len(y0)
+    R = (1 << L.n_m) * (1 << L.n_k)
+    r0 = R // 2 * D
+    rho_ref = oc.density(x[r0:r0 + D], nx)
+    u_ref = velocity(x[r0:r0 + D], nx)
+    M = (Lm.T / enc.lam).tocsr()
+    MT = M.T.tocsr()
+    idx = system_to_reg(nx, cfg.nt, cfg.nk, L.n_k, L.n_m, order=1)
+    print(f"N_C = 1 scan: {L.n} qubits, U_L {len(enc.circuit)} ops, lambda_L {enc.lam}", flush=True)
+
+    res = {}
+    for kq, d in runs:
+        coefs, c, _err = qsp.inverse_polynomial(kq, d)
+        phases, _it, _r = qsp.solve_phases(coefs)
+        ops, params = cc.build_qsvt_arrays(enc, phases)
+        plan = sv.sv_plan_create(L.n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED)
+        st = sv.State(L.n, sv.SV_C128)
+        sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
+        t0 = time.time()
+        sv.sv_plan_execute(plan, st.h, 1)
+        got = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)[idx]
+        t_gpu = time.time() - t0
+        st.close()
+        sv.sv_plan_free(plan)
+        want = (-1j) ** d * oq.odd_sv_apply(lambda v: M @ v, lambda v: MT @ v, oq.odd_chebyshev_of_qsp(phases), b)
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        f = ((-1j) ** (-d) * got).real[r0:r0 + D] * nb / (c * enc.lam)
+        drho = np.max(np.abs(oc.density(f, nx) - rho_ref))
+        du = np.max(np.abs(velocity(f, nx) - u_ref))
+        res[(kq, d)] = (drho, du)
+        print(f"  kappa_QSVT {kq:.0f} d {d}: {len(ops)} ops, GPU {t_gpu:.2f} s, rel err vs transform {err:.1e}, "
+              f"|rho - ref| {drho:.2e}, |u - ref| {du:.2e}", flush=True)
+        assert err < 1e-9
+
+    over = [res[(1000.0, d)] for d in (5001, 10001, 15001)]
+    under = [res[(400.0, d)] for d in (2001, 4001, 6001)]
+    assert over[0][0] > over[1][0] > over[2][0]
+    assert over[1][0] < 3e-4 and over[1][1] < 1e-4
+    assert under[0][0] > under[1][0] > under[2][0]
+    assert under[2][0] > 100 * over[1][0]

@@ -192,3 +192,16 @@ def test_nonlinear_correction_of_the_second_order_run():
     d12 = np.max(np.abs(rho1 - rho2))
     assert 6.05e-3 < d12 < 6.15e-3, d12
     assert np.max(np.abs(rho2 - rho_b)) < np.max(np.abs(rho1 - rho_b))
+
+
+def test_kappa_first_order_degree_scan():
+    """Sec. III.E: N_C = 1, N_x = 32, N_t = 32, N_K = 1, dt = 0.1, nu = 2,
+    bounce-back: kappa(L) = lambda_L / sigma_min(L) about 800 with
+    lambda_L = 8 (L_max = 1: dt max|A11| = 0.18 < 1)."""
+    nx, nt, dt = 32, 32, 0.1
+    tau = oc.tau_from_nu(nx, 2.0)
+    A = oc.carleman_matrix(nx, tau, 1, "bounceback")
+    assert dt * abs(A).max() < 1.0
+    L = oc.l_matrix(A, dt, nt, 1, 6, 1)
+    kappa = 8.0 / oc.sigma_min(L)
+    assert 780 < kappa < 820, kappa
