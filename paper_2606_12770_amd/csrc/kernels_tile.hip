@@ -33,6 +33,16 @@ __device__ __forceinline__ C &lds_at(C *lds, uint32_t off)
     return *reinterpret_cast<C *>(reinterpret_cast<unsigned char *>(lds) + off);
 }
 
+// Byte offset of the thread part of an LDS address, hidden from the
+// optimiser: otherwise it rewrites (t << 3) ^ (s << 3) as ((t ^ s) << 3) with
+// the swizzle term XORed in separately, three vector ops per access instead of
+// one.  The empty asm only pins the value in a register.
+__device__ __forceinline__ uint32_t opaque_offset(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <typename C, typename R>
 __device__ __forceinline__ C row2(R ar, R ai, R br, R bi, C a, C b)
 {
@@ -187,7 +197,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
             const TileStage &P = stages[st - 1];
             __syncthreads();
             if (S.perm_begin == S.perm_end) {
-                const uint32_t tw = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
+                const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
                 for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
             } else {
@@ -204,7 +214,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
                 t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
             }
             thr = t2;
-            const uint32_t tr = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
+            const uint32_t tr = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
             for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (S.swz[s] * (uint32_t)sizeof(C)));
         }
@@ -268,7 +278,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
         const TileStage &L = stages[se - 1];
         __syncthreads();
         if (pass->fperm_begin == pass->fperm_end) {
-            const uint32_t tw = lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C);
+            const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
             for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (L.swz[s] * (uint32_t)sizeof(C))) = x[s];
         } else {
@@ -279,7 +289,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
             }
         }
         __syncthreads();
-        const uint32_t tr = lds_swizzle(tid, LOWB) * (uint32_t)sizeof(C);
+        const uint32_t tr = opaque_offset(lds_swizzle(tid, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
         for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (pass->swz0[s] * (uint32_t)sizeof(C)));
     }
