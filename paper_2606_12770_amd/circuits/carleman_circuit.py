@@ -162,7 +162,8 @@ class Layout:
     n_m: int
     with_l: bool = True        # k, m and iL0 present (U_L); False for U_A alone
     with_signal: bool = True
-    order: int = 2             # N_C: 1 has no second copy, no ord qubit and no case register
+    order: int = 2             # N_C: 1 has no second copy and no ord qubit; its case register is padding
+    pad: int = 0               # N_C = 1: width of the case register (value-free label bits that let k park)
     q1: list = field(default_factory=list)
     a1: list = field(default_factory=list)
     q2: list = field(default_factory=list)
@@ -192,6 +193,8 @@ class Layout:
         self.i1 = _reg(p, 2); p += 2
         if self.order == 2:
             self.case = _reg(p, 2); p += 2
+        elif self.pad:
+            self.case = _reg(p, self.pad); p += self.pad
         if self.with_l:
             self.il0 = p; p += 1
         if self.with_signal:
@@ -232,9 +235,10 @@ def layout_for(cfg: CarlemanConfig, with_signal: bool = True) -> Layout:
     n_m = int(math.log2(cfg.nt)) + 1
     if n_k > 3:
         raise ValueError("Taylor order N_K <= 7 (three k qubits) is supported")
-    if cfg.order == 1 and n_k > 1:
-        raise ValueError("the first-order encoding parks k in one label bit: N_K = 1 only")
-    return Layout(n_a, n_k, n_m, True, with_signal, cfg.order)
+    # k parks in the low label bits below at least one value-free bit: at order 1
+    # the two-qubit U_A label gets n_k - 1 padding bits (lambda_L = 2^(n_k + 2) L_max)
+    pad = max(0, n_k - 1) if cfg.order == 1 else 0
+    return Layout(n_a, n_k, n_m, True, with_signal, cfg.order, pad)
 
 
 # ---- conditions ---------------------------------------------------------------
@@ -316,8 +320,8 @@ def a_values_first_order(tau: float) -> list[tuple[float, dict]]:
         for q in range(3):
             v = C[qp, q]
             if v != 0.0:
-                out.append((v, lambda L, qp=qp, q=q: _merge(eq(L.i1, qp), eq(L.q1, q))))
-    out.append((-1.0, lambda L: eq(L.i1, 3)))
+                out.append((v, lambda L, qp=qp, q=q: _merge(eq(L.i1, qp), eq(L.q1, q), eq(L.case, 0))))
+    out.append((-1.0, lambda L: _merge(eq(L.i1, 3), eq(L.case, 0))))
     return out
 
 
@@ -529,6 +533,18 @@ def paper_first_order_instance() -> tuple[CarlemanConfig, list[tuple[float, int]
     return cfg, runs
 
 
+def paper_taylor_order_comparison() -> tuple[list[CarlemanConfig], float, int]:
+    """The N_K-vs-dt comparison of Sec. III.E: N_C = 1, N_x = 32, nu = 2,
+    bounce-back, drho = 0.4, T = 5.6 reached by N_K = 1 with dt = 5.6/128
+    (N_t = 128) and by N_K = 3 with dt = 0.7 (N_t = 8); both at
+    kappa_QSVT = 1200, d = 12001.  Returns ([config N_K = 1, config N_K = 3],
+    kappa_QSVT, d)."""
+    tau = tau_from_nu(32, 2.0)
+    cfgs = [CarlemanConfig(nx=32, tau=tau, nk=1, nt=128, dt=5.6 / 128, boundary="bounceback", drho=0.4, order=1),
+            CarlemanConfig(nx=32, tau=tau, nk=3, nt=8, dt=0.7, boundary="bounceback", drho=0.4, order=1)]
+    return cfgs, 1200.0, 12001
+
+
 # ---- right-hand side and post-selection ------------------------------------------
 
 def initial_populations(cfg: CarlemanConfig) -> np.ndarray:
@@ -726,6 +742,7 @@ __all__ = [
     "layout_for", "eq", "lt", "a_values", "a_vmax", "emit_a_oracle", "build_ua", "build_ul",
     "initial_populations", "rhs_x_block", "postselect_condition", "projector_angles", "build_qsvt",
     "build_qsvt_arrays", "tau_from_nu", "paper_second_order_instance", "paper_first_order_instance",
+    "paper_taylor_order_comparison",
     "emit_swap_if_three", "a_values_first_order",
     "lower_to_elementary", "qubit_count", "U", "X", "PHASE",
 ]

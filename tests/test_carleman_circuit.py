@@ -279,17 +279,25 @@ def test_first_order_ua_encodes_a11(nx, tau, boundary):
     assert np.max(np.abs(apply_block(circ, lam, u, L.n_x)[idx])) < 1e-13
 
 
-@pytest.mark.parametrize("nx,tau,nt,boundary", [(2, 0.9, 1, "periodic"), (4, 0.375, 4, "bounceback"),
-                                                (8, 0.6, 2, "periodic"), (8, 0.375, 8, "bounceback")])
-def test_first_order_ul_encodes_taylor_matrix(nx, tau, nt, boundary):
-    """N_C = 1, N_K = 1: lambda_L = 8 L_max (three label qubits, Sec. III.E)."""
-    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=1, nt=nt, dt=0.1, boundary=boundary, order=1)
+@pytest.mark.parametrize("nx,tau,nt,nk,dt,boundary", [(2, 0.9, 1, 1, 0.1, "periodic"),
+                                                      (4, 0.375, 4, 1, 0.1, "bounceback"),
+                                                      (8, 0.6, 2, 1, 0.1, "periodic"),
+                                                      (8, 0.375, 8, 1, 0.1, "bounceback"),
+                                                      (4, 0.375, 2, 2, 0.3, "bounceback"),
+                                                      (8, 0.375, 2, 3, 0.7, "bounceback"),
+                                                      (4, 0.9, 1, 4, 0.2, "periodic")])
+def test_first_order_ul_encodes_taylor_matrix(nx, tau, nt, nk, dt, boundary):
+    """N_C = 1: lambda_L = 8 L_max for N_K = 1 (three label qubits, Sec. III.E.1)
+    and 2^(n_k + 2) L_max above (four label qubits at N_K = 2, 3, as the
+    kappa of the N_K = 3 run of Sec. III.E needs)."""
+    cfg = cc.CarlemanConfig(nx=nx, tau=tau, nk=nk, nt=nt, dt=dt, boundary=boundary, order=1)
     enc = cc.build_ul(cfg, with_signal=False)
     L = enc.layout
-    assert enc.lam == 8.0 * enc.lmax
+    n_k = L.n_k
+    assert enc.lam == (8.0 if nk == 1 else 2.0 ** (n_k + 2)) * enc.lmax
     A = oc.carleman_matrix(nx, tau, 1, boundary)
-    Lm = oc.l_matrix(A, cfg.dt, nt, 1, L.n_m, L.n_k).toarray()
-    idx = system_to_reg(nx, nt, 1, L.n_k, L.n_m, order=1)
+    Lm = oc.l_matrix(A, cfg.dt, nt, nk, L.n_m, L.n_k).toarray()
+    idx = system_to_reg(nx, nt, nk, L.n_k, L.n_m, order=1)
     phys = np.zeros(1 << L.n_sys, bool)
     phys[idx] = True
     rng = np.random.default_rng(5)
@@ -300,7 +308,3 @@ def test_first_order_ul_encodes_taylor_matrix(nx, tau, nt, boundary):
     assert np.max(np.abs(got[idx] - Lm @ y)) < 1e-12
     assert np.max(np.abs(got[~phys])) < 1e-12
 
-
-def test_first_order_refuses_higher_taylor_orders():
-    with pytest.raises(ValueError):
-        cc.build_ul(cc.CarlemanConfig(nx=4, tau=0.9, nk=2, nt=2, order=1))

@@ -205,3 +205,20 @@ def test_nonlinear_correction_of_the_second_order_run():
     assert abs(d12 - printed) < 0.05e-3, d12   # printed to two significant figures
     assert np.max(np.abs(rho2 - rho_b)) < np.max(np.abs(rho1 - rho_b))
 
+
+
+@pytest.mark.parametrize("run", PRINTED["taylor_order_comparison"]["runs"], ids=lambda r: f"NK{r['N_K']}")
+def test_kappa_taylor_order_comparison(run):
+    """Sec. III.E, N_K-vs-dt trade-off: N_C = 1, N_x = 32, nu = 2, T = 5.6,
+    bounce-back; kappa about 3283 (N_K = 1, dt = 0.04375, N_t = 128) and 1058
+    (N_K = 3, dt = 0.7, N_t = 8), with lambda_L = 2^(label qubits) L_max and
+    L_max = max(1, dt max|A_ij|) (the wall entries C[1,0] - 1 give the max)."""
+    nx = 32
+    A = oc.carleman_matrix(nx, oc.tau_from_nu(nx, 2.0), 1, "bounceback")
+    nk, dt, nt = run["N_K"], run["dt"], run["N_t"]
+    n_k = int(np.ceil(np.log2(nk + 1)))
+    n_m = int(np.log2(nt)) + 1
+    L = oc.l_matrix(A, dt, nt, nk, n_m, n_k)
+    lam = 2.0 ** run["label_qubits"] * max(1.0, dt * abs(A).max())
+    kappa = lam / oc.sigma_min(L)
+    assert abs(kappa / run["kappa"] - 1.0) < 0.01, kappa
