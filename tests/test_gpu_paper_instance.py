@@ -12,7 +12,8 @@ Checks on the system amplitudes with the ancillas and the signal at 0:
   ten label Hadamards per call, 7.1e5 in all), which must itself stay inside
   that bound;
 * the final-time rows against the classical N_K = 3 Taylor solution:
-  1 - F below 1e-5;
+  1 - F below twice the square of the polynomial's relative error (plus 1e-9
+  for FP32);
 * the density at T = 0.4 (amplitudes rescaled by |b| / (c lambda_L)): off the
   exact second-order exponential by at most the Taylor solution's own error
   plus twice the polynomial's relative error times max rho, so far nearer to
@@ -96,7 +97,8 @@ def test_second_order_run_at_full_degree():
     # as infidelity, under the same bar
     leak = np.vdot(sys_amp[rest], sys_amp[rest]).real / np.vdot(sys_amp, sys_amp).real
     log(f"final-time rows: 1 - F vs Taylor {one_minus_f:.2e}; unphysical weight {leak:.1e}")
-    assert one_minus_f < 1e-5
+    # the polynomial's relative error e bounds 1 - F by about e^2; FP32 adds its infidelity
+    assert one_minus_f < 2.0 * poly_err ** 2 + 1e-9
     assert leak < 1e-6
 
     # density at T = N_t dt from the first final-time row
