@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+TILE_LAUNCH = 0   # sv_apply_opts.tile_launch for every fused plan (0: the library's default)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -100,7 +103,7 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
     for name, dtype, mode, elementary in variants:
         circ = cc.lower_to_elementary(native) if elementary else native
         ops, params = circ.arrays()
-        plan = sv.sv_plan_create(circ.n, dtype, ops, params, mode)
+        plan = sv.sv_plan_create(circ.n, dtype, ops, params, mode, tile_launch=TILE_LAUNCH)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(circ.n, dtype)
         sv.sv_set_amplitudes(st, rhs, 0)
@@ -173,7 +176,7 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     ops, params = c.arrays()
     out = {"qubits": n, "gates": len(c), "blocks": blocks, "depth": depth}
     for name, dmin in (("tile_vALU", 0), ("dense_mfma", 16)):
-        plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4, dmin)
+        plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4, dmin, tile_launch=TILE_LAUNCH)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(n, sv.SV_C64)
         sv.sv_plan_execute(plan, st, 1)
@@ -200,7 +203,7 @@ def largest_state(sv, d=1, reps=1):
     phases = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)[0] if d > 1 else np.zeros(2)
     circ = cc.build_qsvt(enc, phases)
     ops, params = circ.arrays()
-    plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED)
+    plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
     info = sv.sv_plan_get_info(plan)
     st = sv.sv_alloc(L.n, sv.SV_C64)
     sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
@@ -253,7 +256,7 @@ def paper_instance(sv, dtypes=("c64", "c128")):
     for name in dtypes:
         dt = sv.SV_C64 if name == "c64" else sv.SV_C128
         t0 = time.time()
-        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED)
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
         t_plan = time.time() - t0
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(L.n, dt)
@@ -303,7 +306,7 @@ def first_order_scan(sv, dtypes=("c64", "c128")):
     amps = {}
     for name in dtypes:
         dt = sv.SV_C64 if name == "c64" else sv.SV_C128
-        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED)
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(L.n, dt)
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
@@ -336,11 +339,15 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-carleman", action="store_true")
+    ap.add_argument("--tile-launch", choices=["auto", "grid", "persistent"], default="auto",
+                    help="how fused tile passes are launched (sv_apply_opts.tile_launch)")
     ap.add_argument("--sections", default="small,grid64,batch,dense,largest",
                     help="comma list of the secondary workloads to run (empty: none); "
                          "'paper' adds the full-degree second-order run (about 2 minutes), "
                          "'first_order' the longest ladder of the first-order degree scan")
     args = ap.parse_args()
+    global TILE_LAUNCH
+    TILE_LAUNCH = {"auto": 0, "grid": 1, "persistent": 2}[args.tile_launch]
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
               f"single MI355X and has no multi-GPU path)", file=sys.stderr)
@@ -356,7 +363,8 @@ def main():
     log(f"circuit: {n} qubits, {args.layers} layers, {n_gates} gates")
 
     # ---- fused complex64 (the headline) ----
-    plan64 = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits)
+    plan64 = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits,
+                               tile_launch=TILE_LAUNCH)
     info64 = sv.sv_plan_get_info(plan64)
     log(f"fused c64 plan: {info64}")
     st64 = sv.sv_alloc(n, sv.SV_C64)
@@ -371,7 +379,8 @@ def main():
     sv.sv_plan_execute(plan64, st64, 1)
 
     # ---- fused complex128 ----
-    plan128 = sv.sv_plan_create(n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits)
+    plan128 = sv.sv_plan_create(n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits,
+                                tile_launch=TILE_LAUNCH)
     info128 = sv.sv_plan_get_info(plan128)
     st128 = sv.sv_alloc(n, sv.SV_C128)
     sv.sv_plan_execute(plan128, st128, 1)

@@ -93,7 +93,16 @@ typedef struct {
     int dense_min_ops; /* fused, complex64: a run of at least this many consecutive ops
                           acting inside 5 qubits (targets and controls) becomes one dense
                           32 x 32 block applied with FP32 matrix cores; 0 = never        */
+    int tile_launch;   /* fused: how tile passes are launched. SV_TILE_LAUNCH_AUTO (0),
+                          SV_TILE_LAUNCH_GRID (1): one workgroup per tile,
+                          SV_TILE_LAUNCH_PERSISTENT (2): one resident workgroup set that
+                          walks the tiles, loading the next tile while computing one.
+                          Results are identical; only the timing differs.            */
 } sv_apply_opts;
+
+#define SV_TILE_LAUNCH_AUTO 0
+#define SV_TILE_LAUNCH_GRID 1
+#define SV_TILE_LAUNCH_PERSISTENT 2
 
 typedef struct sv_state sv_state;
 typedef struct sv_plan sv_plan;

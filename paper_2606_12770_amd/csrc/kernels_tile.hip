@@ -15,6 +15,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "sv_internal.h"
 
 namespace svi {
@@ -52,33 +57,61 @@ __device__ __forceinline__ C row2(R ar, R ai, R br, R bi, C a, C b)
     return r;
 }
 
-__device__ __forceinline__ uint32_t apply_perms(uint32_t l, const TileOp *__restrict__ perms, uint32_t pb,
-                                                uint32_t pe, uint64_t base)
+// First word of an op record (kind, slot, a, b), read whole: sub-dword fields
+// would be fetched with per-lane vector loads (there are no 8- or 16-bit
+// scalar loads), whose waits also drain every older vector load in flight.
+__device__ __forceinline__ uint32_t op_head(const TileOp *op)
+{
+    const void *src = __builtin_assume_aligned(op, 8);
+    uint32_t w;
+    __builtin_memcpy(&w, src, sizeof(w));
+    return w;
+}
+
+// The permutations of an LDS exchange applied to the local index l[s] of every
+// register slot.  The op records are read once per op, outside any per-lane
+// branch (so as scalar loads), and each slot is updated without branches.
+template <int NR>
+__device__ __forceinline__ void apply_perms(uint32_t (&l)[NR], const TileOp *__restrict__ perms, uint32_t pb,
+                                            uint32_t pe, uint64_t base)
 {
     for (uint32_t k = pb; k < pe; ++k) {
-        const TileOp p = perms[k];
+        const TileOp &p = perms[k];
         if ((base & p.gmask) != p.gval) continue;
-        if ((l & p.lmask) != p.lval) continue;
-        switch (p.kind) {
+        const uint32_t lmask = p.lmask, lval = p.lval;
+        const uint32_t head = op_head(&p);
+        const uint32_t kind = head & 0xffu, pa = (head >> 16) & 0xffu, pbits = head >> 24;
+        switch (kind) {
         case T_INC:
         case T_DEC: {
-            const uint32_t m = (1u << p.b) - 1u;
-            uint32_t v = (l >> p.a) & m;
-            v = (p.kind == T_INC ? v + 1u : v - 1u) & m;
-            l = (l & ~(m << p.a)) | (v << p.a);
+            const uint32_t m = ((1u << pbits) - 1u) << pa;
+            const uint32_t step = (kind == T_INC ? 1u : (uint32_t)-1) << pa;
+#pragma unroll
+            for (int s = 0; s < NR; ++s) {
+                const uint32_t v = ((l[s] & m) + step) & m;
+                l[s] = ((l[s] & lmask) == lval) ? ((l[s] & ~m) | v) : l[s];
+            }
             break;
         }
-        case T_SWAP:
-            if (((l >> p.a) ^ (l >> p.b)) & 1u) l ^= (1u << p.a) | (1u << p.b);
+        case T_SWAP: {
+            const uint32_t a = pa, b = pbits, both = (1u << a) | (1u << b);
+#pragma unroll
+            for (int s = 0; s < NR; ++s) {
+                const bool hit = ((l[s] & lmask) == lval) && ((((l[s] >> a) ^ (l[s] >> b)) & 1u) != 0u);
+                l[s] = hit ? (l[s] ^ both) : l[s];
+            }
             break;
-        case T_XFLIP:
-            l ^= 1u << p.a;
+        }
+        case T_XFLIP: {
+            const uint32_t f = 1u << pa;
+#pragma unroll
+            for (int s = 0; s < NR; ++s) l[s] = ((l[s] & lmask) == lval) ? (l[s] ^ f) : l[s];
             break;
+        }
         default:
             break;
         }
     }
-    return l;
 }
 
 // Register-level ops: slot s (with the target slot bit clear) is processed when
@@ -149,17 +182,40 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
         SV_SLOT_DISPATCH1(FN, false, __VA_ARGS__)                       \
     }
 
-// One tile of one pass: load, register stages with LDS exchanges, store.
-// The caller passes the tile counter; every thread of the workgroup calls this.
-// Every pointer comes straight from kernel arguments (plus uniform offsets), so
-// the compiler knows the address spaces and reads the plan tables with scalar
-// loads; pointers read from memory would turn those into per-lane flat loads.
+// Absolute index bits of a tile (uniform): bit runs of the tile counter.
+__device__ __forceinline__ uint64_t tile_base(const TilePass *__restrict__ pass, uint64_t tile)
+{
+    uint64_t base = 0;
+    for (uint32_t r = 0; r < pass->n_tile_runs; ++r) {
+        const uint32_t sh = pass->tile_shift[r];
+        base |= ((tile >> (sh & 0xffu)) & pass->tile_mask[r]) << (sh >> 8);
+    }
+    return base;
+}
+
+// Load mapping: thread bits = local bits [0, nthr), slots = local bits [nthr, b).
+__device__ __forceinline__ uint64_t tile_thread_offset(const TilePass *__restrict__ pass, uint32_t tid)
+{
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < pass->n_gthr_runs; ++r) {
+        const uint32_t sh = pass->gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & pass->gthr_mask[r]) << (sh >> 8);
+    }
+    return gthr;
+}
+
+// The register stages and LDS exchanges of one tile, on amplitudes already in
+// registers (load mapping in, load mapping out).  Every thread of the
+// workgroup calls this.  Every pointer comes straight from kernel arguments
+// (plus uniform offsets), so the compiler knows the address spaces and reads
+// the plan tables with scalar loads; pointers read from memory would turn
+// those into per-lane flat loads.
 template <typename R, int RB>
-__device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
-                                               const TilePass *__restrict__ pass,
-                                               const TileStage *__restrict__ stages,
-                                               const TileOp *__restrict__ ops, const R *__restrict__ prm,
-                                               uint64_t tile, typename CTT<R>::T *lds)
+__device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
+                                             const TilePass *__restrict__ pass,
+                                             const TileStage *__restrict__ stages,
+                                             const TileOp *__restrict__ ops, const R *__restrict__ prm,
+                                             uint64_t base, bool final_exchange, typename CTT<R>::T *lds)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
@@ -167,26 +223,6 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     constexpr uint32_t kAllSlots = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t nthr = pass->nthr;
-
-    // absolute index bits of this tile (uniform): bit runs of the tile counter
-    uint64_t base = 0;
-    for (uint32_t r = 0; r < pass->n_tile_runs; ++r) {
-        const uint32_t sh = pass->tile_shift[r];
-        base |= ((tile >> (sh & 0xffu)) & pass->tile_mask[r]) << (sh >> 8);
-    }
-    // load mapping: thread bits = local bits [0, nthr), slots = local bits [nthr, b)
-    uint64_t gthr = 0;
-    for (uint32_t r = 0; r < pass->n_gthr_runs; ++r) {
-        const uint32_t sh = pass->gthr_shift[r];
-        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & pass->gthr_mask[r]) << (sh >> 8);
-    }
-    C *const pt = psi + (base | gthr);
-
-    C x[NR];
-#pragma unroll
-    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
-
     // current mapping: local index of slot s = thr | regoff[s] (disjoint bits);
     // the LDS swizzle is GF(2)-linear, so its slot part comes precomputed
     uint32_t thr = tid;
@@ -201,10 +237,17 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
 #pragma unroll
                 for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
             } else {
+                // slots in groups of four: the op records are scalar loads,
+                // cheap to repeat, while the indices of all slots at once
+                // would cost registers that lower the occupancy
 #pragma unroll
-                for (int s = 0; s < NR; ++s) {
-                    const uint32_t l = apply_perms(thr | P.regoff[s], ops, S.perm_begin, S.perm_end, base);
-                    lds[lds_swizzle(l, LOWB)] = x[s];
+                for (int g = 0; g < NR; g += 4) {
+                    uint32_t l[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) l[s] = thr | P.regoff[g + s];
+                    apply_perms<4>(l, ops, S.perm_begin, S.perm_end, base);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
                 }
             }
             __syncthreads();
@@ -274,7 +317,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
         }
     }
 
-    if (pass->final_exchange) {
+    if (final_exchange) {
         const TileStage &L = stages[se - 1];
         __syncthreads();
         if (pass->fperm_begin == pass->fperm_end) {
@@ -283,9 +326,13 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
             for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (L.swz[s] * (uint32_t)sizeof(C))) = x[s];
         } else {
 #pragma unroll
-            for (int s = 0; s < NR; ++s) {
-                const uint32_t l = apply_perms(thr | L.regoff[s], ops, pass->fperm_begin, pass->fperm_end, base);
-                lds[lds_swizzle(l, LOWB)] = x[s];
+            for (int g = 0; g < NR; g += 4) {
+                uint32_t l[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) l[s] = thr | L.regoff[g + s];
+                apply_perms<4>(l, ops, pass->fperm_begin, pass->fperm_end, base);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
             }
         }
         __syncthreads();
@@ -293,8 +340,84 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
 #pragma unroll
         for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (pass->swz0[s] * (uint32_t)sizeof(C)));
     }
+}
+
+// The pass's final-exchange flag, read as a whole aligned word (the flag and
+// its padding at offset 20) before any barrier, so that it is a scalar load.
+__device__ __forceinline__ bool pass_final_exchange(const TilePass *__restrict__ pass)
+{
+    uint32_t w;
+    __builtin_memcpy(&w, __builtin_assume_aligned(&pass->final_exchange, 4), sizeof(w));
+    return (w & 0xffu) != 0u;
+}
+
+// One tile of one pass: load, register stages with LDS exchanges, store.
+template <typename R, int RB>
+__device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
+                                               const TilePass *__restrict__ pass,
+                                               const TileStage *__restrict__ stages,
+                                               const TileOp *__restrict__ ops, const R *__restrict__ prm,
+                                               uint64_t tile, typename CTT<R>::T *lds)
+{
+    using C = typename CTT<R>::T;
+    constexpr int NR = 1 << RB;
+    const uint64_t base = tile_base(pass, tile);
+    C *const pt = psi + (base | tile_thread_offset(pass, threadIdx.x));
+    C x[NR];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
+    tile_compute<R, RB>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
 #pragma unroll
     for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+}
+
+// Persistent form: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
+// and issues the loads of its next tile before computing the current one, so
+// the HBM reads of one tile overlap the arithmetic of the previous one.  The
+// tiles are disjoint, so the prefetch never reads what another tile writes.
+// The first LDS exchange of every tile begins with a barrier, which orders it
+// after the previous tile's last LDS reads.
+template <typename R, int RB>
+__global__ void __launch_bounds__(256)
+k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
+                 const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
+                 uint64_t n_tiles)
+{
+    using C = typename CTT<R>::T;
+    constexpr int NR = 1 << RB;
+    extern __shared__ unsigned char smem_raw[];
+    C *const lds = reinterpret_cast<C *>(smem_raw);
+    uint64_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const uint64_t stride = gridDim.x;
+    const uint64_t gthr = tile_thread_offset(pass, threadIdx.x);
+    const bool fx = pass_final_exchange(pass);
+    uint64_t base_next = tile_base(pass, tile);
+    C xn[NR];
+    {
+        const C *const pn = psi + (base_next | gthr);
+#pragma unroll
+        for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
+    }
+    for (;;) {
+        C x[NR];
+#pragma unroll
+        for (int s = 0; s < NR; ++s) x[s] = xn[s];
+        const uint64_t base = base_next;
+        const uint64_t next = tile + stride;
+        if (next < n_tiles) {
+            base_next = tile_base(pass, next);
+            const C *const pn = psi + (base_next | gthr);
+#pragma unroll
+            for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
+        }
+        tile_compute<R, RB>(x, pass, stages, ops, prm, base, fx, lds);
+        C *const pt = psi + (base | gthr);
+#pragma unroll
+        for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+        if (next >= n_tiles) break;
+        tile = next;
+    }
 }
 
 template <typename R, int RB>
@@ -334,12 +457,43 @@ k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict_
                           reinterpret_cast<C *>(smem_raw));
 }
 
+// Resident workgroups of the persistent kernel on the whole device, cached per
+// (kernel, block, LDS) shape.
+template <typename R, int RB>
+static uint64_t pipe_grid(uint32_t block, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::pair<uint32_t, size_t>, uint64_t> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(block, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_tile_pass_pipe<R, RB>, (int)block,
+                                                     lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    (void)hipGetLastError();
+    const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+    cache[key] = g;
+    return g;
+}
+
 template <typename R, int RB>
 static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const TilePass &P = p->passes[pi];
     const uint64_t tiles = 1ull << P.ntile;
+    if (p->tile_launch == SV_TILE_LAUNCH_PERSISTENT) {
+        const uint32_t block = 1u << P.nthr;
+        const size_t lds = sizeof(C) << P.b;
+        const uint64_t g = std::min<uint64_t>(tiles, pipe_grid<R, RB>(block, lds));
+        hipLaunchKernelGGL((k_tile_pass_pipe<R, RB>), dim3((uint32_t)g), dim3(block), lds, st, (C *)psi,
+                           (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
+                           (const TileOp *)p->d_tops, (const R *)p->d_tparams, tiles);
+        return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
+    }
     const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
     const uint32_t gy = (uint32_t)(tiles / gx);
     const dim3 grid(gx, gy);
@@ -392,6 +546,10 @@ int tile_kernel_setup()
     (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -66,7 +66,8 @@ constexpr int kMaxRB = 5;
 constexpr int kMaxB = 14;
 constexpr int kMaxThrRuns = 8;
 constexpr int kMaxTileRuns = 16;
-constexpr int kParamStride = 8;  // reals of parameters reserved per tile op (op k at k * 8)
+constexpr int kParamStride = 8;
+constexpr int kDefaultTileLaunch = SV_TILE_LAUNCH_GRID;  // what SV_TILE_LAUNCH_AUTO resolves to  // reals of parameters reserved per tile op (op k at k * 8)
 
 // LDS placement of local index l: XOR-fold the higher bits into the lowest
 // `lowb` bits so that threads strided by any power of two hit different banks.
@@ -89,7 +90,7 @@ struct TileStage {
     uint32_t thr_run[kMaxThrRuns];
     uint32_t swz[1 << kMaxRB];      // lds_swizzle(regoff[s])
     uint8_t thrpos[16];             // local bit index of thread bit j
-    uint16_t regoff[1 << kMaxRB];   // local index offset of register slot s
+    uint32_t regoff[1 << kMaxRB];   // local index offset of register slot s (32-bit: read with scalar loads)
 };
 
 struct TilePass {
@@ -182,6 +183,7 @@ struct sv_plan {
     int n = 0;
     int dtype = SV_C64;
     int b = 0, rb = 0;
+    int tile_launch = 1;              // SV_TILE_LAUNCH_GRID or SV_TILE_LAUNCH_PERSISTENT (resolved)
     std::vector<svi::Step> steps;
     std::vector<svi::PlainOp> plain;
     std::vector<svi::TilePass> passes;

@@ -563,7 +563,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 uint32_t off = 0;
                 for (int k = 0; k < rb; ++k)
                     if ((s >> k) & 1) off |= 1u << rs[k];
-                S.regoff[s] = (uint16_t)off;
+                S.regoff[s] = (uint32_t)off;
                 S.swz[s] = lds_swizzle(off, lowb);
             }
             S.n_thr_runs = 0;

@@ -322,6 +322,8 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     if (opts) o = *opts;
     if (o.mode != SV_MODE_PLAIN && o.mode != SV_MODE_FUSED) return fail(SV_EINVAL, "unknown mode");
     if (o.dense_min_ops < 0) return fail(SV_EINVAL, "dense_min_ops must be >= 0");
+    if (o.tile_launch < SV_TILE_LAUNCH_AUTO || o.tile_launch > SV_TILE_LAUNCH_PERSISTENT)
+        return fail(SV_EINVAL, "unknown tile_launch");
     int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
     if (rc != SV_OK) return rc;
     int dev = 0;
@@ -332,6 +334,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     if (!p) return fail(SV_ENOMEM, "host allocation failed");
     p->n = n_qubits;
     p->dtype = dtype;
+    p->tile_launch = o.tile_launch == SV_TILE_LAUNCH_AUTO ? svi::kDefaultTileLaunch : o.tile_launch;
     std::string err;
     rc = svi::build_plan(p, ops, n_ops, params, o, err);
     if (rc != SV_OK) {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsv.so")
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EZEROPROB, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SV_C64, SV_C128 = 0, 1
 SV_MODE_PLAIN, SV_MODE_FUSED = 0, 1
+SV_TILE_LAUNCH_AUTO, SV_TILE_LAUNCH_GRID, SV_TILE_LAUNCH_PERSISTENT = 0, 1, 2
 
 EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
@@ -36,7 +37,7 @@ class SVError(RuntimeError):
 
 class sv_apply_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int),
-                ("dense_min_ops", ctypes.c_int)]
+                ("dense_min_ops", ctypes.c_int), ("tile_launch", ctypes.c_int)]
 
 
 class sv_plan_info(ctypes.Structure):
@@ -105,8 +106,8 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
-    return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops)
+def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0, tile_launch=0):
+    return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch)
 
 
 # ---- the C entry points under their own names -------------------------------
@@ -139,16 +140,18 @@ def _ops_params(ops, params):
     return ops, params
 
 
-def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
+def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
+                     tile_launch=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch)
     _check(load_library().sv_apply_circuit(state, ops.ctypes.data, len(ops), _dp(params), len(params),
                                            ctypes.byref(o)))
 
 
-def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0):
+def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
+                   tile_launch=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch)
     out = ctypes.c_void_p()
     _check(load_library().sv_plan_create(n_qubits, dtype, ops.ctypes.data, len(ops), _dp(params), len(params),
                                          ctypes.byref(o), ctypes.byref(out)))

@@ -191,7 +191,7 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
             }
         for (int t = 0; t < T; ++t) thr[t] = t;
         for (int s = 0; s < NR; ++s) ro[s] = (uint32_t)s << nthr;
-        auto exchange = [&](uint32_t pb, uint32_t pe, const uint8_t *thrpos, const uint16_t *regoff) -> int {
+        auto exchange = [&](uint32_t pb, uint32_t pe, const uint8_t *thrpos, const uint32_t *regoff) -> int {
             std::fill(filled.begin(), filled.end(), 0);
             for (int t = 0; t < T; ++t)
                 for (int s = 0; s < NR; ++s) {
@@ -280,9 +280,9 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
         // the last stage must leave the load mapping unless a final exchange follows
         if (P.final_exchange) {
             uint8_t thrpos0[16];
-            uint16_t regoff0[1 << kMaxRB];
+            uint32_t regoff0[1 << kMaxRB];
             for (int j = 0; j < nthr; ++j) thrpos0[j] = (uint8_t)j;
-            for (int s = 0; s < NR; ++s) regoff0[s] = (uint16_t)(s << nthr);
+            for (int s = 0; s < NR; ++s) regoff0[s] = (uint32_t)(s << nthr);
             int rc = exchange(P.fperm_begin, P.fperm_end, thrpos0, regoff0);
             if (rc) return rc;
         } else {

@@ -193,3 +193,26 @@ def test_ul_block_encoding_full_size(name):
     assert abs(norm2 - 1.0) < 1e-4
     assert err < 1e-5
     assert leak < 1e-5 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_c1_ladder_persistent_tile_launch(dtype):
+    """The permutation-heavy Carleman ladder (d = 13, 22 qubits) with the
+    persistent tile launch: bit for bit the one-workgroup-per-tile result and
+    within the usual bars of the oracle."""
+    sv = require_gpu()
+    circ, psi0, want = c1_ladder("native")
+    ops, params = circ.arrays()
+    outs = []
+    for form in (sv.SV_TILE_LAUNCH_PERSISTENT, sv.SV_TILE_LAUNCH_GRID):
+        plan = sv.sv_plan_create(circ.n, dtype, ops, params, sv.SV_MODE_FUSED, tile_launch=form)
+        st = sv.State(circ.n, dtype, psi0)
+        sv.sv_plan_execute(plan, st.h, 1)
+        outs.append(st.amplitudes())
+        st.close()
+        sv.sv_plan_free(plan)
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    if dtype == 1:
+        assert np.max(np.abs(outs[0] - want)) < 1e-12
+    else:
+        assert infid(want, outs[0]) < 1e-6

@@ -163,3 +163,53 @@ def test_benchmark_configuration_28q_prefix(dtype):
     f = infid(want, got)
     print(f"28q prefix dtype={dtype} infid={f:.2e}", flush=True)
     assert f < (1e-12 if dtype == 1 else 1e-6)
+
+
+def _run_plan(sv, circ, psi0, dtype, tile_launch, b=0, rb=0):
+    ops, params = circ.arrays()
+    plan = sv.sv_plan_create(circ.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=tile_launch)
+    st = sv.State(circ.n, dtype, psi0)
+    sv.sv_plan_execute(plan, st.h, 1)
+    out = st.amplitudes()
+    st.close()
+    sv.sv_plan_free(plan)
+    return out
+
+
+@pytest.mark.parametrize("n,b,rb", [(12, 12, 4), (16, 12, 4), (18, 12, 4), (20, 11, 5)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_persistent_tile_launch_matches_oracle(n, b, rb, dtype):
+    """The persistent launch form (resident workgroups walking the tiles, the
+    next tile's loads in flight) against the FP64 reference simulator, and bit
+    for bit against one workgroup per tile (same passes, same arithmetic)."""
+    sv = require_gpu()
+    c = random_mixed_circuit(n, 400, seed=5 * n + b + dtype, max_ctrl=6)
+    psi0 = random_state(n, 3)
+    want = osv.run(c, psi0)
+    got = _run_plan(sv, c, psi0, dtype, sv.SV_TILE_LAUNCH_PERSISTENT, b, rb)
+    grid = _run_plan(sv, c, psi0, dtype, sv.SV_TILE_LAUNCH_GRID, b, rb)
+    print(f"persistent n={n} b={b} rb={rb} dtype={dtype} infid={infid(want, got):.2e}", flush=True)
+    assert np.array_equal(got.view(np.uint64), grid.view(np.uint64))
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert infid(want, got) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_persistent_tile_launch_many_tiles_per_workgroup(dtype):
+    """26 qubits (16,384 tiles: several per resident workgroup) and the
+    benchmark's launch geometry: bit for bit equal to one workgroup per tile,
+    and the inverse circuit returns |0...0>."""
+    sv = require_gpu()
+    n = 26
+    c = random_mixed_circuit(n, 300, seed=11 + dtype, max_ctrl=6)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1.0
+    got = _run_plan(sv, c, psi0, dtype, sv.SV_TILE_LAUNCH_PERSISTENT)
+    grid = _run_plan(sv, c, psi0, dtype, sv.SV_TILE_LAUNCH_GRID)
+    assert np.array_equal(got.view(np.uint64), grid.view(np.uint64))
+    back = _run_plan(sv, c.dagger(), got, dtype, sv.SV_TILE_LAUNCH_PERSISTENT)
+    p0 = abs(back[0]) ** 2 / np.vdot(back, back).real
+    print(f"persistent 26q dtype={dtype}: |<0|U^dagger U|0>|^2 = {p0:.15f}", flush=True)
+    assert 1.0 - p0 < (1e-12 if dtype == 1 else 1e-5)

@@ -116,3 +116,18 @@ def test_postselect_and_inner():
     assert np.max(np.abs(work - want)) < 1e-15
     b = random_state(n, 22)
     assert abs(osv.inner(psi, b, n) - np.vdot(psi, b)) < 1e-14
+
+
+def test_projphase_equals_its_three_gate_form():
+    """The projector-controlled phase of the QSVT circuit figure (Sec. II.D.5)
+    written literally: MCX from the condition onto the signal, diag(e^{i theta},
+    e^{-i theta}) on the signal, the same MCX; against the collapsed op."""
+    n, s, mask, val, th = 7, 3, 0b1100101, 0b0100001, -0.81
+    psi0 = random_state(n, 4)
+    ctrl = {q: (val >> q) & 1 for q in range(n) if (mask >> q) & 1}
+    lit = Circuit(n)
+    lit.x(s, ctrl)
+    lit.u(s, np.diag([np.exp(1j * th), np.exp(-1j * th)]))
+    lit.x(s, ctrl)
+    got = osv.run(Circuit(n).projphase(s, mask, val, th), psi0)
+    assert np.max(np.abs(got - osv.run(lit, psi0))) < 1e-15
