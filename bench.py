@@ -253,10 +253,14 @@ def paper_instance(sv, dtypes=("c64", "c128")):
            "setup_s": {"phases": t_phase, "ladder_arrays": t_arrays},
            "polynomial_rel_err": err, "phase_residual": res}
     amps = {}
+    from paper_2606_12770_amd import autotune
     for name in dtypes:
         dt = sv.SV_C64 if name == "c64" else sv.SV_C128
         t0 = time.time()
-        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
+        (b, rb), tuned = autotune.tune_ladder(enc, dt)
+        t_tune = time.time() - t0
+        t0 = time.time()
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=TILE_LAUNCH)
         t_plan = time.time() - t0
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(L.n, dt)
@@ -271,11 +275,13 @@ def paper_instance(sv, dtypes=("c64", "c128")):
         sv.sv_free(st)
         sv.sv_plan_free(plan)
         gb = info["bytes_moved"] / (ms / 1e3) / 1e9
-        out[name] = {"plan_s": t_plan, "gpu_ms": ms, "gpu_wall_s": wall, "gates_per_s": len(ops) / (ms / 1e3),
+        out[name] = {"geometry": [b, rb], "tune_s": t_tune,
+                     "tuned_ms_proxy_d1001": {f"{k[0]},{k[1]}": v for k, v in tuned.items()},
+                     "plan_s": t_plan, "gpu_ms": ms, "gpu_wall_s": wall, "gates_per_s": len(ops) / (ms / 1e3),
                      "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
                      "GBps_algorithmic": gb, "norm_drift": abs(norm2 - 1.0),
                      "postselect_prob_final_rows": P_final}
-        log(f"paper instance {name}: plan {t_plan:.1f} s, GPU {ms / 1e3:.2f} s ({len(ops) / ms * 1e3:.3g} gates/s, "
+        log(f"paper instance {name}: geometry ({b},{rb}) tuned in {t_tune:.1f} s, plan {t_plan:.1f} s, GPU {ms / 1e3:.2f} s ({len(ops) / ms * 1e3:.3g} gates/s, "
             f"{info['n_tile_passes']} passes, {gb:.0f} GB/s), norm drift {abs(norm2 - 1):.2e}, P_final {P_final:.3e}")
     if "c64" in amps and "c128" in amps:
         a, b = amps["c64"], amps["c128"]
@@ -304,9 +310,11 @@ def first_order_scan(sv, dtypes=("c64", "c128")):
            "config": {"nx": cfg.nx, "nt": cfg.nt, "nk": cfg.nk, "dt": cfg.dt, "tau": cfg.tau, "order": 1,
                       "boundary": cfg.boundary, "drho": cfg.drho}}
     amps = {}
+    from paper_2606_12770_amd import autotune
     for name in dtypes:
         dt = sv.SV_C64 if name == "c64" else sv.SV_C128
-        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
+        (b, rb), _tuned = autotune.tune_ladder(enc, dt)
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=TILE_LAUNCH)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(L.n, dt)
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
@@ -315,10 +323,11 @@ def first_order_scan(sv, dtypes=("c64", "c128")):
         sv.sv_free(st)
         sv.sv_plan_free(plan)
         gb = info["bytes_moved"] / (ms / 1e3) / 1e9
-        out[name] = {"gpu_ms": ms, "gates_per_s": len(ops) / (ms / 1e3), "tile_passes": info["n_tile_passes"],
+        out[name] = {"geometry": [b, rb], "gpu_ms": ms, "gates_per_s": len(ops) / (ms / 1e3),
+                     "tile_passes": info["n_tile_passes"],
                      "launches": info["n_launches"], "GBps_algorithmic": gb,
                      "avg_launch_us": ms * 1e3 / max(1, info["n_launches"])}
-        log(f"first-order scan {name}: d {d}, {len(ops)} ops, {ms:.0f} ms, {len(ops) / ms * 1e3:.3g} gates/s, "
+        log(f"first-order scan {name}: geometry ({b},{rb}), d {d}, {len(ops)} ops, {ms:.0f} ms, {len(ops) / ms * 1e3:.3g} gates/s, "
             f"{info['n_launches']} launches ({ms * 1e3 / max(1, info['n_launches']):.1f} us each), {gb:.0f} GB/s")
     if "c64" in amps and "c128" in amps:
         a, b = amps["c64"], amps["c128"]

@@ -83,3 +83,34 @@ def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_gra
     best = min(times, key=times.get)
     _cache[key] = (best, times)
     return _cache[key]
+
+
+def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES):
+    """Fastest (b, rb) for a QSVT ladder of the block encoding `enc`, timed on a
+    proxy ladder of `proxy_degree` calls (the pass structure repeats every two
+    calls, so a short ladder ranks the geometries as the full one does) on a
+    scratch state.  Returns ((b, rb), {geometry: ms})."""
+    import numpy as np
+    from .circuits import carleman_circuit as cc
+    n = enc.layout.n
+    ops, params = cc.build_qsvt_arrays(enc, np.zeros(proxy_degree + 1))
+    key = ("ladder", hashlib.sha1(ops.tobytes()).hexdigest(), n, dtype)
+    if key in _cache:
+        return _cache[key]
+    state = sv.sv_alloc(n, dtype)
+    times = {}
+    try:
+        for b, rb in candidates:
+            if not _valid(n, b, rb):
+                continue
+            p = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb)
+            try:
+                sv.sv_plan_execute(p, state, 1)
+                times[(b, rb)] = sv.sv_plan_time(p, state, 1)
+            finally:
+                sv.sv_plan_free(p)
+    finally:
+        sv.sv_free(state)
+    best = min(times, key=times.get)
+    _cache[key] = (best, times)
+    return _cache[key]

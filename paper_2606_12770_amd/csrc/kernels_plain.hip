@@ -383,21 +383,14 @@ int launch_to_c128(const void *psi, int dtype, void *d_dst, uint64_t offset, uin
     return status();
 }
 
-// Same-precision copy: 16-byte vectors, four independent loads in flight per
-// thread per iteration.  count16 = bytes / 16.
+// Same-precision copy in 16-byte vectors; count16 = bytes / 16.
 __global__ void __launch_bounds__(256) k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
                                                 uint64_t count16)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < count16; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < count16; i += stride) dst[i] = src[i];
+    // one 16-byte element per thread: every wave's loads are in flight at once
+    // (measured faster than grid-stride loops with several elements per thread)
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count16) dst[i] = src[i];
 }
 
 int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t st)
@@ -406,8 +399,7 @@ int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t
     const dim3 g(grid_for(dim, 256)), b(256);
     if (dts == dtd && (dim * (dts == SV_C64 ? 8 : 16)) % 16 == 0) {
         const uint64_t c16 = dim * (dts == SV_C64 ? 8 : 16) / 16;
-        uint64_t blocks = (c16 + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
+        const uint64_t blocks = (c16 + 255) / 256;  // at most 2^28 for 36 qubits in complex128
         hipLaunchKernelGGL(k_copy16, dim3((uint32_t)blocks), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src, c16);
     } else if (dts == SV_C64 && dtd == SV_C64)
         hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, st, (float2 *)dst, (const float2 *)src, dim);

@@ -25,8 +25,52 @@
 namespace svi {
 
 template <typename R> struct CTT;
-template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4; };
-template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
+template <> struct CTT<float> {
+    using T = float2;
+    using V = float __attribute__((ext_vector_type(2)));  // the same bits as a native vector
+    static constexpr int LOWB = 4;
+};
+template <> struct CTT<double> {
+    using T = double2;
+    using V = double __attribute__((ext_vector_type(2)));
+    static constexpr int LOWB = 3;
+};
+
+// Amplitude traffic hints (bit 0: loads, bit 1: stores marked non-temporal).
+// A pass over a state far larger than the last-level cache streams every
+// amplitude once; non-temporal accesses keep it from displacing lines and,
+// for stores, avoid write-allocate traffic.  States that fit the cache keep
+// ordinary accesses so that consecutive passes hit it.
+constexpr uint32_t kNtLoad = 1u, kNtStore = 2u;
+
+template <typename R>
+__device__ __forceinline__ typename CTT<R>::T amp_load(const typename CTT<R>::T *p, uint32_t hint)
+{
+    using C = typename CTT<R>::T;
+    using V = typename CTT<R>::V;
+    if (hint & kNtLoad) {
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+        C c;
+        c.x = v.x;
+        c.y = v.y;
+        return c;
+    }
+    return *p;
+}
+
+template <typename R>
+__device__ __forceinline__ void amp_store(typename CTT<R>::T *p, typename CTT<R>::T c, uint32_t hint)
+{
+    using V = typename CTT<R>::V;
+    if (hint & kNtStore) {
+        V v;
+        v.x = c.x;
+        v.y = c.y;
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+        return;
+    }
+    *p = c;
+}
 
 
 // LDS element at byte offset `off` (the swizzle XOR is done on byte offsets:
@@ -357,7 +401,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
                                                const TilePass *__restrict__ pass,
                                                const TileStage *__restrict__ stages,
                                                const TileOp *__restrict__ ops, const R *__restrict__ prm,
-                                               uint64_t tile, typename CTT<R>::T *lds)
+                                               uint64_t tile, uint32_t hint, typename CTT<R>::T *lds)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
@@ -365,10 +409,10 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     C *const pt = psi + (base | tile_thread_offset(pass, threadIdx.x));
     C x[NR];
 #pragma unroll
-    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
+    for (int s = 0; s < NR; ++s) x[s] = amp_load<R>(pt + pass->goff[s], hint);
     tile_compute<R, RB>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
 #pragma unroll
-    for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+    for (int s = 0; s < NR; ++s) amp_store<R>(pt + pass->goff[s], x[s], hint);
 }
 
 // Persistent form: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
@@ -381,7 +425,7 @@ template <typename R, int RB>
 __global__ void __launch_bounds__(256)
 k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
                  const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
-                 uint64_t n_tiles)
+                 uint64_t n_tiles, uint32_t hint)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
@@ -397,7 +441,7 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
     {
         const C *const pn = psi + (base_next | gthr);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
+        for (int s = 0; s < NR; ++s) xn[s] = amp_load<R>(pn + pass->goff[s], hint);
     }
     for (;;) {
         C x[NR];
@@ -409,12 +453,12 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
             base_next = tile_base(pass, next);
             const C *const pn = psi + (base_next | gthr);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
+            for (int s = 0; s < NR; ++s) xn[s] = amp_load<R>(pn + pass->goff[s], hint);
         }
         tile_compute<R, RB>(x, pass, stages, ops, prm, base, fx, lds);
         C *const pt = psi + (base | gthr);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+        for (int s = 0; s < NR; ++s) amp_store<R>(pt + pass->goff[s], x[s], hint);
         if (next >= n_tiles) break;
         tile = next;
     }
@@ -423,12 +467,13 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
 template <typename R, int RB>
 __global__ void __launch_bounds__(256)
 k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
-            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
+            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
+            uint32_t hint)
 {
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
     const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, hint, reinterpret_cast<C *>(smem_raw));
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
@@ -453,7 +498,7 @@ k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict_
         if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
     const BatchItem &B = items[lo];
-    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
+    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin, 0u,
                           reinterpret_cast<C *>(smem_raw));
 }
 
@@ -479,19 +524,24 @@ static uint64_t pipe_grid(uint32_t block, size_t lds)
     return g;
 }
 
+// States above this size stream through a pass (the last-level cache is 256 MB).
+constexpr uint64_t kStreamBytes = 512ull << 20;
+constexpr uint32_t kStreamHint = kNtLoad | kNtStore;
+
 template <typename R, int RB>
 static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const TilePass &P = p->passes[pi];
     const uint64_t tiles = 1ull << P.ntile;
+    const uint32_t hint = (sizeof(C) << p->n) > kStreamBytes ? kStreamHint : 0u;
     if (p->tile_launch == SV_TILE_LAUNCH_PERSISTENT) {
         const uint32_t block = 1u << P.nthr;
         const size_t lds = sizeof(C) << P.b;
         const uint64_t g = std::min<uint64_t>(tiles, pipe_grid<R, RB>(block, lds));
         hipLaunchKernelGGL((k_tile_pass_pipe<R, RB>), dim3((uint32_t)g), dim3(block), lds, st, (C *)psi,
                            (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                           (const TileOp *)p->d_tops, (const R *)p->d_tparams, tiles);
+                           (const TileOp *)p->d_tops, (const R *)p->d_tparams, tiles, hint);
         return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
     }
     const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
@@ -501,7 +551,7 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const size_t lds = sizeof(C) << P.b;
     hipLaunchKernelGGL((k_tile_pass<R, RB>), grid, block, lds, st, (C *)psi,
                        (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                       (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+                       (const TileOp *)p->d_tops, (const R *)p->d_tparams, hint);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
