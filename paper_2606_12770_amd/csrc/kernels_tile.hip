@@ -208,6 +208,51 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
     }
 }
 
+// Uncontrolled complex 2x2 gates on every register bit in MASK (bits 0..3),
+// matrices in consecutive parameter blocks in increasing bit order.
+template <int K, int NR, typename C, typename R>
+__device__ __forceinline__ void reg_u_block(C (&x)[NR], const R *__restrict__ pk)
+{
+    R m[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m[e] = pk[e];
+    reg_u<K, NR, true>(x, m, 0u);
+}
+
+template <int MASK, int NR, typename C, typename R>
+__device__ __forceinline__ void reg_um(C (&x)[NR], const R *__restrict__ pk)
+{
+    constexpr int n0 = (MASK & 1) ? 1 : 0;
+    constexpr int n1 = n0 + ((MASK & 2) ? 1 : 0);
+    constexpr int n2 = n1 + ((MASK & 4) ? 1 : 0);
+    if constexpr ((MASK & 1) != 0) reg_u_block<0>(x, pk);
+    if constexpr ((MASK & 2) != 0) reg_u_block<1>(x, pk + 8 * n0);
+    if constexpr ((MASK & 4) != 0) reg_u_block<2>(x, pk + 8 * n1);
+    if constexpr ((MASK & 8) != 0) reg_u_block<3>(x, pk + 8 * n2);
+}
+
+
+// Fixed homes for the amplitudes of the complex64, 16-slot tile at the head of
+// the op loop.  Each op case leaves its results wherever the register
+// allocator put them, and every merge of the cases back into the loop then
+// copies all 32 values between register sets (and holds both sets, which cost
+// a wave of occupancy).  Naming the registers at the loop head makes every
+// case write its results there.  The asm statements contain no instructions.
+template <int NR, typename C>
+__device__ __forceinline__ void fix_regs(C (&x)[NR])
+{
+    if constexpr (NR == 16 && sizeof(x[0].x) == 4) {
+        asm volatile("" : "+{v64}"(x[0].x), "+{v65}"(x[0].y), "+{v66}"(x[1].x), "+{v67}"(x[1].y),
+                          "+{v68}"(x[2].x), "+{v69}"(x[2].y), "+{v70}"(x[3].x), "+{v71}"(x[3].y),
+                          "+{v72}"(x[4].x), "+{v73}"(x[4].y), "+{v74}"(x[5].x), "+{v75}"(x[5].y),
+                          "+{v76}"(x[6].x), "+{v77}"(x[6].y), "+{v78}"(x[7].x), "+{v79}"(x[7].y));
+        asm volatile("" : "+{v80}"(x[8].x), "+{v81}"(x[8].y), "+{v82}"(x[9].x), "+{v83}"(x[9].y),
+                          "+{v84}"(x[10].x), "+{v85}"(x[10].y), "+{v86}"(x[11].x), "+{v87}"(x[11].y),
+                          "+{v88}"(x[12].x), "+{v89}"(x[12].y), "+{v90}"(x[13].x), "+{v91}"(x[13].y),
+                          "+{v92}"(x[14].x), "+{v93}"(x[14].y), "+{v94}"(x[15].x), "+{v95}"(x[15].y));
+    }
+}
+
 #define SV_SLOT_DISPATCH1(FN, F, ...)                                   \
     switch (op.slot) {                                                  \
     case 0: FN<0, NR, F>(__VA_ARGS__); break;                           \
@@ -310,9 +355,28 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
         TileOp nxt;
         if (S.op_begin < S.op_end) nxt = ops[S.op_begin];
         for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
+            fix_regs(x);
             const TileOp op = nxt;
             if (k + 1 < S.op_end) nxt = ops[k + 1];
             const R *__restrict__ pk = prm + (size_t)k * kParamStride;
+            if (op.kind == T_NOP) continue;
+            if (op.kind == T_UM) {
+                switch (op.slot) {
+                case 3: reg_um<3>(x, pk); break;
+                case 5: reg_um<5>(x, pk); break;
+                case 6: reg_um<6>(x, pk); break;
+                case 7: reg_um<7>(x, pk); break;
+                case 9: reg_um<9>(x, pk); break;
+                case 10: reg_um<10>(x, pk); break;
+                case 11: reg_um<11>(x, pk); break;
+                case 12: reg_um<12>(x, pk); break;
+                case 13: reg_um<13>(x, pk); break;
+                case 14: reg_um<14>(x, pk); break;
+                case 15: reg_um<15>(x, pk); break;
+                default: break;
+                }
+                continue;
+            }
             const bool tc = (tid & op.tidmask) == op.tidval;
             if (op.kind == T_PROJ) {
                 const bool zg = (base & op.gmask) == op.gval;
