@@ -232,8 +232,8 @@ __device__ __forceinline__ void reg_um(C (&x)[NR], const R *__restrict__ pk)
 }
 
 
-// Fixed homes for the amplitudes of the complex64, 16-slot tile at the head of
-// the op loop.  Each op case leaves its results wherever the register
+// Fixed homes for the amplitudes of a 16-slot tile (complex64 and complex128)
+// at the head of the op loop.  Each op case leaves its results wherever the register
 // allocator put them, and every merge of the cases back into the loop then
 // copies all 32 values between register sets (and holds both sets, which cost
 // a wave of occupancy).  Naming the registers at the loop head makes every
@@ -250,6 +250,19 @@ __device__ __forceinline__ void fix_regs(C (&x)[NR])
                           "+{v84}"(x[10].x), "+{v85}"(x[10].y), "+{v86}"(x[11].x), "+{v87}"(x[11].y),
                           "+{v88}"(x[12].x), "+{v89}"(x[12].y), "+{v90}"(x[13].x), "+{v91}"(x[13].y),
                           "+{v92}"(x[14].x), "+{v93}"(x[14].y), "+{v94}"(x[15].x), "+{v95}"(x[15].y));
+    } else if constexpr (NR == 16 && sizeof(x[0].x) == 8) {
+        asm volatile("" : "+{v[64:65]}"(x[0].x), "+{v[66:67]}"(x[0].y), "+{v[68:69]}"(x[1].x),
+                          "+{v[70:71]}"(x[1].y), "+{v[72:73]}"(x[2].x), "+{v[74:75]}"(x[2].y),
+                          "+{v[76:77]}"(x[3].x), "+{v[78:79]}"(x[3].y), "+{v[80:81]}"(x[4].x),
+                          "+{v[82:83]}"(x[4].y), "+{v[84:85]}"(x[5].x), "+{v[86:87]}"(x[5].y),
+                          "+{v[88:89]}"(x[6].x), "+{v[90:91]}"(x[6].y), "+{v[92:93]}"(x[7].x),
+                          "+{v[94:95]}"(x[7].y));
+        asm volatile("" : "+{v[96:97]}"(x[8].x), "+{v[98:99]}"(x[8].y), "+{v[100:101]}"(x[9].x),
+                          "+{v[102:103]}"(x[9].y), "+{v[104:105]}"(x[10].x), "+{v[106:107]}"(x[10].y),
+                          "+{v[108:109]}"(x[11].x), "+{v[110:111]}"(x[11].y), "+{v[112:113]}"(x[12].x),
+                          "+{v[114:115]}"(x[12].y), "+{v[116:117]}"(x[13].x), "+{v[118:119]}"(x[13].y),
+                          "+{v[120:121]}"(x[14].x), "+{v[122:123]}"(x[14].y), "+{v[124:125]}"(x[15].x),
+                          "+{v[126:127]}"(x[15].y));
     }
 }
 
