@@ -208,30 +208,6 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
     }
 }
 
-// Uncontrolled complex 2x2 gates on every register bit in MASK (bits 0..3),
-// matrices in consecutive parameter blocks in increasing bit order.
-template <int K, int NR, typename C, typename R>
-__device__ __forceinline__ void reg_u_block(C (&x)[NR], const R *__restrict__ pk)
-{
-    R m[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) m[e] = pk[e];
-    reg_u<K, NR, true>(x, m, 0u);
-}
-
-template <int MASK, int NR, typename C, typename R>
-__device__ __forceinline__ void reg_um(C (&x)[NR], const R *__restrict__ pk)
-{
-    constexpr int n0 = (MASK & 1) ? 1 : 0;
-    constexpr int n1 = n0 + ((MASK & 2) ? 1 : 0);
-    constexpr int n2 = n1 + ((MASK & 4) ? 1 : 0);
-    if constexpr ((MASK & 1) != 0) reg_u_block<0>(x, pk);
-    if constexpr ((MASK & 2) != 0) reg_u_block<1>(x, pk + 8 * n0);
-    if constexpr ((MASK & 4) != 0) reg_u_block<2>(x, pk + 8 * n1);
-    if constexpr ((MASK & 8) != 0) reg_u_block<3>(x, pk + 8 * n2);
-}
-
-
 // Fixed homes for the amplitudes of a 16-slot tile (complex64 and complex128)
 // at the head of the op loop.  Each op case leaves its results wherever the register
 // allocator put them, and every merge of the cases back into the loop then
@@ -372,24 +348,6 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
             const TileOp op = nxt;
             if (k + 1 < S.op_end) nxt = ops[k + 1];
             const R *__restrict__ pk = prm + (size_t)k * kParamStride;
-            if (op.kind == T_NOP) continue;
-            if (op.kind == T_UM) {
-                switch (op.slot) {
-                case 3: reg_um<3>(x, pk); break;
-                case 5: reg_um<5>(x, pk); break;
-                case 6: reg_um<6>(x, pk); break;
-                case 7: reg_um<7>(x, pk); break;
-                case 9: reg_um<9>(x, pk); break;
-                case 10: reg_um<10>(x, pk); break;
-                case 11: reg_um<11>(x, pk); break;
-                case 12: reg_um<12>(x, pk); break;
-                case 13: reg_um<13>(x, pk); break;
-                case 14: reg_um<14>(x, pk); break;
-                case 15: reg_um<15>(x, pk); break;
-                default: break;
-                }
-                continue;
-            }
             const bool tc = (tid & op.tidmask) == op.tidval;
             if (op.kind == T_PROJ) {
                 const bool zg = (base & op.gmask) == op.gval;

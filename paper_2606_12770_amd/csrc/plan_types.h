@@ -39,11 +39,6 @@ enum : uint8_t {
     T_SWAP = 6,   // permutation: exchange local bits a and b
     T_XFLIP = 7,  // permutation: flip local bit a
     T_UR = 8,     // real 2x2 matrix on register slot bit `slot` (4 reals)
-    T_UM = 9,     // uncontrolled complex 2x2 matrices on several register slot bits:
-                  // `slot` is the bit mask (bits 0..3, at least two set); the
-                  // matrices sit in the parameter blocks of this record and of
-                  // the T_NOP records after it, in increasing bit order
-    T_NOP = 10,   // parameter carrier of a T_UM; no effect
 };
 
 // Conditions of register-level ops are pre-split for the stage they run in:

@@ -10,8 +10,6 @@
 // when every qubit they share is diagonal-type (control or phase) in both, or
 // the target of an X in both.
 #include <algorithm>
-#include <array>
-#include <cstdint>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -637,16 +635,6 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 }
             }
         };
-        // Uncontrolled complex 2x2 gates on distinct register bits of one stage
-        // commute, so consecutive ones become one T_UM record (one dispatch in
-        // the kernel instead of one per gate) followed by T_NOP records that
-        // carry the extra matrices.  um_at: tops index of the open T_UM (or of
-        // a T_U that can grow into one), um_n: records it spans.
-        const uint32_t full_slots = (1 << rb) >= 32 ? 0xffffffffu : ((1u << (1 << rb)) - 1u);
-        size_t um_at = SIZE_MAX, um_n = 0;
-        auto um_gates = [&](const TileOp &h) {
-            return h.kind == T_U ? (1u << h.slot) : (uint32_t)h.slot;
-        };
         for (size_t i = 0; i < pb.ops.size(); ++i) {
             const OpInfo &o = info[pb.ops[i]];
             TileOp t{};
@@ -676,44 +664,6 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 t.slot = (uint8_t)(it - cur_rs.begin());
                 if (o.kind == SV_OP_U) {
                     const bool real = o.m[1] == 0.0 && o.m[3] == 0.0 && o.m[5] == 0.0 && o.m[7] == 0.0;
-                    const bool free1q = !real && o.mask == 0 && t.slot < 4 && t.slotmask == full_slots &&
-                                        t.tidmask == 0;
-                    // extend the open T_UM / T_U at the end of this stage's op list
-                    if (free1q && um_at != SIZE_MAX && um_at + um_n == p->tops.size() &&
-                        um_at >= p->stages.back().op_begin && !((um_gates(p->tops[um_at]) >> t.slot) & 1u)) {
-                        const uint32_t mask = um_gates(p->tops[um_at]) | (1u << t.slot);
-                        // matrices of the group in increasing bit order, the new one included
-                        std::vector<std::array<double, 8>> blocks;
-                        int j = 0;
-                        for (int k = 0; k < 4; ++k) {
-                            if (!((mask >> k) & 1u)) continue;
-                            std::array<double, 8> m{};
-                            if (k == (int)t.slot) {
-                                for (int e = 0; e < 8; ++e) m[e] = o.m[e];
-                            } else {
-                                for (int e = 0; e < 8; ++e) m[e] = p->tparams[(um_at + j) * kParamStride + e];
-                                ++j;
-                            }
-                            blocks.push_back(m);
-                        }
-                        TileOp nop{};
-                        nop.kind = T_NOP;
-                        nop.param = put_params(nullptr, 0);
-                        p->tops.push_back(nop);
-                        ++um_n;
-                        for (size_t q = 0; q < blocks.size(); ++q)
-                            for (int e = 0; e < 8; ++e) p->tparams[(um_at + q) * kParamStride + e] = blocks[q][e];
-                        TileOp &h = p->tops[um_at];  // after the push: the vector may have moved
-                        h.kind = T_UM;
-                        h.slot = (uint8_t)mask;
-                        continue;
-                    }
-                    if (free1q) {
-                        um_at = p->tops.size();
-                        um_n = 1;
-                    } else {
-                        um_at = SIZE_MAX;
-                    }
                     t.kind = real ? T_UR : T_U;
                     double v[8];
                     if (real) {

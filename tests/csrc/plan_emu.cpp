@@ -223,7 +223,6 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
             for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
                 const TileOp &op = p.tops[k];
                 const double *prm = p.tparams.data() + op.param;
-                if (op.kind == T_NOP) continue;
                 // the slot/thread split of the condition must agree with the local condition
                 for (int t = 0; t < T; ++t)
                     for (int s = 0; s < NR; ++s) {
@@ -244,26 +243,6 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
                             else return 11;
                             x[(size_t)t * NR + s] *= cd(prm[0], (sb ^ z) ? -prm[1] : prm[1]);
                         }
-                    }
-                    continue;
-                }
-                if (op.kind == T_UM) {
-                    // uncontrolled: every slot and thread, matrices in increasing bit order
-                    if (op.gmask || op.tidmask || op.lmask) return 12;
-                    if (op.slot >= 16 || __builtin_popcount(op.slot) < 2 || (op.slot >> rb)) return 13;
-                    int j = 0;
-                    for (int K = 0; K < 4; ++K) {
-                        if (!((op.slot >> K) & 1u)) continue;
-                        const double *m = prm + 8 * j++;
-                        for (int t = 0; t < T; ++t)
-                            for (int s = 0; s < NR; ++s) {
-                                if (s & (1 << K)) continue;
-                                cd &a = x[(size_t)t * NR + s];
-                                cd &bb = x[(size_t)t * NR + (s | (1 << K))];
-                                const cd a0 = a, b0 = bb;
-                                a = cd(m[0], m[1]) * a0 + cd(m[2], m[3]) * b0;
-                                bb = cd(m[4], m[5]) * a0 + cd(m[6], m[7]) * b0;
-                            }
                     }
                     continue;
                 }
