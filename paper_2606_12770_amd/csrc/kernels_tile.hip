@@ -25,52 +25,8 @@
 namespace svi {
 
 template <typename R> struct CTT;
-template <> struct CTT<float> {
-    using T = float2;
-    using V = float __attribute__((ext_vector_type(2)));  // the same bits as a native vector
-    static constexpr int LOWB = 4;
-};
-template <> struct CTT<double> {
-    using T = double2;
-    using V = double __attribute__((ext_vector_type(2)));
-    static constexpr int LOWB = 3;
-};
-
-// Amplitude traffic hints (bit 0: loads, bit 1: stores marked non-temporal).
-// A pass over a state far larger than the last-level cache streams every
-// amplitude once; non-temporal accesses keep it from displacing lines and,
-// for stores, avoid write-allocate traffic.  States that fit the cache keep
-// ordinary accesses so that consecutive passes hit it.
-constexpr uint32_t kNtLoad = 1u, kNtStore = 2u;
-
-template <typename R>
-__device__ __forceinline__ typename CTT<R>::T amp_load(const typename CTT<R>::T *p, uint32_t hint)
-{
-    using C = typename CTT<R>::T;
-    using V = typename CTT<R>::V;
-    if (hint & kNtLoad) {
-        const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
-        C c;
-        c.x = v.x;
-        c.y = v.y;
-        return c;
-    }
-    return *p;
-}
-
-template <typename R>
-__device__ __forceinline__ void amp_store(typename CTT<R>::T *p, typename CTT<R>::T c, uint32_t hint)
-{
-    using V = typename CTT<R>::V;
-    if (hint & kNtStore) {
-        V v;
-        v.x = c.x;
-        v.y = c.y;
-        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
-        return;
-    }
-    *p = c;
-}
+template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4; };
+template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
 
 
 // LDS element at byte offset `off` (the swizzle XOR is done on byte offsets:
@@ -208,40 +164,6 @@ __device__ __forceinline__ void reg_x(C (&x)[NR], uint32_t slotmask)
     }
 }
 
-// Fixed homes for the amplitudes of a 16-slot tile (complex64 and complex128)
-// at the head of the op loop.  Each op case leaves its results wherever the register
-// allocator put them, and every merge of the cases back into the loop then
-// copies all 32 values between register sets (and holds both sets, which cost
-// a wave of occupancy).  Naming the registers at the loop head makes every
-// case write its results there.  The asm statements contain no instructions.
-template <int NR, typename C>
-__device__ __forceinline__ void fix_regs(C (&x)[NR])
-{
-    if constexpr (NR == 16 && sizeof(x[0].x) == 4) {
-        asm volatile("" : "+{v64}"(x[0].x), "+{v65}"(x[0].y), "+{v66}"(x[1].x), "+{v67}"(x[1].y),
-                          "+{v68}"(x[2].x), "+{v69}"(x[2].y), "+{v70}"(x[3].x), "+{v71}"(x[3].y),
-                          "+{v72}"(x[4].x), "+{v73}"(x[4].y), "+{v74}"(x[5].x), "+{v75}"(x[5].y),
-                          "+{v76}"(x[6].x), "+{v77}"(x[6].y), "+{v78}"(x[7].x), "+{v79}"(x[7].y));
-        asm volatile("" : "+{v80}"(x[8].x), "+{v81}"(x[8].y), "+{v82}"(x[9].x), "+{v83}"(x[9].y),
-                          "+{v84}"(x[10].x), "+{v85}"(x[10].y), "+{v86}"(x[11].x), "+{v87}"(x[11].y),
-                          "+{v88}"(x[12].x), "+{v89}"(x[12].y), "+{v90}"(x[13].x), "+{v91}"(x[13].y),
-                          "+{v92}"(x[14].x), "+{v93}"(x[14].y), "+{v94}"(x[15].x), "+{v95}"(x[15].y));
-    } else if constexpr (NR == 16 && sizeof(x[0].x) == 8) {
-        asm volatile("" : "+{v[64:65]}"(x[0].x), "+{v[66:67]}"(x[0].y), "+{v[68:69]}"(x[1].x),
-                          "+{v[70:71]}"(x[1].y), "+{v[72:73]}"(x[2].x), "+{v[74:75]}"(x[2].y),
-                          "+{v[76:77]}"(x[3].x), "+{v[78:79]}"(x[3].y), "+{v[80:81]}"(x[4].x),
-                          "+{v[82:83]}"(x[4].y), "+{v[84:85]}"(x[5].x), "+{v[86:87]}"(x[5].y),
-                          "+{v[88:89]}"(x[6].x), "+{v[90:91]}"(x[6].y), "+{v[92:93]}"(x[7].x),
-                          "+{v[94:95]}"(x[7].y));
-        asm volatile("" : "+{v[96:97]}"(x[8].x), "+{v[98:99]}"(x[8].y), "+{v[100:101]}"(x[9].x),
-                          "+{v[102:103]}"(x[9].y), "+{v[104:105]}"(x[10].x), "+{v[106:107]}"(x[10].y),
-                          "+{v[108:109]}"(x[11].x), "+{v[110:111]}"(x[11].y), "+{v[112:113]}"(x[12].x),
-                          "+{v[114:115]}"(x[12].y), "+{v[116:117]}"(x[13].x), "+{v[118:119]}"(x[13].y),
-                          "+{v[120:121]}"(x[14].x), "+{v[122:123]}"(x[14].y), "+{v[124:125]}"(x[15].x),
-                          "+{v[126:127]}"(x[15].y));
-    }
-}
-
 #define SV_SLOT_DISPATCH1(FN, F, ...)                                   \
     switch (op.slot) {                                                  \
     case 0: FN<0, NR, F>(__VA_ARGS__); break;                           \
@@ -344,7 +266,6 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
         TileOp nxt;
         if (S.op_begin < S.op_end) nxt = ops[S.op_begin];
         for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
-            fix_regs(x);
             const TileOp op = nxt;
             if (k + 1 < S.op_end) nxt = ops[k + 1];
             const R *__restrict__ pk = prm + (size_t)k * kParamStride;
@@ -436,7 +357,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
                                                const TilePass *__restrict__ pass,
                                                const TileStage *__restrict__ stages,
                                                const TileOp *__restrict__ ops, const R *__restrict__ prm,
-                                               uint64_t tile, uint32_t hint, typename CTT<R>::T *lds)
+                                               uint64_t tile, typename CTT<R>::T *lds)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
@@ -444,10 +365,10 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     C *const pt = psi + (base | tile_thread_offset(pass, threadIdx.x));
     C x[NR];
 #pragma unroll
-    for (int s = 0; s < NR; ++s) x[s] = amp_load<R>(pt + pass->goff[s], hint);
+    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
     tile_compute<R, RB>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
 #pragma unroll
-    for (int s = 0; s < NR; ++s) amp_store<R>(pt + pass->goff[s], x[s], hint);
+    for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
 }
 
 // Persistent form: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
@@ -460,7 +381,7 @@ template <typename R, int RB>
 __global__ void __launch_bounds__(256)
 k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
                  const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
-                 uint64_t n_tiles, uint32_t hint)
+                 uint64_t n_tiles)
 {
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
@@ -476,7 +397,7 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
     {
         const C *const pn = psi + (base_next | gthr);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) xn[s] = amp_load<R>(pn + pass->goff[s], hint);
+        for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
     }
     for (;;) {
         C x[NR];
@@ -488,12 +409,12 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
             base_next = tile_base(pass, next);
             const C *const pn = psi + (base_next | gthr);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) xn[s] = amp_load<R>(pn + pass->goff[s], hint);
+            for (int s = 0; s < NR; ++s) xn[s] = pn[pass->goff[s]];
         }
         tile_compute<R, RB>(x, pass, stages, ops, prm, base, fx, lds);
         C *const pt = psi + (base | gthr);
 #pragma unroll
-        for (int s = 0; s < NR; ++s) amp_store<R>(pt + pass->goff[s], x[s], hint);
+        for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
         if (next >= n_tiles) break;
         tile = next;
     }
@@ -502,13 +423,12 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
 template <typename R, int RB>
 __global__ void __launch_bounds__(256)
 k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
-            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
-            uint32_t hint)
+            const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
 {
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
     const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, hint, reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
@@ -533,7 +453,7 @@ k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict_
         if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
     const BatchItem &B = items[lo];
-    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin, 0u,
+    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
                           reinterpret_cast<C *>(smem_raw));
 }
 
@@ -559,24 +479,19 @@ static uint64_t pipe_grid(uint32_t block, size_t lds)
     return g;
 }
 
-// States above this size stream through a pass (the last-level cache is 256 MB).
-constexpr uint64_t kStreamBytes = 512ull << 20;
-constexpr uint32_t kStreamHint = kNtLoad | kNtStore;
-
 template <typename R, int RB>
 static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const TilePass &P = p->passes[pi];
     const uint64_t tiles = 1ull << P.ntile;
-    const uint32_t hint = (sizeof(C) << p->n) > kStreamBytes ? kStreamHint : 0u;
     if (p->tile_launch == SV_TILE_LAUNCH_PERSISTENT) {
         const uint32_t block = 1u << P.nthr;
         const size_t lds = sizeof(C) << P.b;
         const uint64_t g = std::min<uint64_t>(tiles, pipe_grid<R, RB>(block, lds));
         hipLaunchKernelGGL((k_tile_pass_pipe<R, RB>), dim3((uint32_t)g), dim3(block), lds, st, (C *)psi,
                            (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                           (const TileOp *)p->d_tops, (const R *)p->d_tparams, tiles, hint);
+                           (const TileOp *)p->d_tops, (const R *)p->d_tparams, tiles);
         return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
     }
     const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
@@ -586,7 +501,7 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const size_t lds = sizeof(C) << P.b;
     hipLaunchKernelGGL((k_tile_pass<R, RB>), grid, block, lds, st, (C *)psi,
                        (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                       (const TileOp *)p->d_tops, (const R *)p->d_tparams, hint);
+                       (const TileOp *)p->d_tops, (const R *)p->d_tparams);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
