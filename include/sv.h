@@ -90,9 +90,10 @@ typedef struct {
     int mode;          /* SV_MODE_PLAIN or SV_MODE_FUSED                                  */
     int tile_qubits;   /* fused: qubits resident per tile, 0 = automatic                   */
     int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic        */
-    int dense_min_ops; /* fused, complex64: a run of at least this many consecutive ops
-                          acting inside 5 qubits (targets and controls) becomes one dense
-                          32 x 32 block applied with FP32 matrix cores; 0 = never        */
+    int dense_min_ops; /* fused: a run of at least this many consecutive ops acting
+                          inside 5 qubits (targets and controls) becomes one dense
+                          32 x 32 block applied on matrix cores (FP32 for complex64,
+                          FP64 for complex128); 0 = never                              */
     int tile_launch;   /* fused: how tile passes are launched. SV_TILE_LAUNCH_AUTO (0),
                           SV_TILE_LAUNCH_GRID (1): one workgroup per tile,
                           SV_TILE_LAUNCH_PERSISTENT (2): one resident workgroup set that

@@ -1,4 +1,5 @@
-// Dense 5-qubit block pass on FP32 matrix cores (complex64 states).
+// Dense 5-qubit block passes on matrix cores: FP32 for complex64 states,
+// FP64 for complex128 states (second kernel below).
 //
 // A workgroup stages one tile of 2^12 amplitudes in LDS (five block qubits and
 // seven others, loaded through the coalesced tile mapping).  Each of the four
@@ -103,17 +104,129 @@ k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const f
     }
 }
 
+// Complex128: the same product on FP64 matrix cores, v_mfma_f64_16x16x4f64
+// (M = 16 block rows, N = 16 groups, K = 4 block values per instruction).
+// Operand layout of that instruction (checked on the device): lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result t of lane l is
+// D[4 t + l / 16][l % 16].  A tile holds 128 groups; wave w takes groups
+// 32 w .. 32 w + 31 as two N blocks, both 16-row halves of the block matrix,
+// and keeps the A operands (G_re, G_im for 2 halves x 8 K steps) in registers.
+//   Y_re += G_re X_re + G_im (-X_im),   Y_im += G_im X_re + G_re X_im.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+k_dense_pass_f64(double2 *__restrict__ psi, const DensePass *__restrict__ dp, const double *__restrict__ mats,
+                 uint64_t n_tiles)
+{
+    extern __shared__ unsigned char smem_raw[];
+    double2 *lds = reinterpret_cast<double2 *>(smem_raw);
+    const DensePass &D = *dp;
+    const TilePass &P = D.map;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t r16 = lane & 15u, k4 = lane >> 4;
+
+    const double *G = mats + D.mat;
+    double gre[2][8], gim[2][8];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const uint32_t idx = 32u * (16u * mb + r16) + 4u * ks + k4;
+            gre[mb][ks] = G[2 * idx];
+            gim[mb][ks] = G[2 * idx + 1];
+        }
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
+    uint32_t gl[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const uint32_t g = wave * 32u + 16u * nb + r16;
+        uint32_t o = 0;
+        for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+            const uint32_t w = D.grp_run[r];
+            o |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+        }
+        gl[nb] = o;
+    }
+    const uint32_t tw = lds_swizzle(tid, 3);
+
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
+            const uint32_t sh = P.tile_shift[r];
+            base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
+        }
+        double2 *const pt = psi + (base | gthr);
+        {
+            double2 x[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+        }
+        __syncthreads();
+
+        v4d yre[2][2], yim[2][2];  // [N block][M half]
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                yre[nb][mb] = (v4d){0.0, 0.0, 0.0, 0.0};
+                yim[nb][mb] = (v4d){0.0, 0.0, 0.0, 0.0};
+            }
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const double2 xv = lds[lds_swizzle(gl[nb] | D.joff[4 * ks + k4], 3)];
+                const double xim_neg = -xv.y;
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) {
+                    yre[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(gre[mb][ks], xv.x, yre[nb][mb], 0, 0, 0);
+                    yre[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(gim[mb][ks], xim_neg, yre[nb][mb], 0, 0, 0);
+                    yim[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(gim[mb][ks], xv.x, yim[nb][mb], 0, 0, 0);
+                    yim[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(gre[mb][ks], xv.y, yim[nb][mb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // every wave has read its X before Y overwrites it
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t row = 16u * mb + 4u * t + k4;
+                    lds[lds_swizzle(gl[nb] | D.joff[row], 3)] = make_double2(yre[nb][mb][t], yim[nb][mb][t]);
+                }
+        __syncthreads();
+        {
+            double2 x[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) pt[P.goff[s]] = x[s];
+        }
+        __syncthreads();  // the next tile overwrites the LDS
+    }
+}
+
 int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
 {
-    if (p->dtype != SV_C64) return SV_EUNSUPPORTED;
     const DensePass &D = p->dense[di];
     const uint64_t tiles = 1ull << D.map.ntile;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t cap = (uint64_t)cus * 2;  // resident workgroups per CU at this kernel's register use
+    const uint64_t cap = (uint64_t)cus * 2;  // resident workgroups per CU at these kernels' register and LDS use
     const uint32_t grid = (uint32_t)(tiles < cap ? tiles : cap);
-    hipLaunchKernelGGL(k_dense_pass, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
-                       (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
+    if (p->dtype == SV_C64)
+        hipLaunchKernelGGL(k_dense_pass, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                           (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
+    else
+        hipLaunchKernelGGL(k_dense_pass_f64, dim3(grid), dim3(256), sizeof(double2) << 12, st, (double2 *)psi,
+                           (const DensePass *)p->d_dense + di, (const double *)p->d_dparams, tiles);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 

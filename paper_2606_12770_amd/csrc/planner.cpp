@@ -331,12 +331,12 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
 
-    // ---- dense 5-qubit runs (complex64): maximal runs of consecutive ops whose
-    // qubits fit in five, kept when at least dense_min_ops long ----
+    // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
+    // in five, kept when at least dense_min_ops long ----
     std::vector<int> dense_id(n_ops, -1);
     std::vector<std::pair<size_t, size_t>> runs;
     std::vector<uint64_t> run_support;
-    if (opts.dense_min_ops > 0 && p->dtype == SV_C64 && n >= 12) {
+    if (opts.dense_min_ops > 0 && n >= 12) {
         size_t ws = 0;
         uint64_t S = 0;
         auto close = [&](size_t end) {
@@ -391,7 +391,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 }
             }
         }
-        const int dl = 4;  // LDS swizzle width of complex64
+        const int dl = p->dtype == SV_C64 ? 4 : 3;  // LDS swizzle width of the amplitude size
         for (int s2 = 0; s2 < 16; ++s2) {
             uint64_t off = 0;
             for (int k = 0; k < 4; ++k)

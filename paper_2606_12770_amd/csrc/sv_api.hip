@@ -169,8 +169,12 @@ int upload_plan(sv_plan *p)
     if (rc != SV_OK) return rc;
     if (!p->dense.empty()) {
         if ((rc = up(&p->d_dense, p->dense.data(), p->dense.size() * sizeof(svi::DensePass))) != SV_OK) return rc;
-        std::vector<float> f(p->dparams.begin(), p->dparams.end());
-        rc = up(&p->d_dparams, f.data(), f.size() * sizeof(float));
+        if (p->dtype == SV_C64) {
+            std::vector<float> f(p->dparams.begin(), p->dparams.end());
+            rc = up(&p->d_dparams, f.data(), f.size() * sizeof(float));
+        } else {
+            rc = up(&p->d_dparams, p->dparams.data(), p->dparams.size() * sizeof(double));
+        }
     }
     return rc;
 }

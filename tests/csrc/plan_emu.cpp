@@ -314,6 +314,10 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
     const int n = p.n;
     const uint64_t dim = 1ull << n;
     if (P.b != 12 || P.nthr != 8 || P.rb != 4 || P.ntile != n - 12) return 30;
+    // LDS swizzle width of the amplitude size (8 B complex64, 16 B complex128)
+    const int dl = p.dtype == SV_C64 ? 4 : 3;
+    for (int s = 0; s < 16; ++s)
+        if (P.swz0[s] != lds_swizzle((uint32_t)s << 8, dl)) return 36;
     std::fill(rd.begin(), rd.end(), 0);
     std::fill(wr.begin(), wr.end(), 0);
     // group offsets from the runs, and the exact cover of the local indices

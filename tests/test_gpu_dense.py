@@ -1,7 +1,7 @@
-"""Dense 5-qubit blocks on FP32 matrix cores against the FP64 reference
-simulator: deep runs confined to five qubits become one 32 x 32 block each,
-and the result must match the gate-by-gate oracle (complex64 bar: infidelity
-<= 1e-6) and the tile path on the same circuit."""
+"""Dense 5-qubit blocks on matrix cores against the FP64 reference simulator:
+deep runs confined to five qubits become one 32 x 32 block each, applied with
+FP32 MFMA for complex64 (bar: infidelity <= 1e-6, amplitudes within 1e-5) and
+FP64 MFMA for complex128 (amplitudes within 1e-12 of the gate-by-gate oracle)."""
 import numpy as np
 import pytest
 
@@ -16,23 +16,28 @@ def infid(a, b):
     return 1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n,blocks,depth", [(12, 3, 4), (16, 6, 5), (20, 8, 6), (23, 4, 8)])
-def test_dense_blocks_match_oracle(n, blocks, depth):
+def test_dense_blocks_match_oracle(n, blocks, depth, dtype):
     sv = require_gpu()
     c = random_dense_block_circuit(n, blocks, depth, seed=n)
     psi0 = random_state(n, n + 1)
     want = osv.run(c, psi0)
     ops, params = c.arrays()
-    plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4, 16)
+    dt = sv.SV_C64 if dtype == "c64" else sv.SV_C128
+    plan = sv.sv_plan_create(n, dt, ops, params, sv.SV_MODE_FUSED, 12, 4, 16)
     info = sv.sv_plan_get_info(plan)
-    st = sv.sv_alloc(n, sv.SV_C64, psi0)
+    st = sv.sv_alloc(n, dt, psi0)
     sv.sv_plan_execute(plan, st, 1)
     got = sv.sv_amplitudes(st)
     sv.sv_free(st)
     sv.sv_plan_free(plan)
     f = infid(want, got)
-    print(f"dense n={n} blocks={blocks} depth={depth}: {info['n_dense_passes']} dense passes absorbing "
+    print(f"dense {dtype} n={n} blocks={blocks} depth={depth}: {info['n_dense_passes']} dense passes absorbing "
           f"{info['n_dense_ops']} of {len(c)} ops, infidelity {f:.2e}", flush=True)
     assert info["n_dense_passes"] == blocks
-    assert f < 1e-6
-    assert np.max(np.abs(got - want)) < 1e-5
+    if dtype == "c64":
+        assert f < 1e-6
+        assert np.max(np.abs(got - want)) < 1e-5
+    else:
+        assert np.max(np.abs(got - want)) < 1e-12

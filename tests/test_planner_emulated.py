@@ -118,15 +118,16 @@ def test_precomputed_pass_fields_at_benchmark_size(emu, dtype, b, rb):
     assert rc == 0
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("n,seed", [(12, 0), (14, 1), (16, 2)])
-def test_dense_blocks_match_oracle(emu, n, seed):
+def test_dense_blocks_match_oracle(emu, n, seed, dtype):
     from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
     c = random_dense_block_circuit(n, 4, 5, seed)
     psi0 = random_state(n, seed)
     want = osv.run(c, psi0)
-    got, stats = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=16)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4, dtype, dense_min_ops=16)
     assert np.max(np.abs(got - want)) < 1e-12
     assert stats[0] >= stats[1] + 4  # the four deep runs became dense passes
     # without dense blocks the same plan path agrees too
-    got2, _ = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=0)
+    got2, _ = run_emu(emu, c, psi0, 1, 12, 4, dtype, dense_min_ops=0)
     assert np.max(np.abs(got2 - want)) < 1e-12
