@@ -135,7 +135,8 @@ def batched_carleman(sv, count=64, d=3, reps=3):
     plans = []
     for c in circs:
         ops, params = c.arrays()
-        plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, b, rb))
+        plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, b, rb,
+                                       plain_split=sv.SV_PLAIN_SPLIT_OFF))
     for st, cfg, e in zip(states, cfgs, encs):
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
     batch = sv.sv_batch_create(states, plans, True, 0)

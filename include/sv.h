@@ -99,11 +99,19 @@ typedef struct {
                           SV_TILE_LAUNCH_PERSISTENT (2): one resident workgroup set that
                           walks the tiles, loading the next tile while computing one.
                           Results are identical; only the timing differs.            */
+    int plain_split;   /* fused: SV_PLAIN_SPLIT_AUTO (0): a group of ops whose plain
+                          launches (each sweeping only its controlled subspace) are
+                          modelled cheaper than one tile pass over the whole state runs
+                          as those launches; SV_PLAIN_SPLIT_OFF (1): tile passes only
+                          (required for plans given to sv_batch_create)              */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0
 #define SV_TILE_LAUNCH_GRID 1
 #define SV_TILE_LAUNCH_PERSISTENT 2
+
+#define SV_PLAIN_SPLIT_AUTO 0
+#define SV_PLAIN_SPLIT_OFF 1
 
 typedef struct sv_state sv_state;
 typedef struct sv_plan sv_plan;
@@ -119,6 +127,7 @@ typedef struct {
     int      reg_qubits;      /* register qubits actually used (fused)               */
     uint64_t n_dense_passes;  /* launches that apply a dense 5-qubit block           */
     uint64_t n_dense_ops;     /* IR ops absorbed into dense blocks                   */
+    uint64_t n_split_ops;     /* fused: IR ops run as plain launches by the cost model */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

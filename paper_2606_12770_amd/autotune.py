@@ -64,7 +64,7 @@ def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_gra
     for b, rb in candidates:
         if not _valid(nmin, b, rb):
             continue
-        plans = [sv.sv_plan_create(c.n, dtype, o, p, sv.SV_MODE_FUSED, b, rb)
+        plans = [sv.sv_plan_create(c.n, dtype, o, p, sv.SV_MODE_FUSED, b, rb, plain_split=sv.SV_PLAIN_SPLIT_OFF)
                  for c, (o, p) in zip(circuits, arrays)]
         batch = None
         try:

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sv_internal.h"
 
 namespace svi {
@@ -18,18 +20,25 @@ template <typename R> struct CT;
 template <> struct CT<float> { using T = float2; };
 template <> struct CT<double> { using T = double2; };
 
+// The spread as bit runs: each maximal stretch of consecutive free qubits takes
+// a stretch of counter bits, so a register or a block of adjacent controls
+// costs one run, not one step per fixed bit.  Run r moves counter bits
+// [src, src + width) to index bits [dst, dst + width); packed src | dst << 8 |
+// width << 16.
 struct Deposit {
     uint32_t n;
-    uint8_t pos[64];  // ascending
+    uint32_t run[20];
 };
 
 __device__ __forceinline__ uint64_t deposit_zeros(uint64_t x, const Deposit &d)
 {
+    uint64_t out = 0;
     for (uint32_t k = 0; k < d.n; ++k) {
-        const uint32_t p = d.pos[k];
-        x = ((x >> p) << (p + 1)) | (x & ((1ull << p) - 1ull));
+        const uint32_t r = d.run[k];
+        const uint32_t src = r & 0xffu, dst = (r >> 8) & 0xffu, w = r >> 16;
+        out |= ((x >> src) & ((1ull << w) - 1ull)) << dst;
     }
-    return x;
+    return out;
 }
 
 template <typename R> struct Mat2 { R v[8]; };
@@ -145,6 +154,49 @@ __global__ void __launch_bounds__(256) k_gate_shift(typename CT<R>::T *__restric
     }
 }
 
+// The same shift for registers of at most 8 qubits, with every amplitude of an
+// orbit read before any is written: a workgroup owns P whole orbits (P
+// consecutive free-bit counters, P * 2^width <= 4096 amplitudes), loads them
+// into registers, waits at a barrier and stores them shifted, so no thread
+// walks an orbit serially.  Consecutive items step through whichever index sits
+// on the lower qubits, so that the accesses are coalesced: the register value
+// when the register lies below every free qubit (v_fast), else the orbit
+// counter (P consecutive counters are consecutive free indices).
+template <typename R>
+__global__ void __launch_bounds__(256) k_gate_shift_blk(typename CT<R>::T *__restrict__ psi, uint64_t nblk,
+                                                        Deposit d, uint64_t cval, int base, int width, int up,
+                                                        int lg_p, int v_fast)
+{
+    using C = typename CT<R>::T;
+    constexpr int kMaxItems = 16;
+    const uint32_t len_mask = (1u << width) - 1u;
+    const uint32_t p_mask = (1u << lg_p) - 1u;
+    const uint32_t items = 1u << (lg_p + width);
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {  // uniform per workgroup
+        const uint64_t orb0 = blk << lg_p;
+        C x[kMaxItems];
+        uint64_t dst[kMaxItems];
+#pragma unroll
+        for (int k = 0; k < kMaxItems; ++k) {
+            const uint32_t i = tid + 256u * k;
+            if (i < items) {
+                const uint32_t o = v_fast ? i >> width : i & p_mask;
+                const uint32_t v = v_fast ? i & len_mask : i >> lg_p;
+                const uint64_t r = deposit_zeros(orb0 + o, d) | cval;
+                const uint32_t src = (up ? v - 1u : v + 1u) & len_mask;  // new[v] = old[v -+ 1]
+                x[k] = psi[r | ((uint64_t)src << base)];
+                dst[k] = r | ((uint64_t)v << base);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxItems; ++k)
+            if (tid + 256u * k < items) psi[dst[k]] = x[k];
+        __syncthreads();
+    }
+}
+
 // exp(i theta (1 - 2 (s xor z))), z = [(i & mask) == val], s = bit `sig`
 template <typename R>
 __global__ void __launch_bounds__(256) k_projphase(typename CT<R>::T *__restrict__ psi, uint64_t dim,
@@ -164,12 +216,26 @@ __global__ void __launch_bounds__(256) k_projphase(typename CT<R>::T *__restrict
     }
 }
 
-static Deposit make_deposit(uint64_t fixed_bits)
+static Deposit make_deposit(uint64_t fixed_bits, int n)
 {
+    // free qubits of an n-qubit index, ascending, grouped into runs (at most
+    // n / 2 + 1 <= 19 of them); callers enumerate counters below 2^(free qubits)
     Deposit d{};
     d.n = 0;
-    for (int q = 0; q < 64; ++q)
-        if ((fixed_bits >> q) & 1ull) d.pos[d.n++] = (uint8_t)q;
+    uint32_t src = 0;
+    int q = 0;
+    while (q < n) {
+        if ((fixed_bits >> q) & 1ull) {
+            ++q;
+            continue;
+        }
+        int e = q;
+        while (e < n && !((fixed_bits >> e) & 1ull)) ++e;
+        const uint32_t w = (uint32_t)(e - q);
+        d.run[d.n++] = src | ((uint32_t)q << 8) | (w << 16);
+        src += w;
+        q = e;
+    }
     return d;
 }
 
@@ -186,19 +252,19 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
         Mat2<R> m;
         for (int k = 0; k < 8; ++k) m.v[k] = (R)op.m[k];
         hipLaunchKernelGGL(k_gate_u<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | (1ull << op.target)), op.val, 1ull << op.target, m);
+                           make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target, m);
         break;
     }
     case SV_OP_X: {
         const uint64_t nwork = 1ull << (n - 1 - c);
         hipLaunchKernelGGL(k_gate_x<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | (1ull << op.target)), op.val, 1ull << op.target);
+                           make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target);
         break;
     }
     case SV_OP_PHASE: {
         const uint64_t nwork = 1ull << (n - 1 - c);
         hipLaunchKernelGGL(k_gate_phase<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | (1ull << op.target)), op.val | (1ull << op.target),
+                           make_deposit(op.mask | (1ull << op.target), n), op.val | (1ull << op.target),
                            (R)cos(op.m[0]), (R)sin(op.m[0]));
         break;
     }
@@ -206,16 +272,30 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
         const uint64_t ab = 1ull << op.target, bb = 1ull << op.width;
         const uint64_t nwork = 1ull << (n - 2 - c);
         hipLaunchKernelGGL(k_gate_swap<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | ab | bb), op.val, ab, bb);
+                           make_deposit(op.mask | ab | bb, n), op.val, ab, bb);
         break;
     }
     case SV_OP_INC:
     case SV_OP_DEC: {
         const uint64_t reg = ((1ull << op.width) - 1ull) << op.target;
-        const uint64_t nwork = 1ull << (n - (int)op.width - c);
-        hipLaunchKernelGGL(k_gate_shift<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | reg), op.val, (int)op.target, (int)op.width,
-                           op.kind == SV_OP_INC ? 1 : 0);
+        const int lg_orb = n - (int)op.width - c;  // log2 of the number of orbits
+        const uint64_t nwork = 1ull << lg_orb;
+        if (op.width <= 8) {
+            // P orbits per workgroup with P * 2^width <= 4096 (16 amplitudes per thread)
+            const int lg_p = std::min(lg_orb, 12 - (int)op.width);
+            const uint64_t nblk = 1ull << (lg_orb - lg_p);
+            const int grid = (int)std::min<uint64_t>(nblk, 4096);
+            const uint64_t fixed = op.mask | reg;
+            const uint64_t free_bits = ~fixed & ((n >= 64) ? ~0ull : ((1ull << n) - 1ull));
+            const int low_free = free_bits ? __builtin_ctzll(free_bits) : 64;
+            hipLaunchKernelGGL(k_gate_shift_blk<R>, dim3(grid), dim3(B), 0, st, psi, nblk, make_deposit(fixed, n),
+                               op.val, (int)op.target, (int)op.width, op.kind == SV_OP_INC ? 1 : 0, lg_p,
+                               (int)op.target < low_free ? 1 : 0);
+        } else {
+            hipLaunchKernelGGL(k_gate_shift<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                               make_deposit(op.mask | reg, n), op.val, (int)op.target, (int)op.width,
+                               op.kind == SV_OP_INC ? 1 : 0);
+        }
         break;
     }
     case SV_OP_PROJPHASE: {
@@ -419,7 +499,7 @@ int launch_prob(const void *psi, int n, int dtype, uint64_t mask, uint64_t val, 
     const uint64_t nwork = 1ull << (n - c);
     uint64_t g = (nwork + 255) / 256;
     if (g > (uint64_t)max_blocks) g = max_blocks;
-    const Deposit d = make_deposit(mask);
+    const Deposit d = make_deposit(mask, n);
     if (dtype == SV_C64)
         hipLaunchKernelGGL(k_prob<float>, dim3(g), dim3(256), 0, st, (const float2 *)psi, nwork, d, val, d_partial);
     else

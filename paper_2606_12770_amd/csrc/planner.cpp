@@ -121,6 +121,43 @@ uint64_t plain_bytes(const OpInfo &o, int n, int s)
     }
 }
 
+// Bytes a plain launch of the op moves at cache-line granularity (128 B): a
+// control (or a phase/swap condition) on one of the qubits inside a line
+// does not reduce the lines touched.
+uint64_t touched_bytes(const OpInfo &o, int n, int s)
+{
+    const int line_bits = s == 8 ? 4 : 3;
+    const uint64_t in_line = (1ull << line_bits) - 1ull;
+    const int c = __builtin_popcountll(o.mask & ~in_line);
+    const uint64_t all = 2ull * (1ull << n) * s;
+    switch (o.kind) {
+    case SV_OP_U:
+    case SV_OP_X:
+    case SV_OP_INC:
+    case SV_OP_DEC:
+        return all >> c;
+    case SV_OP_PHASE:
+        return all >> (c + (o.target >= (uint32_t)line_bits ? 1 : 0));
+    case SV_OP_SWAP:
+        return all >> (c + (o.target >= (uint32_t)line_bits && o.width >= (uint32_t)line_bits ? 1 : 0));
+    default:
+        return all;
+    }
+}
+
+// Modelled device time (microseconds) of a tile pass and of one plain launch:
+// a fixed cost per launch (launch, fill and drain of a small grid) plus bytes
+// at the sustained rate of each kernel family.  A plain register shift wider
+// than 8 qubits walks its orbit serially, one dependent access per value.
+constexpr double kTileFixedUs = 8.0, kTileBytesPerUs = 3.8e6;
+constexpr double kPlainFixedUs = 4.0, kPlainBytesPerUs = 4.0e6;
+double plain_us(const OpInfo &o, int n, int s)
+{
+    double t = kPlainFixedUs + (double)touched_bytes(o, n, s) / kPlainBytesPerUs;
+    if ((o.kind == SV_OP_INC || o.kind == SV_OP_DEC) && o.width > 8) t += 0.3 * (double)(1ull << o.width);
+    return t;
+}
+
 // j commutes with every op whose roles are accumulated in (Z, X, G)
 inline bool commutes_with_all(const OpInfo &o, uint64_t Z, uint64_t X, uint64_t G)
 {
@@ -330,6 +367,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const int lowb = p->dtype == SV_C64 ? 4 : 3;  // LDS swizzle width (16 B banks groups)
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
+    const bool plain_split = opts.plain_split != SV_PLAIN_SPLIT_OFF;
 
     // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
     // in five, kept when at least dense_min_ops long ----
@@ -492,6 +530,18 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             }
             if (cand < 0) break;
             pb.S |= info[cand].req;
+        }
+        // a pass whose ops are cheaper as plain launches (each touches only its
+        // controlled subspace) is emitted as those launches, in pass order
+        if (plain_split) {
+            const double tile_us = kTileFixedUs + (double)(2ull * (1ull << n) * esize) / kTileBytesPerUs;
+            double t = 0.0;
+            for (uint32_t j : pb.ops) t += plain_us(info[j], n, esize);
+            if (t < tile_us) {
+                for (uint32_t j : pb.ops) add_plain(info[j]);
+                p->info.n_split_ops += pb.ops.size();
+                continue;
+            }
         }
         // fill the resident set up to b qubits with the lowest unused ones
         for (int q = 0; q < n && __builtin_popcountll(pb.S) < b; ++q) pb.S |= 1ull << q;

@@ -405,6 +405,7 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
         stats[1] = p.info.n_tile_passes;
         stats[2] = p.info.n_stages;
         stats[3] = p.info.bytes_moved;
+        stats[4] = p.info.n_split_ops;
     }
     return 0;
 }

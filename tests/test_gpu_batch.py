@@ -24,7 +24,8 @@ def _plans(sv, circs, dtype, b=12, rb=4):
     out = []
     for c in circs:
         ops, params = c.arrays()
-        out.append(sv.sv_plan_create(c.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb))
+        out.append(sv.sv_plan_create(c.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb,
+                                      plain_split=sv.SV_PLAIN_SPLIT_OFF))
     return out
 
 
@@ -143,8 +144,8 @@ def test_invalid_batches_are_refused():
     c2 = random_mixed_circuit(15, 50, seed=2)
     o1, p1 = c1.arrays()
     o2, p2 = c2.arrays()
-    pa = sv.sv_plan_create(14, 0, o1, p1, sv.SV_MODE_FUSED, 12, 4)
-    pb = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 11, 4)   # other geometry
+    pa = sv.sv_plan_create(14, 0, o1, p1, sv.SV_MODE_FUSED, 12, 4, plain_split=sv.SV_PLAIN_SPLIT_OFF)
+    pb = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 11, 4, plain_split=sv.SV_PLAIN_SPLIT_OFF)  # other geometry
     pc = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_PLAIN)           # per-gate steps
     st = sv.sv_alloc_batch([14, 15], 0)
     for plans, code in (([pa, pb], sv.SV_EINVAL), ([pa, pc], sv.SV_EINVAL)):
@@ -157,7 +158,7 @@ def test_invalid_batches_are_refused():
     # states outside an arena, or from two arenas, are refused
     lone = sv.sv_alloc(15, 0)
     other = sv.sv_alloc_batch([15], 0)
-    pd = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 12, 4)
+    pd = sv.sv_plan_create(15, 0, o2, p2, sv.SV_MODE_FUSED, 12, 4, plain_split=sv.SV_PLAIN_SPLIT_OFF)
     for pair in ([st[0], lone], [st[0], other[0]]):
         with pytest.raises(sv.SVError) as e:
             sv.sv_batch_create(pair, [pa, pd], False)

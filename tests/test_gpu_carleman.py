@@ -13,6 +13,10 @@
   the ancillas projected out must equal L b / lambda_L on every system
   amplitude (the block-encoding property, exact at any size), with the
   classical L b from matrix-free products.
+* The 31-qubit workload (N_x = 64, N_K = 4, N_t = 8) through the whole ladder
+  at d = 3 and d = 13: every system amplitude against the classical
+  singular-value transform of the same phases, from sparse products with the
+  oracle's L (complex64 and complex128).
 """
 import numpy as np
 import pytest
@@ -193,6 +197,50 @@ def test_ul_block_encoding_full_size(name):
     assert abs(norm2 - 1.0) < 1e-4
     assert err < 1e-5
     assert leak < 1e-5 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("d", [3, 13])
+def test_c3_ladder_full_size(d, dtype):
+    sv = require_gpu()
+    cfg = cc.CarlemanConfig(**C3)
+    enc = cc.build_ul(cfg)
+    L = enc.layout
+    phases = qsp.inversion_phases(1.2, d)[0]
+    circ = cc.build_qsvt(enc, phases)
+    print(f"C3 ladder d={d}: {len(circ)} ops on {L.n} qubits, dtype={dtype}", flush=True)
+    st = sv.State(L.n, dtype)
+    sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
+    plan = sv.Plan(L.n, dtype, circ)
+    plan.execute(st)
+    norm2 = st.prob()
+    sys_amp = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)
+    st.close()
+    plan.close()
+
+    A = oc.carleman_matrix(cfg.nx, cfg.tau, 2, cfg.boundary)
+    Lm = oc.l_matrix(A, cfg.dt, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    y0 = oc.carleman_vector(oc.initial_f1(cfg.nx, cfg.amp, cfg.u0))
+    b = oc.l_rhs(y0, cfg.nt, cfg.nk, L.n_m, L.n_k)
+    b /= np.linalg.norm(b)
+    M = (Lm.T / enc.lam).tocsr()
+    MT = M.T.tocsr()
+    want = (-1j) ** d * oq.odd_sv_apply(lambda v: M @ v, lambda v: MT @ v, oq.odd_chebyshev_of_qsp(phases), b)
+    idx = system_to_reg(cfg, L)
+    got = sys_amp[idx]
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    f_tr = infid(want, got)
+    rest = np.ones(1 << L.n_sys, bool)
+    rest[idx] = False
+    leak = np.max(np.abs(sys_amp[rest]))
+    print(f"  norm drift {abs(norm2 - 1):.2e}  rel max err {err:.2e}  infidelity {f_tr:.2e}  "
+          f"unphysical {leak:.2e}", flush=True)
+    eps = 2.0 ** -52 if dtype == 1 else 2.0 ** -23
+    assert abs(norm2 - 1.0) < len(circ) * eps
+    if dtype == 1:
+        assert f_tr < 1e-12 and err < 1e-9 and leak < 1e-12
+    else:
+        assert f_tr < 1e-6 and err < 1e-4 and leak < 1e-5 * np.max(np.abs(want))
 
 
 @pytest.mark.parametrize("dtype", [1, 0])

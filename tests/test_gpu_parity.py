@@ -94,7 +94,7 @@ def test_permutations_bit_exact(dtype, mode):
         elif k == 1:
             c.swap(qs[0], qs[1], ctrl)
         else:
-            w = int(rng.integers(1, 7))
+            w = int(rng.integers(1, 11))  # widths up to 8 shift in one workgroup, wider ones serially
             base = int(rng.integers(0, n - w + 1))
             ctrl = {q: v for q, v in ctrl.items() if not base <= q < base + w}
             (c.inc if k == 2 else c.dec)(base, w, ctrl)
@@ -104,6 +104,45 @@ def test_permutations_bit_exact(dtype, mode):
     want = osv.run(c, psi0)
     got = run_gpu(sv, c, psi0, dtype, mode)
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_plain_split_matches_oracle(dtype):
+    """Fused plans in which the cost model sends some op groups to plain launches
+    (controlled increments of two 7-qubit registers that do not commute, each of
+    which would fill a tile pass of its own) against the reference simulator,
+    and against the same plan with tile passes only."""
+    sv = require_gpu()
+    n = 20
+    rng = np.random.default_rng(3)
+    c = Circuit(n)
+    for layer in range(3):
+        for q in range(n):
+            c.ry(q, rng.uniform(-np.pi, np.pi))
+        for _ in range(4):
+            c.inc(13, 7, {int(q): int(rng.integers(2)) for q in (6, 8, 10, 12)})
+            c.dec(6, 7, {int(q): int(rng.integers(2)) for q in (13, 15, 17, 19)})
+        qs = rng.permutation(n)
+        c.x(int(qs[0]), {int(q): int(rng.integers(2)) for q in qs[1:9]})
+    psi0 = random_state(n, 4)
+    want = osv.run(c, psi0)
+    ops, params = c.arrays()
+    outs = {}
+    for split in (sv.SV_PLAIN_SPLIT_AUTO, sv.SV_PLAIN_SPLIT_OFF):
+        plan = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, 12, 4, plain_split=split)
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(n, dtype, psi0)
+        sv.sv_plan_execute(plan, st, 1)
+        outs[split] = sv.sv_amplitudes(st)
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+        print(f"split={split} dtype={dtype}: {info['n_tile_passes']} tile passes, {info['n_split_ops']} ops as plain "
+              f"launches, infidelity {infid(want, outs[split]):.2e}", flush=True)
+        assert (info["n_split_ops"] > 0) == (split == sv.SV_PLAIN_SPLIT_AUTO)
+        if dtype == 1:
+            assert np.max(np.abs(outs[split] - want)) < 1e-12
+        else:
+            assert infid(want, outs[split]) < 1e-6
 
 
 def test_reductions_postselect_inner():

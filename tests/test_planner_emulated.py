@@ -39,7 +39,7 @@ def emu():
 def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0, dense_min_ops=0):
     ops, params = circ.arrays()
     psi = np.array(psi0, dtype=np.complex128, copy=True)
-    stats = (ctypes.c_uint64 * 4)()
+    stats = (ctypes.c_uint64 * 5)()
     dp = ctypes.POINTER(ctypes.c_double)
     rc = L.emu_run(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(dp), mode, b, rb,
                    psi.ctypes.data_as(dp), stats, dense_min_ops)
@@ -102,6 +102,32 @@ def test_fused_plan_carleman_ladder(emu, b, rb, elementary):
     got, stats = run_emu(emu, circ, psi0, 1, b, rb)
     assert np.max(np.abs(got - want)) < 1e-12
     assert stats[0] * 3 < len(circ)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plain_split_matches_oracle(emu, seed):
+    """A group of ops that is cheaper as plain launches (each sweeping only its
+    controlled subspace) than as one tile pass goes to plain launches: here
+    controlled increments of two 7-qubit registers that do not commute, so each
+    would fill a pass of its own.  Uncontrolled layers stay in tile passes.
+    The mixed plan must equal the reference simulator."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    n = 20
+    rng = np.random.default_rng(seed)
+    c = Circuit(n)
+    for layer in range(3):
+        for q in range(n):
+            c.ry(q, rng.uniform(-np.pi, np.pi))
+        for _ in range(4):
+            c.inc(13, 7, {int(q): int(rng.integers(2)) for q in (6, 8, 10, 12)})
+            c.dec(6, 7, {int(q): int(rng.integers(2)) for q in (13, 15, 17, 19)})
+        qs = rng.permutation(n)
+        c.x(int(qs[0]), {int(q): int(rng.integers(2)) for q in qs[1:9]})
+    psi0 = random_state(n, seed)
+    want = osv.run(c, psi0)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[4] > 0 and stats[1] > 0  # some ops went to plain launches, some stayed in tile passes
 
 
 @pytest.mark.parametrize("dtype,b,rb", [(0, 12, 4), (0, 12, 5), (0, 13, 5), (1, 12, 4), (1, 11, 5)])
