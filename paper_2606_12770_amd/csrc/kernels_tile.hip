@@ -269,9 +269,11 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
             const TileOp op = nxt;
             if (k + 1 < S.op_end) nxt = ops[k + 1];
             const R *__restrict__ pk = prm + (size_t)k * kParamStride;
+            // tile condition first: a uniform branch taken before any per-lane work
+            const bool zg = (base & op.gmask) == op.gval;
+            if (!zg && op.kind != T_PROJ) continue;
             const bool tc = (tid & op.tidmask) == op.tidval;
             if (op.kind == T_PROJ) {
-                const bool zg = (base & op.gmask) == op.gval;
                 const R c = pk[0], sn = pk[1];
                 const uint32_t sig_thread = op.a == 2 ? ((tid >> op.b) & 1u) : 0u;
                 const uint32_t sig_tile = op.a == 0 ? (uint32_t)((base >> op.b) & 1ull) : 0u;
@@ -288,7 +290,6 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
                 }
                 continue;
             }
-            if ((base & op.gmask) != op.gval) continue;
             if (!tc) continue;
             if (op.kind == T_U) {
                 R m[8];

@@ -151,6 +151,11 @@ uint64_t touched_bytes(const OpInfo &o, int n, int s)
 // than 8 qubits walks its orbit serially, one dependent access per value.
 constexpr double kTileFixedUs = 8.0, kTileBytesPerUs = 3.8e6;
 constexpr double kPlainFixedUs = 4.0, kPlainBytesPerUs = 4.0e6;
+// Cost of one op inside a tile pass: every tile reads its record and checks its
+// tile condition (register moves and scalar work per wave, measured about
+// 0.3 ns per tile and op), and the amplitudes it applies to cost about 0.32 ps
+// each (the VALU work of a complex 2 x 2 gate in the fused kernel).
+constexpr double kOpPerTileUs = 0.31e-3, kOpPerAmpUs = 0.32e-6;
 double plain_us(const OpInfo &o, int n, int s)
 {
     double t = kPlainFixedUs + (double)touched_bytes(o, n, s) / kPlainBytesPerUs;
@@ -531,17 +536,61 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             if (cand < 0) break;
             pb.S |= info[cand].req;
         }
-        // a pass whose ops are cheaper as plain launches (each touches only its
-        // controlled subspace) is emitted as those launches, in pass order
+        // Ops cheaper as plain launches (each sweeps only its controlled
+        // subspace) than inside the pass leave it: to the front when they
+        // commute with every op kept before them, else to the back when they
+        // commute with every op kept after them.  If what remains is cheaper
+        // as plain launches than one pass over the state, the pass goes too.
+        std::vector<uint32_t> tail_plain;
         if (plain_split) {
             const double tile_us = kTileFixedUs + (double)(2ull * (1ull << n) * esize) / kTileBytesPerUs;
+            const double tiles = (double)(1ull << (n - b));
+            auto leaves = [&](const OpInfo &o) {
+                // inside the pass every tile walks the op record, and the tiles
+                // meeting the op's non-resident controls do its arithmetic
+                const int g = __builtin_popcountll(o.mask & ~pb.S);
+                const double in_pass = kOpPerTileUs * tiles + kOpPerAmpUs * (double)(1ull << (n - g));
+                return plain_us(o, n, esize) < in_pass;
+            };
+            std::vector<uint32_t> front, keep, back, kept;
+            uint64_t Z = 0, X = 0, G = 0;
+            for (uint32_t j : pb.ops) {
+                const OpInfo &o = info[j];
+                if (leaves(o) && commutes_with_all(o, Z, X, G)) {
+                    front.push_back(j);
+                    continue;
+                }
+                keep.push_back(j);
+                Z |= o.z;
+                X |= o.x;
+                G |= o.g;
+            }
+            Z = X = G = 0;
+            for (size_t i = keep.size(); i-- > 0;) {
+                const OpInfo &o = info[keep[i]];
+                if (leaves(o) && commutes_with_all(o, Z, X, G)) {
+                    back.push_back(keep[i]);
+                    continue;
+                }
+                kept.push_back(keep[i]);
+                Z |= o.z;
+                X |= o.x;
+                G |= o.g;
+            }
+            std::reverse(kept.begin(), kept.end());
+            std::reverse(back.begin(), back.end());
+            for (uint32_t j : front) add_plain(info[j]);
+            p->info.n_split_ops += front.size() + back.size();
             double t = 0.0;
-            for (uint32_t j : pb.ops) t += plain_us(info[j], n, esize);
-            if (t < tile_us) {
-                for (uint32_t j : pb.ops) add_plain(info[j]);
-                p->info.n_split_ops += pb.ops.size();
+            for (uint32_t j : kept) t += plain_us(info[j], n, esize);
+            if (kept.empty() || t < tile_us) {
+                for (uint32_t j : kept) add_plain(info[j]);
+                for (uint32_t j : back) add_plain(info[j]);
+                p->info.n_split_ops += kept.size();
                 continue;
             }
+            pb.ops = kept;
+            tail_plain = back;
         }
         // fill the resident set up to b qubits with the lowest unused ones
         for (int q = 0; q < n && __builtin_popcountll(pb.S) < b; ++q) pb.S |= 1ull << q;
@@ -774,6 +823,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->info.n_tile_passes += 1;
         p->info.n_stages += P.stage_end - P.stage_begin;
         p->info.bytes_moved += 2ull * (1ull << n) * esize;
+        for (uint32_t j : tail_plain) add_plain(info[j]);
     }
     p->tparams.resize(p->tops.size() * kParamStride, 0.0);
     p->info.tile_pass_bytes = 2ull * (1ull << n) * esize;
