@@ -155,44 +155,45 @@ __global__ void __launch_bounds__(256) k_gate_shift(typename CT<R>::T *__restric
 }
 
 // The same shift for registers of at most 8 qubits, with every amplitude of an
-// orbit read before any is written: a workgroup owns P whole orbits (P
-// consecutive free-bit counters, P * 2^width <= 4096 amplitudes), loads them
-// into registers, waits at a barrier and stores them shifted, so no thread
-// walks an orbit serially.  Consecutive items step through whichever index sits
-// on the lower qubits, so that the accesses are coalesced: the register value
-// when the register lies below every free qubit (v_fast), else the orbit
-// counter (P consecutive counters are consecutive free indices).
+// orbit read before any is written: a workgroup owns P = 2^(12 - width) whole
+// orbits (4,096 amplitudes, 16 per thread), loads them into registers, waits at
+// a barrier and stores them shifted, so no thread walks an orbit serially.
+// Item i = tid + 256 k of a workgroup is orbit o at register value v; the split
+// of i into (o, v) puts consecutive lanes on whichever index lies on the lower
+// qubits, so that accesses are coalesced.  The index spread is linear over
+// disjoint counter bits, so it is taken apart once: the workgroup's orbit base
+// (uniform), the thread's own bits (once per thread) and the 16 per-item parts
+// (computed on the host, passed in `it`).
+struct ShiftItems {
+    uint64_t kdep[16];  // spread counter bits of item k's orbit part
+    uint32_t kv[16];    // register-value bits of item k
+    uint32_t sh_o, m_o; // thread part of the orbit counter: (tid >> sh_o) & m_o
+    uint32_t sh_v, m_v; // thread part of the register value: (tid >> sh_v) & m_v
+};
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_gate_shift_blk(typename CT<R>::T *__restrict__ psi, uint64_t nblk,
                                                         Deposit d, uint64_t cval, int base, int width, int up,
-                                                        int lg_p, int v_fast)
+                                                        ShiftItems it)
 {
     using C = typename CT<R>::T;
-    constexpr int kMaxItems = 16;
     const uint32_t len_mask = (1u << width) - 1u;
-    const uint32_t p_mask = (1u << lg_p) - 1u;
-    const uint32_t items = 1u << (lg_p + width);
+    const int lg_p = 12 - width;
     const uint32_t tid = threadIdx.x;
+    const uint64_t dep_t = deposit_zeros((tid >> it.sh_o) & it.m_o, d) | cval;
+    const uint32_t v_t = (tid >> it.sh_v) & it.m_v;
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {  // uniform per workgroup
-        const uint64_t orb0 = blk << lg_p;
-        C x[kMaxItems];
-        uint64_t dst[kMaxItems];
+        const uint64_t r0 = deposit_zeros(blk << lg_p, d) | dep_t;
+        C x[16];
 #pragma unroll
-        for (int k = 0; k < kMaxItems; ++k) {
-            const uint32_t i = tid + 256u * k;
-            if (i < items) {
-                const uint32_t o = v_fast ? i >> width : i & p_mask;
-                const uint32_t v = v_fast ? i & len_mask : i >> lg_p;
-                const uint64_t r = deposit_zeros(orb0 + o, d) | cval;
-                const uint32_t src = (up ? v - 1u : v + 1u) & len_mask;  // new[v] = old[v -+ 1]
-                x[k] = psi[r | ((uint64_t)src << base)];
-                dst[k] = r | ((uint64_t)v << base);
-            }
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t v = v_t | it.kv[k];
+            const uint32_t src = (up ? v - 1u : v + 1u) & len_mask;  // new[v] = old[v -+ 1]
+            x[k] = psi[r0 | it.kdep[k] | ((uint64_t)src << base)];
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kMaxItems; ++k)
-            if (tid + 256u * k < items) psi[dst[k]] = x[k];
+        for (int k = 0; k < 16; ++k) psi[r0 | it.kdep[k] | ((uint64_t)(v_t | it.kv[k]) << base)] = x[k];
         __syncthreads();
     }
 }
@@ -214,6 +215,18 @@ __global__ void __launch_bounds__(256) k_projphase(typename CT<R>::T *__restrict
         r.y = fma(a.x, sn, a.y * c);
         psi[i] = r;
     }
+}
+
+// The device spread of deposit_zeros, on the host (for per-item constants).
+static uint64_t deposit_host(uint64_t x, const Deposit &d)
+{
+    uint64_t out = 0;
+    for (uint32_t k = 0; k < d.n; ++k) {
+        const uint32_t r = d.run[k];
+        const uint32_t src = r & 0xffu, dst = (r >> 8) & 0xffu, w = r >> 16;
+        out |= ((x >> src) & ((1ull << w) - 1ull)) << dst;
+    }
+    return out;
 }
 
 static Deposit make_deposit(uint64_t fixed_bits, int n)
@@ -280,17 +293,43 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
         const uint64_t reg = ((1ull << op.width) - 1ull) << op.target;
         const int lg_orb = n - (int)op.width - c;  // log2 of the number of orbits
         const uint64_t nwork = 1ull << lg_orb;
-        if (op.width <= 8) {
-            // P orbits per workgroup with P * 2^width <= 4096 (16 amplitudes per thread)
-            const int lg_p = std::min(lg_orb, 12 - (int)op.width);
-            const uint64_t nblk = 1ull << (lg_orb - lg_p);
-            const int grid = (int)std::min<uint64_t>(nblk, 4096);
+        if (op.width <= 8 && lg_orb + (int)op.width >= 12) {
+            const int w = (int)op.width;
+            const int lg_p = 12 - w;  // orbits per workgroup, 4096 amplitudes in all
             const uint64_t fixed = op.mask | reg;
             const uint64_t free_bits = ~fixed & ((n >= 64) ? ~0ull : ((1ull << n) - 1ull));
             const int low_free = free_bits ? __builtin_ctzll(free_bits) : 64;
-            hipLaunchKernelGGL(k_gate_shift_blk<R>, dim3(grid), dim3(B), 0, st, psi, nblk, make_deposit(fixed, n),
-                               op.val, (int)op.target, (int)op.width, op.kind == SV_OP_INC ? 1 : 0, lg_p,
-                               (int)op.target < low_free ? 1 : 0);
+            const bool v_fast = (int)op.target < low_free;  // the register lies below every free qubit
+            const Deposit d = make_deposit(fixed, n);
+            // item i = tid + 256 k -> (orbit o, value v), split into thread and item parts
+            ShiftItems it{};
+            for (int k = 0; k < 16; ++k) {
+                uint64_t o_k;
+                uint32_t v_k;
+                if (v_fast) {             // v = i mod 2^w, o = i >> w
+                    o_k = (uint64_t)k << (8 - w);
+                    v_k = 0;
+                } else if (lg_p >= 8) {   // o = i mod P (P >= 256), v = i / P
+                    o_k = (uint64_t)(k & ((1 << (lg_p - 8)) - 1)) << 8;
+                    v_k = (uint32_t)k >> (lg_p - 8);
+                } else {                  // P < 256: o = tid mod P, v = i / P
+                    o_k = 0;
+                    v_k = (uint32_t)k << (8 - lg_p);
+                }
+                it.kdep[k] = deposit_host(o_k, d);
+                it.kv[k] = v_k;
+            }
+            if (v_fast) {
+                it.sh_o = (uint32_t)w; it.m_o = 0xffu; it.sh_v = 0; it.m_v = (1u << w) - 1u;
+            } else if (lg_p >= 8) {
+                it.sh_o = 0; it.m_o = 0xffu; it.sh_v = 0; it.m_v = 0;
+            } else {
+                it.sh_o = 0; it.m_o = (1u << lg_p) - 1u; it.sh_v = (uint32_t)lg_p; it.m_v = 0xffu;
+            }
+            const uint64_t nblk = 1ull << (lg_orb - lg_p);
+            const int grid = (int)std::min<uint64_t>(nblk, 4096);
+            hipLaunchKernelGGL(k_gate_shift_blk<R>, dim3(grid), dim3(B), 0, st, psi, nblk, d, op.val, (int)op.target, w,
+                               op.kind == SV_OP_INC ? 1 : 0, it);
         } else {
             hipLaunchKernelGGL(k_gate_shift<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
                                make_deposit(op.mask | reg, n), op.val, (int)op.target, (int)op.width,
