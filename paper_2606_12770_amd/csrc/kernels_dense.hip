@@ -20,6 +20,17 @@ namespace svi {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// Absolute index bits of a tile: bit runs of the tile counter.
+__device__ __forceinline__ uint64_t dense_tile_base(const TilePass &P, uint64_t tile)
+{
+    uint64_t base = 0;
+    for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
+        const uint32_t sh = P.tile_shift[r];
+        base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
+    }
+    return base;
+}
+
 // Persistent: a workgroup loads its matrix operands once (64 values per lane)
 // and then strides over tiles, so the 8 KiB block matrix is not fetched again
 // for every tile.
@@ -63,19 +74,23 @@ k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const f
     }
     const uint32_t tw = lds_swizzle(tid, 4);
 
-    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint64_t base = 0;
-        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
-            const uint32_t sh = P.tile_shift[r];
-            base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
-        }
-        float2 *const pt = psi + (base | gthr);
-        float2 x[16];
+    // the amplitudes of the next tile are loaded while the current one is multiplied
+    float2 x[16];
+    if (blockIdx.x < n_tiles) {
+        const float2 *p0 = psi + (dense_tile_base(P, blockIdx.x) | gthr);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+        for (int s = 0; s < 16; ++s) x[s] = p0[P.goff[s]];
+    }
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        float2 *const pt = psi + (dense_tile_base(P, tile) | gthr);
 #pragma unroll
         for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
         __syncthreads();
+        if (tile + gridDim.x < n_tiles) {
+            const float2 *pn = psi + (dense_tile_base(P, tile + gridDim.x) | gthr);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = pn[P.goff[s]];
+        }
 
         float2 xb[16];
 #pragma unroll
@@ -96,10 +111,11 @@ k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const f
         for (int t = 0; t < 16; ++t)
             lds[lds_swizzle(gl | D.joff[8u * (t / 4) + 4u * h + (t % 4)], 4)] = make_float2(acc_re[t], acc_im[t]);
         __syncthreads();
+        float2 y[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) x[s] = lds[tw ^ P.swz0[s]];
+        for (int s = 0; s < 16; ++s) y[s] = lds[tw ^ P.swz0[s]];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = x[s];
+        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = y[s];
         __syncthreads();  // the next tile overwrites the LDS
     }
 }
@@ -155,12 +171,7 @@ k_dense_pass_f64(double2 *__restrict__ psi, const DensePass *__restrict__ dp, co
     const uint32_t tw = lds_swizzle(tid, 3);
 
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint64_t base = 0;
-        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
-            const uint32_t sh = P.tile_shift[r];
-            base |= ((tile >> (sh & 0xffu)) & P.tile_mask[r]) << (sh >> 8);
-        }
-        double2 *const pt = psi + (base | gthr);
+        double2 *const pt = psi + (dense_tile_base(P, tile) | gthr);
         {
             double2 x[16];
 #pragma unroll
