@@ -156,6 +156,7 @@ constexpr double kPlainFixedUs = 4.0, kPlainBytesPerUs = 4.0e6;
 // 0.3 ns per tile and op), and the amplitudes it applies to cost about 0.32 ps
 // each (the VALU work of a complex 2 x 2 gate in the fused kernel).
 constexpr double kOpPerTileUs = 0.31e-3, kOpPerAmpUs = 0.32e-6;
+constexpr int kLookahead = 8;  // candidate resident-set widenings compared per step
 double plain_us(const OpInfo &o, int n, int s)
 {
     double t = kPlainFixedUs + (double)touched_bytes(o, n, s) / kPlainBytesPerUs;
@@ -373,6 +374,9 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
     const bool plain_split = opts.plain_split != SV_PLAIN_SPLIT_OFF;
+    // resident-set lookahead for states whose passes are bound by HBM sweeps
+    // (planning cost grows by the candidates times the window per widening)
+    const bool lookahead = n >= 24;
 
     // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
     // in five, kept when at least dense_min_ops long ----
@@ -510,9 +514,28 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         PassBuild pb;
         pb.S = lowmask;
         const size_t wend = std::min(n_ops, first + W);
+        // ops of the window that a resident set S would let into the pass now
+        auto gain = [&](uint64_t S) {
+            uint64_t Z = 0, X = 0, G = 0;
+            int cnt = 0;
+            for (size_t j = first; j < wend; ++j) {
+                if (done[j]) continue;
+                const OpInfo &o = info[j];
+                if (dense_id[j] < 0 && (o.req & ~S) == 0 && commutes_with_all(o, Z, X, G)) {
+                    ++cnt;
+                    continue;
+                }
+                Z |= o.z;
+                X |= o.x;
+                G |= o.g;
+            }
+            return cnt;
+        };
         while (true) {
             uint64_t Z = 0, X = 0, G = 0;
             long cand = -1;
+            uint64_t alt[kLookahead];
+            int n_alt = 0;
             for (size_t j = first; j < wend; ++j) {
                 if (done[j]) continue;
                 const OpInfo &o = info[j];
@@ -528,13 +551,34 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                     pb.ops.push_back((uint32_t)j);
                     continue;
                 }
-                if (ready && cand < 0 && __builtin_popcountll(pb.S | o.req) <= b) cand = (long)j;
+                if (ready && __builtin_popcountll(pb.S | o.req) <= b) {
+                    if (cand < 0) cand = (long)j;
+                    const uint64_t m = o.req & ~pb.S;
+                    bool seen = false;
+                    for (int a = 0; a < n_alt; ++a) seen = seen || alt[a] == m;
+                    if (!seen && n_alt < kLookahead) alt[n_alt++] = m;
+                }
                 Z |= o.z;
                 X |= o.x;
                 G |= o.g;
             }
             if (cand < 0) break;
-            pb.S |= info[cand].req;
+            if (lookahead && n_alt > 1) {
+                // widen the resident set by the candidate that admits the most ops
+                // per added qubit (one step of lookahead over the window)
+                double best = -1.0;
+                uint64_t pick = alt[0];
+                for (int a = 0; a < n_alt; ++a) {
+                    const double v = (double)gain(pb.S | alt[a]) / (double)__builtin_popcountll(alt[a]);
+                    if (v > best) {
+                        best = v;
+                        pick = alt[a];
+                    }
+                }
+                pb.S |= pick;
+            } else {
+                pb.S |= info[cand].req;
+            }
         }
         // Ops cheaper as plain launches (each sweeps only its controlled
         // subspace) than inside the pass leave it: to the front when they
