@@ -660,6 +660,78 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 }
             }
         }
+        // Order the pass's ops for few register stages (list scheduling): an op
+        // whose predecessors in the pass (earlier ops it does not commute with)
+        // are placed runs as soon as its target is in the current register set,
+        // and diagonal ops run in any stage.  When nothing more fits, the ready
+        // permutations are placed (they ride on the exchange) and the next
+        // register set takes the targets of the ready ops.
+        {
+            const size_t m = pb.ops.size();
+            std::vector<std::vector<uint32_t>> pred(m);
+            for (size_t i = 0; i < m; ++i) {
+                const OpInfo &oi = info[pb.ops[i]];
+                for (size_t j = 0; j < i; ++j) {
+                    const OpInfo &oj = info[pb.ops[j]];
+                    if (!commutes_with_all(oi, oj.z, oj.x, oj.g)) pred[i].push_back((uint32_t)j);
+                }
+            }
+            std::vector<char> placed(m, 0);
+            std::vector<uint32_t> order;
+            order.reserve(m);
+            auto ready = [&](size_t i) {
+                for (uint32_t j : pred[i])
+                    if (!placed[j]) return false;
+                return true;
+            };
+            auto reg_kind = [](uint32_t k) { return k == SV_OP_U || k == SV_OP_X; };
+            auto perm_kind = [](uint32_t k) { return k == SV_OP_INC || k == SV_OP_DEC || k == SV_OP_SWAP; };
+            uint64_t regs = 0;
+            for (int k = 0; k < rb; ++k) regs |= 1ull << P.spos[nthr + k];
+            size_t left = m;
+            while (left) {
+                for (bool progress = true; progress;) {
+                    progress = false;
+                    for (size_t i = 0; i < m; ++i) {
+                        if (placed[i] || !ready(i)) continue;
+                        const OpInfo &o = info[pb.ops[i]];
+                        if (perm_kind(o.kind) || (reg_kind(o.kind) && !((regs >> o.target) & 1ull))) continue;
+                        placed[i] = 1;
+                        order.push_back(pb.ops[i]);
+                        --left;
+                        progress = true;
+                    }
+                }
+                if (!left) break;
+                for (bool progress = true; progress;) {
+                    progress = false;
+                    for (size_t i = 0; i < m; ++i) {
+                        if (placed[i] || !ready(i) || !perm_kind(info[pb.ops[i]].kind)) continue;
+                        placed[i] = 1;
+                        order.push_back(pb.ops[i]);
+                        --left;
+                        progress = true;
+                    }
+                }
+                uint64_t nr = 0;
+                int cnt = 0;
+                for (size_t i = 0; i < m && cnt < rb; ++i) {
+                    if (placed[i] || !ready(i)) continue;
+                    const OpInfo &o = info[pb.ops[i]];
+                    if (reg_kind(o.kind) && !((nr >> o.target) & 1ull)) {
+                        nr |= 1ull << o.target;
+                        ++cnt;
+                    }
+                }
+                for (int k = 0; k < n && cnt < rb; ++k)
+                    if (((regs >> k) & 1ull) && !((nr >> k) & 1ull)) {
+                        nr |= 1ull << k;
+                        ++cnt;
+                    }
+                regs = nr;
+            }
+            pb.ops = order;
+        }
         for (int s = 0; s < (1 << rb); ++s) {
             uint64_t off = 0;
             for (int k = 0; k < rb; ++k)
@@ -822,8 +894,9 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 p->tops.push_back(t);
                 continue;
             }
-            // diagonal ops
-            if (!pending.empty()) flush_into_new_stage(cur_rs);
+            // diagonal ops (after pending permutations, the new stage already takes
+            // the registers the following ops need)
+            if (!pending.empty()) flush_into_new_stage(choose_rs(i));
             if (o.kind == SV_OP_PHASE) {
                 split(o.mask | (1ull << o.target), o.val | (1ull << o.target), t);
                 t.kind = T_PHASE;
