@@ -647,47 +647,105 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         P.rb = (uint8_t)rb;
         P.nthr = (uint8_t)nthr;
         P.ntile = (uint8_t)(n - b);
+        // Commutation dependences inside the pass: op i follows every earlier op
+        // of the pass it does not commute with.
+        const size_t m = pb.ops.size();
+        std::vector<std::vector<uint32_t>> pred(m);
+        for (size_t i = 0; i < m; ++i) {
+            const OpInfo &oi = info[pb.ops[i]];
+            for (size_t j = 0; j < i; ++j) {
+                const OpInfo &oj = info[pb.ops[j]];
+                if (!commutes_with_all(oi, oj.z, oj.x, oj.g)) pred[i].push_back((uint32_t)j);
+            }
+        }
+        std::vector<char> placed(m, 0);
+        auto ready = [&](size_t i) {
+            for (uint32_t j : pred[i])
+                if (!placed[j]) return false;
+            return true;
+        };
+        auto reg_kind = [](uint32_t k) { return k == SV_OP_U || k == SV_OP_X; };
+        auto perm_kind = [](uint32_t k) { return k == SV_OP_INC || k == SV_OP_DEC || k == SV_OP_SWAP; };
+        // Register qubits for the next stage: among `allowed`, the targets of the
+        // most ready register ops (earlier first on ties), then those of `keep`,
+        // then the highest allowed qubits.
+        auto pick_regs = [&](uint64_t allowed, uint64_t keep) {
+            int cnt[64] = {0}, first_at[64];
+            for (int q = 0; q < 64; ++q) first_at[q] = 1 << 30;
+            for (size_t i = 0; i < m; ++i) {
+                if (placed[i] || !ready(i)) continue;
+                const OpInfo &o = info[pb.ops[i]];
+                if (!reg_kind(o.kind) || !((allowed >> o.target) & 1ull)) continue;
+                cnt[o.target]++;
+                first_at[o.target] = std::min(first_at[o.target], (int)i);
+            }
+            uint64_t r = 0;
+            int c = 0;
+            while (c < rb) {
+                int best = -1;
+                for (int q = 0; q < n; ++q)
+                    if (cnt[q] > 0 && !((r >> q) & 1ull) &&
+                        (best < 0 || cnt[q] > cnt[best] || (cnt[q] == cnt[best] && first_at[q] < first_at[best])))
+                        best = q;
+                if (best < 0) break;
+                r |= 1ull << best;
+                ++c;
+            }
+            for (int q = 0; q < n && c < rb; ++q)
+                if (((keep & allowed) >> q & 1ull) && !((r >> q) & 1ull)) {
+                    r |= 1ull << q;
+                    ++c;
+                }
+            for (int q = n - 1; q >= 0 && c < rb; --q)
+                if (((allowed >> q) & 1ull) && !((r >> q) & 1ull)) {
+                    r |= 1ull << q;
+                    ++c;
+                }
+            return r;
+        };
+        // Local bit order: the other resident qubits ascending (the lowest ones
+        // first, so the load stays coalesced), then the first stage's registers.
+        // Qubits of an incremented register stay out of the first registers, so
+        // that every such register keeps consecutive local bits.
+        uint64_t shifted = 0;
+        for (uint32_t j : pb.ops)
+            if (info[j].kind == SV_OP_INC || info[j].kind == SV_OP_DEC) shifted |= info[j].req;
+        uint64_t init_regs = pick_regs(pb.S & ~lowmask & ~shifted, 0);
+        if (__builtin_popcountll(init_regs) < rb) {  // too few free qubits: the highest ones, in order
+            init_regs = 0;
+            for (int q = n - 1, c = 0; q >= 0 && c < rb; --q)
+                if ((pb.S >> q) & 1ull) {
+                    init_regs |= 1ull << q;
+                    ++c;
+                }
+        }
         int lpos[64];
         for (int q = 0; q < 64; ++q) lpos[q] = -1;
         {
             int k = 0, t = 0;
             for (int q = 0; q < n; ++q) {
-                if ((pb.S >> q) & 1ull) {
+                if (((pb.S >> q) & 1ull) && !((init_regs >> q) & 1ull)) {
                     P.spos[k] = (uint8_t)q;
                     lpos[q] = k++;
-                } else {
+                } else if (!((pb.S >> q) & 1ull)) {
                     P.tpos[t++] = (uint8_t)q;
                 }
             }
+            for (int q = 0; q < n; ++q)
+                if ((init_regs >> q) & 1ull) {
+                    P.spos[k] = (uint8_t)q;
+                    lpos[q] = k++;
+                }
         }
         // Order the pass's ops for few register stages (list scheduling): an op
-        // whose predecessors in the pass (earlier ops it does not commute with)
-        // are placed runs as soon as its target is in the current register set,
-        // and diagonal ops run in any stage.  When nothing more fits, the ready
-        // permutations are placed (they ride on the exchange) and the next
-        // register set takes the targets of the ready ops.
+        // whose predecessors are placed runs as soon as its target is in the
+        // current register set, and diagonal ops run in any stage.  When nothing
+        // more fits, the ready permutations are placed (they ride on the
+        // exchange) and the next register set is picked as above.
         {
-            const size_t m = pb.ops.size();
-            std::vector<std::vector<uint32_t>> pred(m);
-            for (size_t i = 0; i < m; ++i) {
-                const OpInfo &oi = info[pb.ops[i]];
-                for (size_t j = 0; j < i; ++j) {
-                    const OpInfo &oj = info[pb.ops[j]];
-                    if (!commutes_with_all(oi, oj.z, oj.x, oj.g)) pred[i].push_back((uint32_t)j);
-                }
-            }
-            std::vector<char> placed(m, 0);
             std::vector<uint32_t> order;
             order.reserve(m);
-            auto ready = [&](size_t i) {
-                for (uint32_t j : pred[i])
-                    if (!placed[j]) return false;
-                return true;
-            };
-            auto reg_kind = [](uint32_t k) { return k == SV_OP_U || k == SV_OP_X; };
-            auto perm_kind = [](uint32_t k) { return k == SV_OP_INC || k == SV_OP_DEC || k == SV_OP_SWAP; };
-            uint64_t regs = 0;
-            for (int k = 0; k < rb; ++k) regs |= 1ull << P.spos[nthr + k];
+            uint64_t regs = init_regs;
             size_t left = m;
             while (left) {
                 for (bool progress = true; progress;) {
@@ -713,22 +771,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                         progress = true;
                     }
                 }
-                uint64_t nr = 0;
-                int cnt = 0;
-                for (size_t i = 0; i < m && cnt < rb; ++i) {
-                    if (placed[i] || !ready(i)) continue;
-                    const OpInfo &o = info[pb.ops[i]];
-                    if (reg_kind(o.kind) && !((nr >> o.target) & 1ull)) {
-                        nr |= 1ull << o.target;
-                        ++cnt;
-                    }
-                }
-                for (int k = 0; k < n && cnt < rb; ++k)
-                    if (((regs >> k) & 1ull) && !((nr >> k) & 1ull)) {
-                        nr |= 1ull << k;
-                        ++cnt;
-                    }
-                regs = nr;
+                regs = pick_regs(pb.S, regs);
             }
             pb.ops = order;
         }
