@@ -377,6 +377,8 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     // resident-set lookahead for states whose passes are bound by HBM sweeps
     // (planning cost grows by the candidates times the window per widening)
     const bool lookahead = n >= 24;
+    // two steps (pairs of widenings) while the planning cost stays small
+    const bool lookahead2 = lookahead && n_ops <= 200000;
 
     // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
     // in five, kept when at least dense_min_ops long ----
@@ -565,11 +567,17 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             if (cand < 0) break;
             if (lookahead && n_alt > 1) {
                 // widen the resident set by the candidate that admits the most ops
-                // per added qubit (one step of lookahead over the window)
+                // per added qubit, alone or followed by a second candidate
                 double best = -1.0;
                 uint64_t pick = alt[0];
                 for (int a = 0; a < n_alt; ++a) {
-                    const double v = (double)gain(pb.S | alt[a]) / (double)__builtin_popcountll(alt[a]);
+                    double v = (double)gain(pb.S | alt[a]) / (double)__builtin_popcountll(alt[a]);
+                    for (int c = 0; c < (lookahead2 ? n_alt : 0); ++c) {
+                        const uint64_t u = alt[a] | alt[c];
+                        if (c == a || __builtin_popcountll(pb.S | u) > b) continue;
+                        const double v2 = (double)gain(pb.S | u) / (double)__builtin_popcountll(u);
+                        if (v2 > v) v = v2;
+                    }
                     if (v > best) {
                         best = v;
                         pick = alt[a];
