@@ -68,6 +68,19 @@ def test_fused_plan_matches_oracle_layered(emu, n, b, rb):
     assert stats[0] * 4 < len(c)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_fused_plan_matches_oracle_24q(emu, dtype):
+    """At 24 qubits the planner widens resident sets with lookahead; the op
+    order, register choice and plain split are those of the large states."""
+    n = 24
+    c = random_layered_circuit(n, 3, seed=5, n_mcx=10, max_ctrl=8, inc_width=6)
+    psi0 = random_state(n, 6)
+    want = osv.run(c, psi0)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4, dtype)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[1] * 4 < len(c)
+
+
 def test_plain_plan_matches_oracle(emu):
     n = 9
     c = random_mixed_circuit(n, 300, seed=11)
