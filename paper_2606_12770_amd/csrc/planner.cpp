@@ -756,12 +756,15 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             uint64_t regs = init_regs;
             size_t left = m;
             while (left) {
+                const size_t left_before = left;
                 for (bool progress = true; progress;) {
                     progress = false;
                     for (size_t i = 0; i < m; ++i) {
                         if (placed[i] || !ready(i)) continue;
                         const OpInfo &o = info[pb.ops[i]];
                         if (perm_kind(o.kind) || (reg_kind(o.kind) && !((regs >> o.target) & 1ull))) continue;
+                        // (an X whose target is a register runs in the stage; otherwise it
+                        // waits for the exchange and flips its local bit there)
                         placed[i] = 1;
                         order.push_back(pb.ops[i]);
                         --left;
@@ -769,17 +772,49 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                     }
                 }
                 if (!left) break;
+                // X gates ride along (as flips of their local bit) only on an
+                // exchange that applies other permutations anyway
+                bool perms_here = false;
                 for (bool progress = true; progress;) {
                     progress = false;
                     for (size_t i = 0; i < m; ++i) {
                         if (placed[i] || !ready(i) || !perm_kind(info[pb.ops[i]].kind)) continue;
+                        perms_here = true;
                         placed[i] = 1;
                         order.push_back(pb.ops[i]);
                         --left;
                         progress = true;
                     }
                 }
-                regs = pick_regs(pb.S, regs);
+                uint64_t next_regs = pick_regs(pb.S, regs);
+                // X gates whose targets miss the next registers ride along (as flips of
+                // their local bit) on an exchange that applies other permutations anyway
+                for (bool progress = perms_here; progress;) {
+                    progress = false;
+                    for (size_t i = 0; i < m; ++i) {
+                        if (placed[i] || !ready(i)) continue;
+                        const OpInfo &o = info[pb.ops[i]];
+                        if (o.kind != SV_OP_X && !perm_kind(o.kind)) continue;
+                        if (o.kind == SV_OP_X && ((next_regs >> o.target) & 1ull)) continue;
+                        placed[i] = 1;
+                        order.push_back(pb.ops[i]);
+                        --left;
+                        progress = true;
+                    }
+                    if (progress) next_regs = pick_regs(pb.S, regs);
+                }
+                if (left == left_before && next_regs == regs) {
+                    // nothing placed and nothing will change: take the first ready op
+                    // as it comes (the emission below accepts any order)
+                    for (size_t i = 0; i < m; ++i)
+                        if (!placed[i] && ready(i)) {
+                            placed[i] = 1;
+                            order.push_back(pb.ops[i]);
+                            --left;
+                            break;
+                        }
+                }
+                regs = next_regs;
             }
             pb.ops = order;
         }
@@ -904,6 +939,14 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         for (size_t i = 0; i < pb.ops.size(); ++i) {
             const OpInfo &o = info[pb.ops[i]];
             TileOp t{};
+            const bool x_flip = o.kind == SV_OP_X && !pending.empty();
+            if (x_flip) {  // a flip of the target's local bit, applied on the next exchange
+                split(o.mask, o.val, t);
+                t.kind = T_XFLIP;
+                t.a = (uint8_t)lpos[o.target];
+                pending.push_back(t);
+                continue;
+            }
             if (is_perm_kind(o.kind)) {
                 split(o.mask, o.val, t);
                 if (o.kind == SV_OP_SWAP) {
