@@ -379,6 +379,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const bool lookahead = n >= 24;
     // two steps (pairs of widenings) while the planning cost stays small
     const bool lookahead2 = lookahead && n_ops <= 200000;
+    // X gates as flips on permutation exchanges: measured faster from 20 qubits
+    // up; below that a pass is so short that the per-slot addressing of a
+    // permutation exchange costs more than the register stage it saves
+    const bool x_flips = n >= 20;
 
     // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
     // in five, kept when at least dense_min_ops long ----
@@ -789,7 +793,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 uint64_t next_regs = pick_regs(pb.S, regs);
                 // X gates whose targets miss the next registers ride along (as flips of
                 // their local bit) on an exchange that applies other permutations anyway
-                for (bool progress = perms_here; progress;) {
+                for (bool progress = perms_here && x_flips; progress;) {
                     progress = false;
                     for (size_t i = 0; i < m; ++i) {
                         if (placed[i] || !ready(i)) continue;
@@ -939,7 +943,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         for (size_t i = 0; i < pb.ops.size(); ++i) {
             const OpInfo &o = info[pb.ops[i]];
             TileOp t{};
-            const bool x_flip = o.kind == SV_OP_X && !pending.empty();
+            const bool x_flip = x_flips && o.kind == SV_OP_X && !pending.empty();
             if (x_flip) {  // a flip of the target's local bit, applied on the next exchange
                 split(o.mask, o.val, t);
                 t.kind = T_XFLIP;
