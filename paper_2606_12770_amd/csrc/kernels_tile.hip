@@ -220,6 +220,7 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int LOWB = CTT<R>::LOWB;
+    constexpr int PG = (sizeof(R) == 4 && NR == 16) ? 8 : 4;  // slots per permutation group
     constexpr uint32_t kAllSlots = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
 
     const uint32_t tid = threadIdx.x;
@@ -237,17 +238,17 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
 #pragma unroll
                 for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
             } else {
-                // slots in groups of four: the op records are scalar loads,
-                // cheap to repeat, while the indices of all slots at once
-                // would cost registers that lower the occupancy
+                // slots in groups of PG (8 for complex64, 4 for complex128): the
+                // op records are scalar loads, cheap to repeat, while more slot
+                // indices at once would cost registers and a wave of occupancy
 #pragma unroll
-                for (int g = 0; g < NR; g += 4) {
-                    uint32_t l[4];
+                for (int g = 0; g < NR; g += PG) {
+                    uint32_t l[PG];
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) l[s] = thr | P.regoff[g + s];
-                    apply_perms<4>(l, ops, S.perm_begin, S.perm_end, base);
+                    for (int s = 0; s < PG; ++s) l[s] = thr | P.regoff[g + s];
+                    apply_perms<PG>(l, ops, S.perm_begin, S.perm_end, base);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
+                    for (int s = 0; s < PG; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
                 }
             }
             __syncthreads();
@@ -327,13 +328,13 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
             for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (L.swz[s] * (uint32_t)sizeof(C))) = x[s];
         } else {
 #pragma unroll
-            for (int g = 0; g < NR; g += 4) {
-                uint32_t l[4];
+            for (int g = 0; g < NR; g += PG) {
+                uint32_t l[PG];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) l[s] = thr | L.regoff[g + s];
-                apply_perms<4>(l, ops, pass->fperm_begin, pass->fperm_end, base);
+                for (int s = 0; s < PG; ++s) l[s] = thr | L.regoff[g + s];
+                apply_perms<PG>(l, ops, pass->fperm_begin, pass->fperm_end, base);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
+                for (int s = 0; s < PG; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
             }
         }
         __syncthreads();
