@@ -379,10 +379,8 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     const bool lookahead = n >= 24;
     // two steps (pairs of widenings) while the planning cost stays small
     const bool lookahead2 = lookahead && n_ops <= 200000;
-    // X gates as flips on permutation exchanges: measured faster from 20 qubits
-    // up; below that a pass is so short that the per-slot addressing of a
-    // permutation exchange costs more than the register stage it saves
-    const bool x_flips = n >= 20;
+    // X gates as flips of their local bit on exchanges that apply permutations
+    const bool x_flips = true;
 
     // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
     // in five, kept when at least dense_min_ops long ----
