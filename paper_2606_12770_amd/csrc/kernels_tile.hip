@@ -220,7 +220,7 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
     using C = typename CTT<R>::T;
     constexpr int NR = 1 << RB;
     constexpr int LOWB = CTT<R>::LOWB;
-    constexpr int PG = (NR == 16) ? 8 : 4;  // slots per permutation group
+    constexpr int PG = (NR == 16) ? 16 : 4;  // slots per permutation group
     constexpr uint32_t kAllSlots = (NR >= 32) ? 0xffffffffu : ((1u << NR) - 1u);
 
     const uint32_t tid = threadIdx.x;
@@ -238,9 +238,9 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
 #pragma unroll
                 for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
             } else {
-                // slots in groups of PG: the op records are scalar loads, cheap
-                // to repeat, while more slot indices at once would cost
-                // registers and a wave of occupancy
+                // all 16 slot indices at once, so the permutation records are
+                // walked once (measured faster even where the indices cost the
+                // complex64 tile a wave of occupancy); 32-slot tiles in groups of 4
 #pragma unroll
                 for (int g = 0; g < NR; g += PG) {
                     uint32_t l[PG];
