@@ -26,7 +26,7 @@ namespace svi {
 
 template <typename R> struct CTT;
 template <> struct CTT<float> { using T = float2; static constexpr int LOWB = 4; };
-template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 3; };
+template <> struct CTT<double> { using T = double2; static constexpr int LOWB = 4; };  // 8-byte halves in LDS
 
 
 // LDS element at byte offset `off` (the swizzle XOR is done on byte offsets:
@@ -204,6 +204,29 @@ __device__ __forceinline__ uint64_t tile_thread_offset(const TilePass *__restric
     return gthr;
 }
 
+// One complex128 exchange in two halves through an LDS array of doubles: the
+// real parts (write at byte offsets wa[s], barrier, read at tr ^ 8 swz[s]),
+// then the imaginary parts the same way.  The caller has passed the barrier
+// that ends the previous use of the LDS.
+// Write offsets come from `wr(s)` (recomputed or looked up, as the caller
+// chooses); the new real part lands in x[s].x once the old one is in LDS.
+template <int NR, typename W>
+__device__ __forceinline__ void exchange_halves(double2 (&x)[NR], unsigned char *lds, W wr, uint32_t tr,
+                                                const uint32_t *__restrict__ swz)
+{
+#pragma unroll
+    for (int s = 0; s < NR; ++s) *reinterpret_cast<double *>(lds + wr(s)) = x[s].x;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NR; ++s) x[s].x = *reinterpret_cast<const double *>(lds + (tr ^ (swz[s] * 8u)));
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NR; ++s) *reinterpret_cast<double *>(lds + wr(s)) = x[s].y;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NR; ++s) x[s].y = *reinterpret_cast<const double *>(lds + (tr ^ (swz[s] * 8u)));
+}
+
 // The register stages and LDS exchanges of one tile, on amplitudes already in
 // registers (load mapping in, load mapping out).  Every thread of the
 // workgroup calls this.  Every pointer comes straight from kernel arguments
@@ -233,7 +256,35 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
         if (st != pass->stage_begin) {
             const TileStage &P = stages[st - 1];
             __syncthreads();
-            if (S.perm_begin == S.perm_end) {
+            if constexpr (sizeof(R) == 8) {
+                // complex128: the real parts go through LDS, then the imaginary
+                // parts, in an array of doubles half the tile's size, so that
+                // three workgroups share a CU where whole amplitudes allow two
+                uint32_t t2 = 0;
+                for (uint32_t r = 0; r < S.n_thr_runs; ++r) {
+                    const uint32_t w = S.thr_run[r];
+                    t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+                }
+                const uint32_t tr = opaque_offset(lds_swizzle(t2, LOWB) * 8u);
+                unsigned char *const lb = reinterpret_cast<unsigned char *>(lds);
+                if (S.perm_begin == S.perm_end) {
+                    const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * 8u);
+                    exchange_halves<NR>(x, lb, [&](int s) { return tw ^ (P.swz[s] * 8u); }, tr, S.swz);
+                } else {
+                    uint32_t wa[NR];
+#pragma unroll
+                    for (int g = 0; g < NR; g += PG) {
+                        uint32_t l[PG];
+#pragma unroll
+                        for (int s = 0; s < PG; ++s) l[s] = thr | P.regoff[g + s];
+                        apply_perms<PG>(l, ops, S.perm_begin, S.perm_end, base);
+#pragma unroll
+                        for (int s = 0; s < PG; ++s) wa[g + s] = lds_swizzle(l[s], LOWB) * 8u;
+                    }
+                    exchange_halves<NR>(x, lb, [&](int s) { return wa[s]; }, tr, S.swz);
+                }
+                thr = t2;
+            } else if (S.perm_begin == S.perm_end) {
                 const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
                 for (int s = 0; s < NR; ++s) lds_at(lds, tw ^ (P.swz[s] * (uint32_t)sizeof(C))) = x[s];
@@ -251,16 +302,18 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
                     for (int s = 0; s < PG; ++s) lds[lds_swizzle(l[s], LOWB)] = x[g + s];
                 }
             }
-            __syncthreads();
-            uint32_t t2 = 0;
-            for (uint32_t r = 0; r < S.n_thr_runs; ++r) {
-                const uint32_t w = S.thr_run[r];
-                t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
-            }
-            thr = t2;
-            const uint32_t tr = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
+            if constexpr (sizeof(R) == 4) {
+                __syncthreads();
+                uint32_t t2 = 0;
+                for (uint32_t r = 0; r < S.n_thr_runs; ++r) {
+                    const uint32_t w = S.thr_run[r];
+                    t2 |= ((tid >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+                }
+                thr = t2;
+                const uint32_t tr = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
-            for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (S.swz[s] * (uint32_t)sizeof(C)));
+                for (int s = 0; s < NR; ++s) x[s] = lds_at(lds, tr ^ (S.swz[s] * (uint32_t)sizeof(C)));
+            }
         }
         // op records are prefetched one ahead; parameters sit at a fixed stride,
         // so their loads do not wait for the record
@@ -322,6 +375,27 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
     if (final_exchange) {
         const TileStage &L = stages[se - 1];
         __syncthreads();
+        if constexpr (sizeof(R) == 8) {
+            const uint32_t tr = opaque_offset(lds_swizzle(tid, LOWB) * 8u);
+            unsigned char *const lb = reinterpret_cast<unsigned char *>(lds);
+            if (pass->fperm_begin == pass->fperm_end) {
+                const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * 8u);
+                exchange_halves<NR>(x, lb, [&](int s) { return tw ^ (L.swz[s] * 8u); }, tr, pass->swz0);
+            } else {
+                uint32_t wa[NR];
+#pragma unroll
+                for (int g = 0; g < NR; g += PG) {
+                    uint32_t l[PG];
+#pragma unroll
+                    for (int s = 0; s < PG; ++s) l[s] = thr | L.regoff[g + s];
+                    apply_perms<PG>(l, ops, pass->fperm_begin, pass->fperm_end, base);
+#pragma unroll
+                    for (int s = 0; s < PG; ++s) wa[g + s] = lds_swizzle(l[s], LOWB) * 8u;
+                }
+                exchange_halves<NR>(x, lb, [&](int s) { return wa[s]; }, tr, pass->swz0);
+            }
+            return;
+        }
         if (pass->fperm_begin == pass->fperm_end) {
             const uint32_t tw = opaque_offset(lds_swizzle(thr, LOWB) * (uint32_t)sizeof(C));
 #pragma unroll
@@ -489,7 +563,7 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const uint64_t tiles = 1ull << P.ntile;
     if (p->tile_launch == SV_TILE_LAUNCH_PERSISTENT) {
         const uint32_t block = 1u << P.nthr;
-        const size_t lds = sizeof(C) << P.b;
+        const size_t lds = (size_t)8 << P.b;  // 8 bytes per amplitude: a complex64, or half a complex128
         const uint64_t g = std::min<uint64_t>(tiles, pipe_grid<R, RB>(block, lds));
         hipLaunchKernelGGL((k_tile_pass_pipe<R, RB>), dim3((uint32_t)g), dim3(block), lds, st, (C *)psi,
                            (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
@@ -500,7 +574,7 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const uint32_t gy = (uint32_t)(tiles / gx);
     const dim3 grid(gx, gy);
     const dim3 block(1u << P.nthr);
-    const size_t lds = sizeof(C) << P.b;
+    const size_t lds = (size_t)8 << P.b;
     hipLaunchKernelGGL((k_tile_pass<R, RB>), grid, block, lds, st, (C *)psi,
                        (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
                        (const TileOp *)p->d_tops, (const R *)p->d_tparams);
@@ -515,7 +589,7 @@ static int launch_batch_t(const BatchTables &T, const BatchItem *d_items, uint32
     const uint32_t gx = total > 65536 ? 65536u : (uint32_t)total;
     const uint64_t gy = (total + gx - 1) / gx;
     if (gy > 65535) return SV_EUNSUPPORTED;
-    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), sizeof(C) << T.b, st,
+    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
                        (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages, (const TileOp *)T.ops,
                        (const R *)T.prm, d_items, n_items, total);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;

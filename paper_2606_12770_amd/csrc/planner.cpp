@@ -370,7 +370,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
 
     const int nthr = b - rb;
     const int L0 = std::min(nthr, p->dtype == SV_C64 ? 5 : 4);
-    const int lowb = p->dtype == SV_C64 ? 4 : 3;  // LDS swizzle width (16 B banks groups)
+    const int lowb = 4;  // LDS swizzle width: 8-byte elements (a complex64, or half a complex128)
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;
     const bool plain_split = opts.plain_split != SV_PLAIN_SPLIT_OFF;

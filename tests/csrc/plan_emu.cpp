@@ -105,7 +105,7 @@ int check_pass_fields(const sv_plan &p, uint32_t pi)
 {
     const TilePass &P = p.passes[pi];
     const int b = P.b, rb = P.rb, nthr = P.nthr, NR = 1 << rb, T = 1 << nthr;
-    const int lowb = p.dtype == SV_C64 ? 4 : 3;
+    const int lowb = 4;
     // precomputed pass fields: run maps and swizzled slot offsets
     for (int s = 0; s < NR; ++s)
         if (P.swz0[s] != lds_swizzle((uint32_t)s << nthr, lowb)) return 20;
@@ -163,7 +163,7 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
     std::vector<int> filled((size_t)1 << b);
     std::vector<uint32_t> thr(T);
     std::vector<uint32_t> ro(NR);
-    const int lowb = p.dtype == SV_C64 ? 4 : 3;
+    const int lowb = 4;
     {
         const int rc = check_pass_fields(p, pi);
         if (rc) return rc;
