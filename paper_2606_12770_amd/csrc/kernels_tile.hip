@@ -233,7 +233,7 @@ __device__ __forceinline__ void exchange_halves(double2 (&x)[NR], unsigned char 
 // (plus uniform offsets), so the compiler knows the address spaces and reads
 // the plan tables with scalar loads; pointers read from memory would turn
 // those into per-lane flat loads.
-template <typename R, int RB>
+template <typename R, int RB, bool GR = false>
 __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
                                              const TilePass *__restrict__ pass,
                                              const TileStage *__restrict__ stages,
@@ -318,10 +318,46 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
         // op records are prefetched one ahead; parameters sit at a fixed stride,
         // so their loads do not wait for the record
         TileOp nxt;
-        if (S.op_begin < S.op_end) nxt = ops[S.op_begin];
+        if (!GR && S.op_begin < S.op_end) nxt = ops[S.op_begin];
+        uint32_t run_end = 0;  // gate runs: end of the run whose matching ops are being applied
+        uint64_t run_v = 0;
         for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
-            const TileOp op = nxt;
-            if (k + 1 < S.op_end) nxt = ops[k + 1];
+            TileOp op;
+            if constexpr (GR) {
+                // (record reads without the one-ahead prefetch, which the jumps
+                // below would make per-lane; readfirstlane keeps the indices and
+                // so the record reads scalar)
+                op = ops[k];
+                if (run_end != 0 && (k >= run_end || op.gval != run_v)) {
+                    // the run's ops for this tile are done: continue after the run
+                    k = __builtin_amdgcn_readfirstlane(run_end);
+                    run_end = 0;
+                    if (k >= S.op_end) break;
+                    op = ops[k];
+                }
+                const uint32_t L = (uint32_t)op.a | ((uint32_t)op.b << 8);
+                if (run_end == 0 && L >= 2 && op.kind != T_PROJ) {
+                    // ops k .. k + L - 1 share op's tile mask, sorted by tile value:
+                    // bisect for the first whose value is this tile's
+                    const uint64_t v = base & op.gmask;
+                    uint32_t lo = k, hi = k + L;
+                    while (lo < hi) {
+                        const uint32_t mid = __builtin_amdgcn_readfirstlane((lo + hi) >> 1);
+                        if (ops[mid].gval < v) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo >= k + L || ops[lo].gval != v) {  // no op of the run acts on this tile
+                        k += L - 1;
+                        continue;
+                    }
+                    run_end = k + L;
+                    run_v = v;
+                    k = __builtin_amdgcn_readfirstlane(lo);
+                    op = ops[k];
+                }
+            } else {
+                op = nxt;
+                if (k + 1 < S.op_end) nxt = ops[k + 1];
+            }
             const R *__restrict__ pk = prm + (size_t)k * kParamStride;
             // tile condition first: a uniform branch taken before any per-lane work
             const bool zg = (base & op.gmask) == op.gval;
@@ -428,7 +464,7 @@ __device__ __forceinline__ bool pass_final_exchange(const TilePass *__restrict__
 }
 
 // One tile of one pass: load, register stages with LDS exchanges, store.
-template <typename R, int RB>
+template <typename R, int RB, bool GR = false>
 __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
                                                const TilePass *__restrict__ pass,
                                                const TileStage *__restrict__ stages,
@@ -442,7 +478,7 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     C x[NR];
 #pragma unroll
     for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
-    tile_compute<R, RB>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
+    tile_compute<R, RB, GR>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
 #pragma unroll
     for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
 }
@@ -496,7 +532,9 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
     }
 }
 
-template <typename R, int RB>
+// GR: the pass holds gate runs (a separate instantiation, so passes without
+// them keep the plain op loop with its one-ahead record prefetch).
+template <typename R, int RB, bool GR>
 __global__ void __launch_bounds__(256)
 k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
             const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
@@ -504,7 +542,7 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
     const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    tile_pass_body<R, RB>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB, GR>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
@@ -575,9 +613,14 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const dim3 grid(gx, gy);
     const dim3 block(1u << P.nthr);
     const size_t lds = (size_t)8 << P.b;
-    hipLaunchKernelGGL((k_tile_pass<R, RB>), grid, block, lds, st, (C *)psi,
-                       (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                       (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+    if (P.gate_runs)
+        hipLaunchKernelGGL((k_tile_pass<R, RB, true>), grid, block, lds, st, (C *)psi,
+                           (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
+                           (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+    else
+        hipLaunchKernelGGL((k_tile_pass<R, RB, false>), grid, block, lds, st, (C *)psi,
+                           (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
+                           (const TileOp *)p->d_tops, (const R *)p->d_tparams);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
@@ -618,10 +661,14 @@ int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 int tile_kernel_setup()
 {
     const int big = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -46,6 +46,12 @@ enum : uint8_t {
 //   (tid & tidmask) == tidval : the thread part holds
 //   (tile base & gmask) == gval : the tile part holds (uniform)
 // Permutations keep the condition on the whole local index (lmask, lval).
+// Gate runs: in a pass with gate_runs set, a register op or T_PHASE whose
+// (a | b << 8) = L >= 2 heads a run of L consecutive ops of its stage that share
+// its tile mask (gmask) and are sorted by tile value (gval); none is a T_PROJ.
+// A tile applies only the ops of the run whose gval is its own, so it can find
+// them by bisection and pass over the rest.  (Ops with different tile values
+// never act in the same tile, so sorting them changes nothing.)
 struct TileOp {
     uint8_t kind;
     uint8_t slot;
@@ -98,7 +104,8 @@ struct TilePass {
     uint32_t fperm_begin, fperm_end;  // permutations on the final exchange
     uint8_t b, rb, nthr, ntile;
     uint8_t final_exchange;           // 1: exchange back to the load mapping before the store
-    uint8_t pad[3];
+    uint8_t gate_runs;                // 1: some stage holds gate runs (see TileOp)
+    uint8_t pad[2];
     uint32_t n_tile_runs;             // tile counter bits -> absolute index bits, as runs
     uint32_t n_gthr_runs;             // thread bits -> absolute index bits (load mapping), as runs
     uint32_t tile_shift[kMaxTileRuns];  // src | dst << 8

@@ -157,6 +157,7 @@ constexpr double kPlainFixedUs = 4.0, kPlainBytesPerUs = 4.0e6;
 // each (the VALU work of a complex 2 x 2 gate in the fused kernel).
 constexpr double kOpPerTileUs = 0.31e-3, kOpPerAmpUs = 0.32e-6;
 constexpr int kLookahead = 8;  // candidate resident-set widenings compared per step
+constexpr int kMinGateRun = 6;  // shortest run of ops with one tile mask worth a bisection
 double plain_us(const OpInfo &o, int n, int s)
 {
     double t = kPlainFixedUs + (double)touched_bytes(o, n, s) / kPlainBytesPerUs;
@@ -1039,6 +1040,50 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         for (uint32_t j : tail_plain) add_plain(info[j]);
     }
     p->tparams.resize(p->tops.size() * kParamStride, 0.0);
+    // Gate runs: within a stage, maximal runs of consecutive ops (no T_PROJ)
+    // with one nonzero tile mask are sorted by tile value (stable, parameters
+    // moved along) and their first op records the run length.  Used from 21
+    // qubits up: the run kernel reads op records without the one-ahead
+    // prefetch, which on the short passes of smaller states costs more than
+    // the bisection saves (measured 6% slower at 19 qubits).
+    for (TilePass &P : p->passes) {
+        if (n < 21) break;
+        for (uint32_t st = P.stage_begin; st < P.stage_end; ++st) {
+            const TileStage &S = p->stages[st];
+            uint32_t k = S.op_begin;
+            while (k < S.op_end) {
+                const TileOp &h = p->tops[k];
+                uint32_t e = k + 1;
+                if (h.kind != T_PROJ && h.gmask != 0)
+                    while (e < S.op_end && p->tops[e].kind != T_PROJ && p->tops[e].gmask == h.gmask && e - k < 0xffffu) ++e;
+                const uint32_t L = e - k;
+                if (L >= (uint32_t)kMinGateRun) {
+                    std::vector<uint32_t> idx(L);
+                    for (uint32_t i = 0; i < L; ++i) idx[i] = k + i;
+                    std::stable_sort(idx.begin(), idx.end(),
+                                     [&](uint32_t a, uint32_t b) { return p->tops[a].gval < p->tops[b].gval; });
+                    std::vector<TileOp> ro(L);
+                    std::vector<double> rp((size_t)L * kParamStride);
+                    for (uint32_t i = 0; i < L; ++i) {
+                        ro[i] = p->tops[idx[i]];
+                        for (int j = 0; j < kParamStride; ++j)
+                            rp[(size_t)i * kParamStride + j] = p->tparams[(size_t)idx[i] * kParamStride + j];
+                    }
+                    for (uint32_t i = 0; i < L; ++i) {
+                        TileOp t = ro[i];
+                        t.param = (k + i) * (uint32_t)kParamStride;
+                        t.a = i == 0 ? (uint8_t)(L & 0xffu) : 0;
+                        t.b = i == 0 ? (uint8_t)(L >> 8) : 0;
+                        p->tops[k + i] = t;
+                        for (int j = 0; j < kParamStride; ++j)
+                            p->tparams[(size_t)(k + i) * kParamStride + j] = rp[(size_t)i * kParamStride + j];
+                    }
+                    P.gate_runs = 1;
+                }
+                k = e;
+            }
+        }
+    }
     p->info.tile_pass_bytes = 2ull * (1ull << n) * esize;
     p->info.n_launches = p->steps.size();
     return SV_OK;

@@ -121,6 +121,20 @@ int check_pass_fields(const sv_plan &p, uint32_t pi)
         // the kernel reads the parameters of op k at k * kParamStride
         for (uint32_t k = S.op_begin; k < S.op_end; ++k)
             if (p.tops[k].param != k * (uint32_t)kParamStride || (k + 1) * kParamStride > p.tparams.size()) return 26;
+        // gate runs: the run a head announces lies in the stage, shares the
+        // head's tile mask, holds no T_PROJ and is sorted by tile value
+        for (uint32_t k = S.op_begin; k < S.op_end; ++k) {
+            const TileOp &t = p.tops[k];
+            if (t.kind == T_PROJ) continue;
+            const uint32_t L = (uint32_t)t.a | ((uint32_t)t.b << 8);
+            if (L == 0) continue;
+            if (!P.gate_runs || L < 2 || k + L > S.op_end || t.gmask == 0) return 27;
+            for (uint32_t j = k + 1; j < k + L; ++j) {
+                const TileOp &u = p.tops[j];
+                if (u.kind == T_PROJ || u.gmask != t.gmask || u.gval < p.tops[j - 1].gval) return 28;
+                if ((uint32_t)u.a | ((uint32_t)u.b << 8)) return 28;
+            }
+        }
         for (int s = 0; s < NR; ++s)
             if (S.swz[s] != lds_swizzle(S.regoff[s], lowb)) return 22;
         for (int t = 0; t < T; ++t) {
@@ -406,6 +420,11 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
         stats[2] = p.info.n_stages;
         stats[3] = p.info.bytes_moved;
         stats[4] = p.info.n_split_ops;
+        uint64_t in_runs = 0;  // ops that gate runs cover
+        for (const TileStage &S : p.stages)
+            for (uint32_t k = S.op_begin; k < S.op_end; ++k)
+                if (p.tops[k].kind != T_PROJ) in_runs += (uint32_t)p.tops[k].a | ((uint32_t)p.tops[k].b << 8);
+        stats[5] = in_runs;
     }
     return 0;
 }

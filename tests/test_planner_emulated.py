@@ -39,7 +39,7 @@ def emu():
 def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0, dense_min_ops=0):
     ops, params = circ.arrays()
     psi = np.array(psi0, dtype=np.complex128, copy=True)
-    stats = (ctypes.c_uint64 * 5)()
+    stats = (ctypes.c_uint64 * 6)()
     dp = ctypes.POINTER(ctypes.c_double)
     rc = L.emu_run(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(dp), mode, b, rb,
                    psi.ctypes.data_as(dp), stats, dense_min_ops)
@@ -79,6 +79,22 @@ def test_fused_plan_matches_oracle_24q(emu, dtype):
     got, stats = run_emu(emu, c, psi0, 1, 12, 4, dtype)
     assert np.max(np.abs(got - want)) < 1e-12
     assert stats[1] * 4 < len(c)
+
+
+def test_gate_runs_carleman_22q(emu):
+    """From 21 qubits the planner sorts runs of ops that share a tile mask by
+    tile value (the kernel then bisects for a tile's ops); the Carleman value
+    encodings form such runs.  The 22-qubit ladder at d = 3 through the fused
+    planner against the reference simulator, complex64 plan."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    cfg = cc.CarlemanConfig(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05)
+    enc = cc.build_ul(cfg)
+    circ = cc.build_qsvt(enc, np.random.default_rng(3).uniform(-np.pi, np.pi, 4))
+    psi0 = random_state(circ.n, 9)
+    want = osv.run(circ, psi0)
+    got, stats = run_emu(emu, circ, psi0, 1, 12, 4, 0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[5] > 0  # the plan holds gate runs
 
 
 def test_plain_plan_matches_oracle(emu):
