@@ -551,7 +551,7 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 // the state's first amplitude in the arena, its pass in the table and its first
 // work index.  Workgroup w finds its item by binary search over item_begin and
 // runs that tile.  Instances of a launch share the geometry (b, RB).
-template <typename R, int RB>
+template <typename R, int RB, bool GR>
 __global__ void __launch_bounds__(256)
 k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict__ passes,
              const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
@@ -567,7 +567,7 @@ k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict_
         if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
     const BatchItem &B = items[lo];
-    tile_pass_body<R, RB>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
+    tile_pass_body<R, RB, GR>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
                           reinterpret_cast<C *>(smem_raw));
 }
 
@@ -626,27 +626,34 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
 
 template <typename R, int RB>
 static int launch_batch_t(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total,
-                          hipStream_t st)
+                          bool gate_runs, hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const uint32_t gx = total > 65536 ? 65536u : (uint32_t)total;
     const uint64_t gy = (total + gx - 1) / gx;
     if (gy > 65535) return SV_EUNSUPPORTED;
-    hipLaunchKernelGGL((k_tile_batch<R, RB>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
-                       (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages, (const TileOp *)T.ops,
-                       (const R *)T.prm, d_items, n_items, total);
+    // a level holding gate runs takes the bisecting instantiation (it runs every
+    // other pass of the level correctly too, without the record prefetch)
+    if (gate_runs)
+        hipLaunchKernelGGL((k_tile_batch<R, RB, true>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
+                           (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages,
+                           (const TileOp *)T.ops, (const R *)T.prm, d_items, n_items, total);
+    else
+        hipLaunchKernelGGL((k_tile_batch<R, RB, false>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
+                           (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages,
+                           (const TileOp *)T.ops, (const R *)T.prm, d_items, n_items, total);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
 int launch_tile_batch(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total_work,
-                      hipStream_t st)
+                      bool gate_runs, hipStream_t st)
 {
     if (!n_items || !total_work) return SV_OK;
     if (T.dtype == SV_C64)
-        return T.rb == 5 ? launch_batch_t<float, 5>(T, d_items, n_items, total_work, st)
-                         : launch_batch_t<float, 4>(T, d_items, n_items, total_work, st);
-    return T.rb == 5 ? launch_batch_t<double, 5>(T, d_items, n_items, total_work, st)
-                     : launch_batch_t<double, 4>(T, d_items, n_items, total_work, st);
+        return T.rb == 5 ? launch_batch_t<float, 5>(T, d_items, n_items, total_work, gate_runs, st)
+                         : launch_batch_t<float, 4>(T, d_items, n_items, total_work, gate_runs, st);
+    return T.rb == 5 ? launch_batch_t<double, 5>(T, d_items, n_items, total_work, gate_runs, st)
+                     : launch_batch_t<double, 4>(T, d_items, n_items, total_work, gate_runs, st);
 }
 
 int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
@@ -673,10 +680,14 @@ int tile_kernel_setup()
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipGetLastError();
     return SV_OK;
 }
