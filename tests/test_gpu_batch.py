@@ -4,6 +4,8 @@
   states that running each plan on its own gives (same tile code, same
   arithmetic: bit-identical), with and without HIP-graph capture.
 * Small Carleman-LBM instances in a batch against the FP64 reference simulator.
+* A batch that holds a plan with gate runs (22-qubit Carleman ladder) matches
+  its plans run alone, bit for bit.
 * Graph replays, with the program's own eager work between them, match the
   eager result after every replay.
 * Invalid batches are refused on the host.
@@ -103,6 +105,45 @@ def test_batch_of_carleman_ladders_matches_oracle():
         want = osv.run(c, v)
         print(f"carleman batch n={c.n}: maxabs {np.max(np.abs(got - want)):.1e}", flush=True)
         assert np.max(np.abs(got - want)) < 1e-12
+    sv.sv_batch_free(batch)
+    for st in states:
+        sv.sv_free(st)
+    for p in plans:
+        sv.sv_plan_free(p)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_batch_with_gate_runs(dtype):
+    """A 22-qubit Carleman ladder (its value encodings become gate runs from 21
+    qubits; the CPU plan emulation of the same configuration shows the runs)
+    batched with smaller circuits: the level that holds runs takes the run
+    kernel for all of its passes, and every instance must come out bit-identical
+    to its plan run alone; the ladder also against the reference simulator."""
+    sv = require_gpu()
+    cfg = cc.CarlemanConfig(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05)
+    ladder = cc.build_qsvt(cc.build_ul(cfg), np.random.default_rng(3).uniform(-np.pi, np.pi, 4))
+    assert ladder.n == 22
+    circs = [ladder, random_mixed_circuit(16, 200, seed=5, max_ctrl=4), random_layered_circuit(21, 3, seed=6)]
+    inits = [random_state(c.n, 40 + i) for i, c in enumerate(circs)]
+    plans = _plans(sv, circs, dtype)
+    states = sv.sv_alloc_batch([c.n for c in circs], dtype)
+    for st, v in zip(states, inits):
+        sv.sv_set_amplitudes(st, v, 0)
+    batch = sv.sv_batch_create(states, plans, True, ONE_GROUP)
+    sv.sv_batch_execute(batch, 1)
+    for i, (c, v, p, st) in enumerate(zip(circs, inits, plans, states)):
+        got = sv.sv_amplitudes(st)
+        ref = sv.sv_alloc(c.n, dtype, v)
+        sv.sv_plan_execute(p, ref, 1)
+        want = sv.sv_amplitudes(ref)
+        sv.sv_free(ref)
+        print(f"gate-run batch instance {i}: n={c.n} dtype={dtype} maxabs={np.max(np.abs(got - want)):.1e}",
+              flush=True)
+        assert np.array_equal(got, want)
+        if i == 0:
+            oracle = osv.run(c, v)
+            tol = 1e-12 if dtype == 1 else 1e-5
+            assert np.max(np.abs(got - oracle)) < tol
     sv.sv_batch_free(batch)
     for st in states:
         sv.sv_free(st)
