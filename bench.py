@@ -441,8 +441,8 @@ def main():
     log(f"tile passes only: {ms_t:.2f} ms/step, {info_t['n_tile_passes']} launches, {avg_launch_ms * 1e3:.1f} us each")
     achieved = info_t["tile_pass_bytes"] / (avg_launch_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_tile_pass<float,4,false>", n),
-            "kernel": "k_tile_pass<float,4,false>", "launches_per_step": info64["n_launches"],
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_tile_pass<float,4,false,true>", n),
+            "kernel": "k_tile_pass<float,4,false,true>", "launches_per_step": info64["n_launches"],
             "tile_pass_launches_per_step": info64["n_tile_passes"], "avg_launch_us": avg_launch_ms * 1e3,
             "timed_on": "the same circuit planned with tile passes only",
             "tile_only_ms_per_step": ms_t}

@@ -464,7 +464,38 @@ __device__ __forceinline__ bool pass_final_exchange(const TilePass *__restrict__
 }
 
 // One tile of one pass: load, register stages with LDS exchanges, store.
-template <typename R, int RB, bool GR = false>
+// State accesses with the nontemporal hint (the pass's `stream` flag): the
+// amplitudes are read once and written once per pass.
+__device__ __forceinline__ float2 load_nt(const float2 *p)
+{
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 load_nt(const double2 *p)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void store_nt(float2 *p, float2 x)
+{
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+__device__ __forceinline__ void store_nt(double2 *p, double2 x)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+
+template <typename R, int RB, bool GR = false, bool NT = false>
 __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
                                                const TilePass *__restrict__ pass,
                                                const TileStage *__restrict__ stages,
@@ -476,11 +507,23 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     const uint64_t base = tile_base(pass, tile);
     C *const pt = psi + (base | tile_thread_offset(pass, threadIdx.x));
     C x[NR];
+    // (NT is a template parameter, not a branch on the flag: the compiler merges
+    // the loads of two branches into one and drops the hint)
+    if constexpr (NT) {
 #pragma unroll
-    for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
+        for (int s = 0; s < NR; ++s) x[s] = load_nt(pt + pass->goff[s]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
+    }
     tile_compute<R, RB, GR>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
+    if constexpr (NT) {
 #pragma unroll
-    for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+        for (int s = 0; s < NR; ++s) store_nt(pt + pass->goff[s], x[s]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
+    }
 }
 
 // Persistent form: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
@@ -533,8 +576,9 @@ k_tile_pass_pipe(typename CTT<R>::T *__restrict__ psi, const TilePass *__restric
 }
 
 // GR: the pass holds gate runs (a separate instantiation, so passes without
-// them keep the plain op loop with its one-ahead record prefetch).
-template <typename R, int RB, bool GR>
+// them keep the plain op loop with its one-ahead record prefetch).  NT: the
+// pass's `stream` flag (nontemporal state loads and stores).
+template <typename R, int RB, bool GR, bool NT>
 __global__ void __launch_bounds__(256)
 k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ pass,
             const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm)
@@ -542,7 +586,7 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
     using C = typename CTT<R>::T;
     extern __shared__ unsigned char smem_raw[];
     const uint64_t tile = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    tile_pass_body<R, RB, GR>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB, GR, NT>(psi, pass, stages, ops, prm, tile, reinterpret_cast<C *>(smem_raw));
 }
 
 // Batched tile passes: one launch runs pass `level` of every instance of a
@@ -551,7 +595,7 @@ k_tile_pass(typename CTT<R>::T *__restrict__ psi, const TilePass *__restrict__ p
 // the state's first amplitude in the arena, its pass in the table and its first
 // work index.  Workgroup w finds its item by binary search over item_begin and
 // runs that tile.  Instances of a launch share the geometry (b, RB).
-template <typename R, int RB, bool GR>
+template <typename R, int RB, bool GR, bool NT>
 __global__ void __launch_bounds__(256)
 k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict__ passes,
              const TileStage *__restrict__ stages, const TileOp *__restrict__ ops, const R *__restrict__ prm,
@@ -567,8 +611,8 @@ k_tile_batch(typename CTT<R>::T *__restrict__ arena, const TilePass *__restrict_
         if (items[mid].item_begin <= w) lo = mid; else hi = mid;
     }
     const BatchItem &B = items[lo];
-    tile_pass_body<R, RB, GR>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
-                          reinterpret_cast<C *>(smem_raw));
+    tile_pass_body<R, RB, GR, NT>(arena + B.psi_off, passes + B.pass_index, stages, ops, prm, w - B.item_begin,
+                                  reinterpret_cast<C *>(smem_raw));
 }
 
 // Resident workgroups of the persistent kernel on the whole device, cached per
@@ -613,47 +657,48 @@ static int launch_tile_t(const sv_plan *p, uint32_t pi, void *psi, hipStream_t s
     const dim3 grid(gx, gy);
     const dim3 block(1u << P.nthr);
     const size_t lds = (size_t)8 << P.b;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, (C *)psi, (const TilePass *)p->d_passes + pi,
+                           (const TileStage *)p->d_stages, (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+    };
     if (P.gate_runs)
-        hipLaunchKernelGGL((k_tile_pass<R, RB, true>), grid, block, lds, st, (C *)psi,
-                           (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                           (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+        P.stream ? go(k_tile_pass<R, RB, true, true>) : go(k_tile_pass<R, RB, true, false>);
     else
-        hipLaunchKernelGGL((k_tile_pass<R, RB, false>), grid, block, lds, st, (C *)psi,
-                           (const TilePass *)p->d_passes + pi, (const TileStage *)p->d_stages,
-                           (const TileOp *)p->d_tops, (const R *)p->d_tparams);
+        P.stream ? go(k_tile_pass<R, RB, false, true>) : go(k_tile_pass<R, RB, false, false>);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
 template <typename R, int RB>
 static int launch_batch_t(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total,
-                          bool gate_runs, hipStream_t st)
+                          bool gate_runs, bool stream, hipStream_t st)
 {
     using C = typename CTT<R>::T;
     const uint32_t gx = total > 65536 ? 65536u : (uint32_t)total;
     const uint64_t gy = (total + gx - 1) / gx;
     if (gy > 65535) return SV_EUNSUPPORTED;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st, (C *)T.arena,
+                           (const TilePass *)T.passes, (const TileStage *)T.stages, (const TileOp *)T.ops,
+                           (const R *)T.prm, d_items, n_items, total);
+    };
     // a level holding gate runs takes the bisecting instantiation (it runs every
     // other pass of the level correctly too, without the record prefetch)
     if (gate_runs)
-        hipLaunchKernelGGL((k_tile_batch<R, RB, true>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
-                           (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages,
-                           (const TileOp *)T.ops, (const R *)T.prm, d_items, n_items, total);
+        stream ? go(k_tile_batch<R, RB, true, true>) : go(k_tile_batch<R, RB, true, false>);
     else
-        hipLaunchKernelGGL((k_tile_batch<R, RB, false>), dim3(gx, (uint32_t)gy), dim3(1u << T.nthr), (size_t)8 << T.b, st,
-                           (C *)T.arena, (const TilePass *)T.passes, (const TileStage *)T.stages,
-                           (const TileOp *)T.ops, (const R *)T.prm, d_items, n_items, total);
+        stream ? go(k_tile_batch<R, RB, false, true>) : go(k_tile_batch<R, RB, false, false>);
     return hipGetLastError() == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 
 int launch_tile_batch(const BatchTables &T, const BatchItem *d_items, uint32_t n_items, uint64_t total_work,
-                      bool gate_runs, hipStream_t st)
+                      bool gate_runs, bool stream, hipStream_t st)
 {
     if (!n_items || !total_work) return SV_OK;
     if (T.dtype == SV_C64)
-        return T.rb == 5 ? launch_batch_t<float, 5>(T, d_items, n_items, total_work, gate_runs, st)
-                         : launch_batch_t<float, 4>(T, d_items, n_items, total_work, gate_runs, st);
-    return T.rb == 5 ? launch_batch_t<double, 5>(T, d_items, n_items, total_work, gate_runs, st)
-                     : launch_batch_t<double, 4>(T, d_items, n_items, total_work, gate_runs, st);
+        return T.rb == 5 ? launch_batch_t<float, 5>(T, d_items, n_items, total_work, gate_runs, stream, st)
+                         : launch_batch_t<float, 4>(T, d_items, n_items, total_work, gate_runs, stream, st);
+    return T.rb == 5 ? launch_batch_t<double, 5>(T, d_items, n_items, total_work, gate_runs, stream, st)
+                     : launch_batch_t<double, 4>(T, d_items, n_items, total_work, gate_runs, stream, st);
 }
 
 int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
@@ -663,31 +708,27 @@ int launch_tile_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
     return p->rb == 5 ? launch_tile_t<double, 5>(p, pi, psi, st) : launch_tile_t<double, 4>(p, pi, psi, st);
 }
 
+template <typename R, int RB>
+static void set_lds_limit(int bytes)
+{
+    const void *const kernels[] = {
+        (const void *)k_tile_pass<R, RB, false, false>, (const void *)k_tile_pass<R, RB, false, true>,
+        (const void *)k_tile_pass<R, RB, true, false>,  (const void *)k_tile_pass<R, RB, true, true>,
+        (const void *)k_tile_batch<R, RB, false, false>, (const void *)k_tile_batch<R, RB, false, true>,
+        (const void *)k_tile_batch<R, RB, true, false>,  (const void *)k_tile_batch<R, RB, true, true>,
+        (const void *)k_tile_pass_pipe<R, RB>};
+    for (const void *k : kernels) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 // LDS above 64 KiB per workgroup must be requested per kernel.  A refusal is
 // not fatal: a launch that then exceeds the limit fails with a runtime error.
 int tile_kernel_setup()
 {
     const int big = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<float, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass<double, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<float, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_pass_pipe<double, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<float, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)k_tile_batch<double, 5, true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    set_lds_limit<float, 4>(big);
+    set_lds_limit<float, 5>(big);
+    set_lds_limit<double, 4>(big);
+    set_lds_limit<double, 5>(big);
     (void)hipGetLastError();
     return SV_OK;
 }

@@ -99,13 +99,26 @@ struct TileStage {
     uint32_t regoff[1 << kMaxRB];   // local index offset of register slot s (32-bit: read with scalar loads)
 };
 
+// Whether tile passes stream a state of `bytes` (all the states of a batched
+// level together) with nontemporal loads and stores.  16 MiB or less, or
+// 256 MiB or more, takes the hint; a state in between stays in the last-level
+// cache from pass to pass, and the hint would send it back to HBM.  Measured on
+// MI355X: the 19-qubit first-order ladders (4 and 8 MiB) 4-10% faster with it,
+// the 28- and 31-qubit circuits (2 and 16 GiB) 2% faster, the 23-qubit
+// second-order ladder (64 and 128 MiB) 3-7% slower.
+inline bool stream_state_bytes(uint64_t bytes)
+{
+    return bytes <= (16ull << 20) || bytes >= (256ull << 20);
+}
+
 struct TilePass {
     uint32_t stage_begin, stage_end;
     uint32_t fperm_begin, fperm_end;  // permutations on the final exchange
     uint8_t b, rb, nthr, ntile;
     uint8_t final_exchange;           // 1: exchange back to the load mapping before the store
     uint8_t gate_runs;                // 1: some stage holds gate runs (see TileOp)
-    uint8_t pad[2];
+    uint8_t stream;                   // 1: state loads and stores carry the nontemporal hint
+    uint8_t pad[1];
     uint32_t n_tile_runs;             // tile counter bits -> absolute index bits, as runs
     uint32_t n_gthr_runs;             // thread bits -> absolute index bits (load mapping), as runs
     uint32_t tile_shift[kMaxTileRuns];  // src | dst << 8

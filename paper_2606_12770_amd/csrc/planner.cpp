@@ -1030,6 +1030,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         for (auto &t : pending) p->tops.push_back(t);
         P.fperm_end = (uint32_t)p->tops.size();
         P.final_exchange = (!at_load_mapping || !pending.empty()) ? 1 : 0;
+        P.stream = stream_state_bytes((p->dtype == SV_C64 ? 8ull : 16ull) << n) ? 1 : 0;
         pending.clear();
 
         p->steps.push_back(Step{1, (uint32_t)p->passes.size()});

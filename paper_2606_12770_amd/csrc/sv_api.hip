@@ -31,6 +31,7 @@ struct sv_batch {
     std::vector<uint32_t> n_items;      // per level
     std::vector<uint64_t> total;        // per level
     std::vector<uint8_t> gate_runs;     // per level: some pass of the level holds gate runs
+    std::vector<uint8_t> stream_state;  // per level: nontemporal state accesses (the level's total state bytes)
     std::vector<svi::BatchItem *> d_items;
     std::vector<sv_state *> states;
     bool use_graph = false;
@@ -735,11 +736,13 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
             std::vector<svi::BatchItem> items;
             uint64_t total = 0;
             uint8_t runs = 0;
+            uint64_t level_bytes = 0;
             for (size_t i : grp) {
                 const sv_plan *p = plans[i];
                 if (lv >= p->steps.size()) continue;
                 const uint32_t pi = p->steps[lv].index;
                 runs |= p->passes[pi].gate_runs;
+                level_bytes += (uint64_t)es << p->n;
                 svi::BatchItem it{};
                 it.psi_off = (uint64_t)((char *)states[i]->d_psi - (char *)arena->d_mem) / es;
                 it.pass_index = pass_base[i] + pi;
@@ -758,6 +761,7 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
             B->n_items.push_back((uint32_t)items.size());
             B->total.push_back(total);
             B->gate_runs.push_back(runs);
+            B->stream_state.push_back(svi::stream_state_bytes(level_bytes) ? 1 : 0);
         }
     }
     B->groups = groups.size();
@@ -770,7 +774,7 @@ int batch_launch_all(sv_batch *B)
 {
     for (size_t lv = 0; lv < B->d_items.size(); ++lv) {
         int rc = svi::launch_tile_batch(B->tables, B->d_items[lv], B->n_items[lv], B->total[lv], B->gate_runs[lv] != 0,
-                                        B->stream);
+                                        B->stream_state[lv] != 0, B->stream);
         if (rc != SV_OK) return fail(rc, "batched launch failed");
     }
     return SV_OK;

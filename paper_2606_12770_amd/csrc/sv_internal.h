@@ -41,8 +41,8 @@ int launch_copy(void *dst, int dtd, const void *src, int dts, int n, hipStream_t
 constexpr int kReduceBlocks = 2048;
 
 // batched tile passes: items of one level, on `stream`; `gate_runs` when some
-// pass of the level holds gate runs
+// pass of the level holds gate runs, `stream_state` for nontemporal state accesses
 int launch_tile_batch(const BatchTables &tables, const BatchItem *d_items, uint32_t n_items, uint64_t total_work,
-                      bool gate_runs, hipStream_t stream);
+                      bool gate_runs, bool stream_state, hipStream_t stream);
 
 }  // namespace svi
