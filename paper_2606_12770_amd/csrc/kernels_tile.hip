@@ -20,6 +20,7 @@
 #include <mutex>
 #include <utility>
 
+#include "state_access.h"
 #include "sv_internal.h"
 
 namespace svi {
@@ -464,37 +465,6 @@ __device__ __forceinline__ bool pass_final_exchange(const TilePass *__restrict__
 }
 
 // One tile of one pass: load, register stages with LDS exchanges, store.
-// State accesses with the nontemporal hint (the pass's `stream` flag): the
-// amplitudes are read once and written once per pass.
-__device__ __forceinline__ float2 load_nt(const float2 *p)
-{
-    typedef float v2 __attribute__((ext_vector_type(2)));
-    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ double2 load_nt(const double2 *p)
-{
-    typedef double v2 __attribute__((ext_vector_type(2)));
-    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void store_nt(float2 *p, float2 x)
-{
-    typedef float v2 __attribute__((ext_vector_type(2)));
-    v2 v;
-    v.x = x.x;
-    v.y = x.y;
-    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
-}
-__device__ __forceinline__ void store_nt(double2 *p, double2 x)
-{
-    typedef double v2 __attribute__((ext_vector_type(2)));
-    v2 v;
-    v.x = x.x;
-    v.y = x.y;
-    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
-}
-
 template <typename R, int RB, bool GR = false, bool NT = false>
 __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ psi,
                                                const TilePass *__restrict__ pass,
@@ -507,23 +477,11 @@ __device__ __forceinline__ void tile_pass_body(typename CTT<R>::T *__restrict__ 
     const uint64_t base = tile_base(pass, tile);
     C *const pt = psi + (base | tile_thread_offset(pass, threadIdx.x));
     C x[NR];
-    // (NT is a template parameter, not a branch on the flag: the compiler merges
-    // the loads of two branches into one and drops the hint)
-    if constexpr (NT) {
 #pragma unroll
-        for (int s = 0; s < NR; ++s) x[s] = load_nt(pt + pass->goff[s]);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NR; ++s) x[s] = pt[pass->goff[s]];
-    }
+    for (int s = 0; s < NR; ++s) x[s] = load_state<NT>(pt + pass->goff[s]);
     tile_compute<R, RB, GR>(x, pass, stages, ops, prm, base, pass_final_exchange(pass), lds);
-    if constexpr (NT) {
 #pragma unroll
-        for (int s = 0; s < NR; ++s) store_nt(pt + pass->goff[s], x[s]);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NR; ++s) pt[pass->goff[s]] = x[s];
-    }
+    for (int s = 0; s < NR; ++s) store_state<NT>(pt + pass->goff[s], x[s]);
 }
 
 // Persistent form: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
