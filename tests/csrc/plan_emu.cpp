@@ -116,6 +116,11 @@ int check_pass_fields(const sv_plan &p, uint32_t pi)
             g1 |= (uint64_t)(((uint32_t)t >> (P.gthr_shift[r] & 0xffu)) & P.gthr_mask[r]) << (P.gthr_shift[r] >> 8);
         if (g0 != g1) return 21;
     }
+    {
+        // nontemporal state accesses for 16 MiB of state or less, or 256 MiB or more
+        const uint64_t bytes = (p.dtype == SV_C64 ? 8ull : 16ull) << p.n;
+        if (P.stream != ((bytes <= (16ull << 20) || bytes >= (256ull << 20)) ? 1 : 0)) return 37;
+    }
     for (uint32_t st = P.stage_begin; st < P.stage_end; ++st) {
         const TileStage &S = p.stages[st];
         // the kernel reads the parameters of op k at k * kParamStride
