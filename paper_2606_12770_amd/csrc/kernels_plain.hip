@@ -12,6 +12,7 @@
 
 #include <algorithm>
 
+#include "state_access.h"
 #include "sv_internal.h"
 
 namespace svi {
@@ -61,7 +62,7 @@ static inline int grid_for(uint64_t work, int block)
     return (int)g;
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_u(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
                                                 Deposit d, uint64_t cval, uint64_t tbit, Mat2<R> m)
 {
@@ -70,13 +71,13 @@ __global__ void __launch_bounds__(256) k_gate_u(typename CT<R>::T *__restrict__ 
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
         const uint64_t i0 = deposit_zeros(w, d) | cval;
         const uint64_t i1 = i0 | tbit;
-        const C a = psi[i0], b = psi[i1];
-        psi[i0] = mat_row(m.v[0], m.v[1], m.v[2], m.v[3], a, b);
-        psi[i1] = mat_row(m.v[4], m.v[5], m.v[6], m.v[7], a, b);
+        const C a = load_state<NT>(psi + i0), b = load_state<NT>(psi + i1);
+        store_state<NT>(psi + i0, mat_row(m.v[0], m.v[1], m.v[2], m.v[3], a, b));
+        store_state<NT>(psi + i1, mat_row(m.v[4], m.v[5], m.v[6], m.v[7], a, b));
     }
 }
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_x(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
                                                 Deposit d, uint64_t cval, uint64_t tbit)
 {
@@ -85,14 +86,14 @@ __global__ void __launch_bounds__(256) k_gate_x(typename CT<R>::T *__restrict__ 
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
         const uint64_t i0 = deposit_zeros(w, d) | cval;
         const uint64_t i1 = i0 | tbit;
-        const C a = psi[i0], b = psi[i1];
-        psi[i0] = b;
-        psi[i1] = a;
+        const C a = load_state<NT>(psi + i0), b = load_state<NT>(psi + i1);
+        store_state<NT>(psi + i0, b);
+        store_state<NT>(psi + i1, a);
     }
 }
 
 // multiply by (c, s) every amplitude whose target bit is 1 and controls hold
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_phase(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
                                                     Deposit d, uint64_t setbits, R c, R s)
 {
@@ -100,16 +101,16 @@ __global__ void __launch_bounds__(256) k_gate_phase(typename CT<R>::T *__restric
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
         const uint64_t i = deposit_zeros(w, d) | setbits;
-        const C a = psi[i];
+        const C a = load_state<NT>(psi + i);
         C r;
         r.x = fma(a.x, c, -a.y * s);
         r.y = fma(a.x, s, a.y * c);
-        psi[i] = r;
+        store_state<NT>(psi + i, r);
     }
 }
 
 // exchange amplitude i (bit a = 1, bit b = 0) with i ^ abit ^ bbit
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_swap(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
                                                    Deposit d, uint64_t cval, uint64_t abit, uint64_t bbit)
 {
@@ -118,9 +119,9 @@ __global__ void __launch_bounds__(256) k_gate_swap(typename CT<R>::T *__restrict
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
         const uint64_t i = deposit_zeros(w, d) | cval | abit;
         const uint64_t j = i ^ abit ^ bbit;
-        const C x = psi[i], y = psi[j];
-        psi[i] = y;
-        psi[j] = x;
+        const C x = load_state<NT>(psi + i), y = load_state<NT>(psi + j);
+        store_state<NT>(psi + i, y);
+        store_state<NT>(psi + j, x);
     }
 }
 
@@ -171,7 +172,7 @@ struct ShiftItems {
     uint32_t sh_v, m_v; // thread part of the register value: (tid >> sh_v) & m_v
 };
 
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_shift_blk(typename CT<R>::T *__restrict__ psi, uint64_t nblk,
                                                         Deposit d, uint64_t cval, int base, int width, int up,
                                                         ShiftItems it)
@@ -189,11 +190,11 @@ __global__ void __launch_bounds__(256) k_gate_shift_blk(typename CT<R>::T *__res
         for (int k = 0; k < 16; ++k) {
             const uint32_t v = v_t | it.kv[k];
             const uint32_t src = (up ? v - 1u : v + 1u) & len_mask;  // new[v] = old[v -+ 1]
-            x[k] = psi[r0 | it.kdep[k] | ((uint64_t)src << base)];
+            x[k] = load_state<NT>(psi + (r0 | it.kdep[k] | ((uint64_t)src << base)));
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) psi[r0 | it.kdep[k] | ((uint64_t)(v_t | it.kv[k]) << base)] = x[k];
+        for (int k = 0; k < 16; ++k) store_state<NT>(psi + (r0 | it.kdep[k] | ((uint64_t)(v_t | it.kv[k]) << base)), x[k]);
         __syncthreads();
     }
 }
@@ -252,7 +253,7 @@ static Deposit make_deposit(uint64_t fixed_bits, int n)
     return d;
 }
 
-template <typename R>
+template <typename R, bool NT>
 static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
 {
     using C = typename CT<R>::T;
@@ -264,19 +265,19 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
         const uint64_t nwork = 1ull << (n - 1 - c);
         Mat2<R> m;
         for (int k = 0; k < 8; ++k) m.v[k] = (R)op.m[k];
-        hipLaunchKernelGGL(k_gate_u<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+        hipLaunchKernelGGL((k_gate_u<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
                            make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target, m);
         break;
     }
     case SV_OP_X: {
         const uint64_t nwork = 1ull << (n - 1 - c);
-        hipLaunchKernelGGL(k_gate_x<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+        hipLaunchKernelGGL((k_gate_x<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
                            make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target);
         break;
     }
     case SV_OP_PHASE: {
         const uint64_t nwork = 1ull << (n - 1 - c);
-        hipLaunchKernelGGL(k_gate_phase<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+        hipLaunchKernelGGL((k_gate_phase<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
                            make_deposit(op.mask | (1ull << op.target), n), op.val | (1ull << op.target),
                            (R)cos(op.m[0]), (R)sin(op.m[0]));
         break;
@@ -284,7 +285,7 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
     case SV_OP_SWAP: {
         const uint64_t ab = 1ull << op.target, bb = 1ull << op.width;
         const uint64_t nwork = 1ull << (n - 2 - c);
-        hipLaunchKernelGGL(k_gate_swap<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+        hipLaunchKernelGGL((k_gate_swap<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
                            make_deposit(op.mask | ab | bb, n), op.val, ab, bb);
         break;
     }
@@ -328,7 +329,7 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
             }
             const uint64_t nblk = 1ull << (lg_orb - lg_p);
             const int grid = (int)std::min<uint64_t>(nblk, 4096);
-            hipLaunchKernelGGL(k_gate_shift_blk<R>, dim3(grid), dim3(B), 0, st, psi, nblk, d, op.val, (int)op.target, w,
+            hipLaunchKernelGGL((k_gate_shift_blk<R, NT>), dim3(grid), dim3(B), 0, st, psi, nblk, d, op.val, (int)op.target, w,
                                op.kind == SV_OP_INC ? 1 : 0, it);
         } else {
             hipLaunchKernelGGL(k_gate_shift<R>, dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
@@ -351,8 +352,11 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
 
 int launch_plain(const PlainOp &op, int n, int dtype, void *psi, hipStream_t stream)
 {
-    return dtype == SV_C64 ? launch_plain_t<float>(op, n, psi, stream)
-                           : launch_plain_t<double>(op, n, psi, stream);
+    // nontemporal state accesses by the size rule of the tile passes
+    const bool nt = stream_state_bytes((dtype == SV_C64 ? 8ull : 16ull) << n);
+    if (dtype == SV_C64)
+        return nt ? launch_plain_t<float, true>(op, n, psi, stream) : launch_plain_t<float, false>(op, n, psi, stream);
+    return nt ? launch_plain_t<double, true>(op, n, psi, stream) : launch_plain_t<double, false>(op, n, psi, stream);
 }
 
 // ---------------------------------------------------------------------------
