@@ -1,7 +1,7 @@
 // State-vector loads and stores with an optional nontemporal hint, for the
-// tile passes, which read and write every amplitude once.  (The dense
-// block pass keeps plain accesses: with the hint its complex128 form was 17%
-// slower and its complex64 form unchanged.)
+// tile passes and the plain gate kernels, which read and write each amplitude
+// they touch once.  (The dense block pass keeps plain accesses: with the hint
+// its complex128 form was 17% slower and its complex64 form unchanged.)
 // The hint is a template parameter: two branches over the same addresses would
 // be merged by the compiler into one access without the hint.
 #pragma once
