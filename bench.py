@@ -51,8 +51,22 @@ def cpu_baseline(circ, budget_s: float):
     dt = time.perf_counter() - t0
     del psi
     return {"value": done / dt, "unit": "gates/s", "cores": osv.threads(), "kind": "oracle",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
             "sample": f"first {done} of {len(ops)} gates of the same 28-qubit circuit, complex128, "
                       f"{dt:.1f} s on {osv.threads()} OpenMP threads"}
+
+
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def measured_traffic(kernel_name, qubits):

@@ -60,7 +60,7 @@ extern "C" {
  *                                                    projector-controlled phase of one QSVT step
  *                                                    (QSVT circuit figure, Sec. II.D.5); here
  *                                                    ctrl_* is the projector condition
- * The elementary gate set of Sec. III (Toffoli, CNOT, H, X, R_Y, S, S^dagger and
+ * The elementary gate set of Sec. III.F.2 (Toffoli, CNOT, H, X, R_Y, S, S^dagger and
  * their multi-controlled forms) maps onto U, X, RY and PHASE.
  */
 #define SV_OP_U          0
@@ -132,107 +132,164 @@ typedef struct {
 
 /* ---- state lifetime ------------------------------------------------------- */
 
-/* Allocate a 2^n_qubits-amplitude state in device memory (1 <= n_qubits <= 36).
- * init: NULL for |0...0>, else 2^n interleaved complex128 values (converted to the
- * state's precision).  stream: a hipStream_t to issue work on, or NULL for a
- * stream the library creates.  On success *out owns the state. */
+/* sv_alloc — the simulated register of the circuit of Sec. II.D (system
+ * register: Carleman index, Taylor index k and time step m; row labels i_L and
+ * i_A, target t; the QSVT signal qubit of Sec. II.D.5), as 2^n_qubits
+ * amplitudes in device memory (1 <= n_qubits <= 36; the qubit counts of
+ * Sec. III.F.1).  init: NULL for |0...0>, else 2^n interleaved complex128
+ * host values, converted to the state's precision: this is how the
+ * right-hand side b is loaded, f(0) in the m = 0 block and zero elsewhere
+ * (Sec. II.D.5).  stream: a hipStream_t to issue work on, or NULL for one the
+ * library creates.  On success *out owns the state (free with sv_free).
+ * Errors: SV_EINVAL (bad n_qubits or dtype, out NULL), SV_ENOMEM (the state
+ * does not fit the free device memory), SV_EDEVICE. */
 int sv_alloc(int n_qubits, int dtype, const double *init, void *stream, sv_state **out);
 
-/* Release a state (NULL is accepted). */
+/* sv_free — releases a state of sv_alloc / sv_alloc_batch (the register of
+ * Sec. II.D) and its stream if the library created it.  NULL is accepted. */
 int sv_free(sv_state *s);
 
-/* Qubit count and precision of a state. */
+/* sv_info — qubit count (Sec. III.F.1) and precision of a state; either
+ * output pointer may be NULL.  SV_EINVAL for a NULL state. */
 int sv_info(const sv_state *s, int *n_qubits, int *dtype);
 
 /* ---- circuits ------------------------------------------------------------- */
 
-/* Apply ops[0..n_ops) in order (plans, runs, frees the plan).  opts NULL = fused. */
+/* sv_apply_circuit — applies ops[0..n_ops) in order: the elementary gate set
+ * of Sec. III.F.2 (Toffoli, CNOT, H, X, R_Y, S, S^dagger) and the
+ * multi-controlled forms the block encodings of Sec. II.D.1-II.D.4 are built
+ * from (value loads R_Y, controlled increments and decrements for streaming
+ * and the k, m counters, register swaps), plus the projector-controlled phase
+ * of the QSVT ladder (Sec. II.D.5).  params is the float64 parameter pool the
+ * ops index (n_params reals); both arrays are the caller's and only read.
+ * opts NULL = fused.  The call plans, runs and frees a plan.  Errors:
+ * SV_EINVAL (an op fails validation: nothing is launched and the state is
+ * unchanged), SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED. */
 int sv_apply_circuit(sv_state *s, const sv_op *ops, size_t n_ops,
                      const double *params, size_t n_params, const sv_apply_opts *opts);
 
-/* Plan an op list once for states of n_qubits qubits and precision dtype, so it
- * can be executed many times (the QSVT ladder repeats the same U_L / U_L^dagger
- * op lists d times).  The plan copies everything it needs. */
+/* sv_plan_create — plans an op list once for states of n_qubits qubits and
+ * precision dtype so that it can run many times: the QSVT ladder of
+ * Sec. II.D.5 applies the same U_L and U_L^dagger op lists d times, so its
+ * elementary gate count is linear in d (Sec. III.F.2).  The plan copies what
+ * it needs from ops and params.  Errors as sv_apply_circuit; *out owns the
+ * plan (free with sv_plan_free). */
 int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops,
                    const double *params, size_t n_params, const sv_apply_opts *opts,
                    sv_plan **out);
+
+/* sv_plan_free — releases a plan of sv_plan_create (the reusable U_L or
+ * U_L^dagger of Sec. II.D.5).  NULL is accepted. */
 int sv_plan_free(sv_plan *p);
+
+/* sv_plan_get_info — launch and byte counts of a plan (the per-call cost of
+ * the U_L oracle, Sec. III.F.2).  SV_EINVAL for NULL arguments. */
 int sv_plan_get_info(const sv_plan *p, sv_plan_info *info);
 
-/* Execute a plan `repeat` times on a state of matching size and precision. */
+/* sv_plan_execute — runs a plan `repeat` times on a state of matching size and
+ * precision (repeated U_L calls of the ladder, Sec. II.D.5).  SV_EINVAL on a
+ * size or precision mismatch or repeat < 0 (nothing launched). */
 int sv_plan_execute(sv_plan *p, sv_state *s, int repeat);
 
-/* Execute a sequence of plans: plans[seq[0]], plans[seq[1]], ... seq_len entries,
- * one host call (the QSVT ladder: phase, U_L, phase, U_L^dagger, ...). */
-int sv_plan_execute_seq(sv_plan *const *plans, const int32_t *seq, size_t seq_len, sv_state *s);
+/* sv_plan_execute_seq — runs plans[seq[0]], plans[seq[1]], ... (seq_len
+ * entries) in one host call: the QSVT ladder of Sec. II.D.5 as phase, U_L,
+ * phase, U_L^dagger, ...  plans holds n_plans entries; every seq entry must
+ * lie in [0, n_plans), and every referenced plan must match the state, or the
+ * call returns SV_EINVAL before any launch. */
+int sv_plan_execute_seq(sv_plan *const *plans, size_t n_plans, const int32_t *seq, size_t seq_len,
+                        sv_state *s);
 
-/* Execute a plan `repeat` times bracketed by HIP events on the state's stream;
- * *ms is the elapsed device time of all repeats. */
+/* sv_plan_time — as sv_plan_execute (the ladder's repeated oracle calls,
+ * Sec. II.D.5), bracketed by HIP events on the state's stream; *ms is the
+ * elapsed device time of all repeats.  SV_EINVAL for ms NULL or repeat < 1. */
 int sv_plan_time(sv_plan *p, sv_state *s, int repeat, double *ms);
 
 /* ---- reductions, post-selection, read-out (all accumulate in FP64) ---------- */
 
-/* P = sum of |a_i|^2 over (i & mask) == value.  If keep != 0 the other amplitudes
- * are set to zero, and if renormalize != 0 the kept ones are divided by sqrt(P).
- * mask = 0, value = 0, keep = 0 returns the squared norm (norm drift check).
- * P == 0 with keep != 0 gives SV_EZEROPROB and leaves the state unchanged. */
+/* sv_postselect — the post-selection that completes the QSVT solve: the
+ * solution sits in the block where every block-encoding ancilla (the row
+ * labels and the target) and the QSVT signal qubit are 0 (Sec. II.D.5), and
+ * the final-time state in the rows m >= N_t of the time-step register, which
+ * the terminal-copy rows of L fill (Sec. II.D.4); the success probability of
+ * that projection scales as 1/kappa (Sec. IV.D.1).
+ * *prob_out = P = sum of |a_i|^2 over (i & mask) == value, in FP64 for either
+ * precision.  keep != 0: the other amplitudes are set to zero; renormalize
+ * != 0 then divides the kept ones by sqrt(P).  mask = 0, value = 0, keep = 0
+ * returns the squared norm (norm drift check).  Errors: SV_EINVAL (mask or
+ * value outside the state, value not inside mask), SV_EZEROPROB (P == 0 with
+ * keep != 0; the state is unchanged). */
 int sv_postselect(sv_state *s, uint64_t mask, uint64_t value, int keep, int renormalize,
                   double *prob_out);
 
-/* Copy amplitudes [offset, offset+count) to host as interleaved complex128. */
+/* sv_amplitudes — read-out of amplitudes [offset, offset+count) to the
+ * caller's host buffer `out` (2 count doubles, interleaved complex128): the
+ * simulated output state that Sec. III.E compares with the classical Taylor
+ * solution (a full read-out that only a classical simulation affords,
+ * Sec. IV.D.1).  Allocates a device staging buffer per call.  SV_EINVAL for a
+ * range outside the state. */
 int sv_amplitudes(const sv_state *s, uint64_t offset, uint64_t count, double *out);
 
-/* Overwrite amplitudes [offset, offset+count) from host interleaved complex128. */
+/* sv_set_amplitudes — overwrites amplitudes [offset, offset+count) from the
+ * caller's host interleaved complex128 values: the right-hand side b, f(0) in
+ * the m = 0 block (Sec. II.D.5).  SV_EINVAL for a range outside the state. */
 int sv_set_amplitudes(sv_state *s, uint64_t offset, uint64_t count, const double *in);
 
-/* Copy the amplitudes of src into dst (same qubit count; precisions may differ). */
+/* sv_copy — copies the amplitudes of src into dst (same qubit count;
+ * precisions may differ): a reference state kept beside a run, for the
+ * comparisons of Sec. III.E.  SV_EINVAL on a size mismatch. */
 int sv_copy(sv_state *dst, const sv_state *src);
 
-/* <a|b> = sum conj(a_i) b_i in FP64 (same qubit count; precisions may differ). */
+/* sv_inner — <a|b> = sum conj(a_i) b_i in FP64 (same qubit count; precisions
+ * may differ): the overlap behind the fidelity of a run against a reference
+ * state, the agreement measure of Sec. III.E.  SV_EINVAL on a size mismatch. */
 int sv_inner(const sv_state *a, const sv_state *b, double *re, double *im);
 
 /* ---- batches of independent circuits ---------------------------------------
- * Many small circuits (for instance Carleman-LBM instances of different grid
- * sizes, Taylor orders and step counts, hence different qubit counts) run
- * together: launch k executes the k-th tile pass of every instance, as one
- * grid over all their tiles, so small states share the device instead of
- * running one after another. */
+ * Many independent instances of the circuit of Sec. II.D (different grid
+ * sizes, Taylor orders and step counts, hence different qubit counts, as in
+ * the parameter scans of Sec. III.D-III.E) run together on one device. */
 
-/* Allocate `count` states of n_qubits[i] qubits, precision dtype, in one device
- * arena (each state starts on a 2 MiB boundary), all on one stream (stream, or a
- * library-created one when NULL), each initialised to |0...0>.  out[i] receives
- * the states; free each with sv_free (the arena goes with the last one).  On an
- * error no state is returned and nothing stays allocated. */
+/* sv_alloc_batch — `count` registers of the circuit of Sec. II.D, of
+ * n_qubits[i] qubits and precision dtype, in one device arena (each state
+ * starts on a 2 MiB boundary), all on one stream (stream, or a library-created
+ * one when NULL), each initialised to |0...0>.  out[i] receives the states;
+ * free each with sv_free (the arena goes with the last one).  On an error no
+ * state is returned and nothing stays allocated. */
 int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_state **out);
 
 typedef struct sv_batch sv_batch;
 
-/* Bind plans[i] to states[i] for i < count.  Every plan must be fused (tile
- * passes only), with one tile geometry and precision across the batch; the
- * states must be distinct and come from one sv_alloc_batch arena.  Instances, ordered by size, are
- * packed into groups of at most group_bytes of state (0: 192 MiB, about what
- * the last-level cache holds; UINT64_MAX: one group); a group runs level by
- * level, each level one launch over the tiles of all its instances.
- * use_graph != 0 captures all launches in a HIP graph on first execution and
- * replays it afterwards.  The batch keeps its own copy of the plans' tables
- * (the plans may be freed) and points into the arena: free it before the
- * states. */
+/* sv_batch_create — binds plans[i] (each the ladder or oracle of one instance
+ * of Sec. II.D.5) to states[i] for i < count.  Every plan must be fused
+ * (tile passes only), with one tile geometry and precision across the batch;
+ * the states must be distinct and come from one sv_alloc_batch arena.
+ * Instances, ordered by size, are packed into groups of at most group_bytes
+ * of state (0: 192 MiB, about what the last-level cache holds; UINT64_MAX: one
+ * group); a group runs level by level, each level one launch over the tiles of
+ * all its instances.  use_graph != 0 captures all launches in a HIP graph on
+ * first execution and replays it afterwards.  The batch keeps its own copy of
+ * the plans' tables (the plans may be freed) and points into the arena: free
+ * it before the states. */
 int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
                     uint64_t group_bytes, sv_batch **out);
 
-/* Run every instance's plan `repeat` times; returns when the work is done. */
+/* sv_batch_execute — runs every instance's plan (Sec. II.D.5 ladders)
+ * `repeat` times; returns when the work is done. */
 int sv_batch_execute(sv_batch *b, int repeat);
 
-/* As sv_batch_execute, bracketed by HIP events (graph capture, if any, happens
- * before the timed region); *ms is the device time of all repeats. */
+/* sv_batch_time — as sv_batch_execute (Sec. II.D.5 ladders), bracketed by HIP
+ * events (graph capture, if any, happens before the timed region); *ms is the
+ * device time of all repeats. */
 int sv_batch_time(sv_batch *b, int repeat, double *ms);
 
-/* Launches and groups of one execution, and the total IR ops it applies. */
+/* sv_batch_levels — launches and groups of one execution, and the total IR
+ * ops (elementary gates of Sec. III.F.2) it applies. */
 int sv_batch_levels(const sv_batch *b, uint64_t *launches, uint64_t *groups, uint64_t *gates);
 
+/* sv_batch_free — releases a batch (its copies of the Sec. II.D.5 plans). */
 int sv_batch_free(sv_batch *b);
 
-/* ---- diagnostics ---------------------------------------------------------- */
+/* ---- diagnostics (library-defined; no passage of the paper) --------------- */
 const char *sv_strerror(int code);
 const char *sv_last_error(void);
 

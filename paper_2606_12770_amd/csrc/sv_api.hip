@@ -98,27 +98,30 @@ int validate_ops(int n, const sv_op *ops, size_t n_ops, const double *params, si
         case SV_OP_PROJPHASE: np = 1; break;
         default: break;
         }
-        if (np && (!params || o.param + np > n_params)) return bad("parameter offset out of range");
+        // (unsigned comparisons written so that no sum can wrap around)
+        if (np && (!params || n_params < np || o.param > (uint64_t)(n_params - np)))
+            return bad("parameter offset out of range");
         switch (o.kind) {
         case SV_OP_U:
         case SV_OP_X:
         case SV_OP_PHASE:
         case SV_OP_RY:
         case SV_OP_PROJPHASE:
-            if ((int)o.target >= n) return bad("target qubit >= n");
+            if (o.target >= (uint32_t)n) return bad("target qubit >= n");
             if ((o.ctrl_mask >> o.target) & 1ull) return bad("target is also a control");
             if (o.width != 0) return bad("width must be 0");
             break;
         case SV_OP_INC:
         case SV_OP_DEC: {
             if (o.width < 1 || o.width > 24) return bad("register width must be in [1, 24]");
-            if ((int)(o.target + o.width) > n) return bad("register exceeds the qubit count");
+            if (o.target >= (uint32_t)n || o.width > (uint32_t)n - o.target)
+                return bad("register exceeds the qubit count");
             const uint64_t reg = ((1ull << o.width) - 1ull) << o.target;
             if (reg & o.ctrl_mask) return bad("register overlaps the controls");
             break;
         }
         case SV_OP_SWAP:
-            if ((int)o.target >= n || (int)o.width >= n) return bad("swap qubit >= n");
+            if (o.target >= (uint32_t)n || o.width >= (uint32_t)n) return bad("swap qubit >= n");
             if (o.target == o.width) return bad("swap of a qubit with itself");
             if (((o.ctrl_mask >> o.target) & 1ull) || ((o.ctrl_mask >> o.width) & 1ull))
                 return bad("swap qubit is also a control");
@@ -385,9 +388,11 @@ int sv_plan_execute(sv_plan *p, sv_state *s, int repeat)
     return SV_OK;
 }
 
-int sv_plan_execute_seq(sv_plan *const *plans, const int32_t *seq, size_t seq_len, sv_state *s)
+int sv_plan_execute_seq(sv_plan *const *plans, size_t n_plans, const int32_t *seq, size_t seq_len, sv_state *s)
 {
     if (!plans || (!seq && seq_len)) return fail(SV_EINVAL, "NULL argument");
+    for (size_t k = 0; k < seq_len; ++k)
+        if (seq[k] < 0 || (size_t)seq[k] >= n_plans) return fail(SV_EINVAL, "sequence entry outside the plan array");
     for (size_t k = 0; k < seq_len; ++k) {
         int rc = check_plan_state(plans[seq[k]], s);
         if (rc != SV_OK) return rc;

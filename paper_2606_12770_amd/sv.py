@@ -71,7 +71,7 @@ def load_library(path: str = LIB_PATH):
         "sv_plan_free": [vp],
         "sv_plan_get_info": [vp, ctypes.POINTER(sv_plan_info)],
         "sv_plan_execute": [vp, vp, ctypes.c_int],
-        "sv_plan_execute_seq": [pvp, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, vp],
+        "sv_plan_execute_seq": [pvp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, vp],
         "sv_plan_time": [vp, vp, ctypes.c_int, dp],
         "sv_postselect": [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp],
         "sv_amplitudes": [vp, ctypes.c_uint64, ctypes.c_uint64, dp],
@@ -176,7 +176,8 @@ def sv_plan_execute(plan, state, repeat: int = 1):
 def sv_plan_execute_seq(plans, seq, state):
     arr = (ctypes.c_void_p * len(plans))(*[p.value for p in plans])
     s = np.ascontiguousarray(seq, dtype=np.int32)
-    _check(load_library().sv_plan_execute_seq(arr, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(s), state))
+    _check(load_library().sv_plan_execute_seq(arr, len(plans), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              len(s), state))
 
 
 def sv_plan_time(plan, state, repeat: int = 1) -> float:

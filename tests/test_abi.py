@@ -57,3 +57,85 @@ def test_error_strings_without_device():
     assert lib.sv_strerror(0).decode() == "ok"
     assert "zero-probability" in lib.sv_strerror(-3).decode()
     assert lib.sv_strerror(-99).decode() == "unknown error"
+
+
+def _comment_blocks():
+    """Each declared function with the comment block written right above it
+    (a declaration that directly follows another shares its block)."""
+    text = open(HEADER).read()
+    out = {}
+    pending = ""
+    for m in re.finditer(r"/\*(.*?)\*/|\b(sv_[a-z_0-9]+)\s*\(", text, flags=re.S):
+        if m.group(1) is not None:
+            pending = m.group(1)
+        elif m.group(2) not in out:
+            out[m.group(2)] = pending
+    return out
+
+
+def test_every_entry_point_cites_the_passage_that_defines_it():
+    """Every exported computation names the section of the paper it follows;
+    only the two diagnostics calls are library-defined, and say so."""
+    blocks = _comment_blocks()
+    names = declared_functions()
+    assert set(blocks) >= set(names)
+    for name in names:
+        block = blocks[name]
+        if name in ("sv_strerror", "sv_last_error"):
+            assert "no passage of the paper" in block, name
+            continue
+        assert re.search(r"Sec\. (II|III|IV)(\.[A-F](\.\d)?)?", block), f"{name}: no section cited"
+        assert name in block, f"{name}: its comment block does not name it"
+
+
+def _plan_create_rc(n, ops, params):
+    """sv_plan_create on host-validated input: argument checks run before any
+    HIP call, so invalid ops are refused here without a device."""
+    lib = sv.load_library()
+    ops = np.ascontiguousarray(ops, dtype=OP_DTYPE)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    out = ctypes.c_void_p()
+    return lib.sv_plan_create(n, sv.SV_C64, ops.ctypes.data, len(ops),
+                              params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(params), None,
+                              ctypes.byref(out))
+
+
+def test_out_of_range_ops_are_refused_before_any_launch():
+    from paper_2606_12770_amd.circuits import ir
+    n = 10
+    params = np.zeros(8)
+
+    def op(kind, target=0, width=0, mask=0, val=0, param=0):
+        r = np.zeros(1, dtype=OP_DTYPE)
+        r["kind"], r["target"], r["width"] = kind, target, width
+        r["ctrl_mask"], r["ctrl_val"], r["param"] = mask, val, param
+        return r
+
+    bad = [
+        op(ir.X, target=0xFFFFFFFF),                       # wraps to -1 as a signed int
+        op(ir.X, target=1 << 31),
+        op(ir.U, target=1 << 31),
+        op(ir.PHASE, target=3, param=0xFFFFFFFFFFFFFFFF),  # param + count wraps around
+        op(ir.U, target=3, param=(1 << 64) - 4),
+        op(ir.U, target=3, param=1),                       # needs params[1..9): one past the pool
+        op(ir.INC, target=0xFFFFFFFE, width=4),            # target + width wraps around
+        op(ir.INC, target=8, width=3),                     # register past the last qubit
+        op(ir.SWAP, target=2, width=0xFFFFFFFF),
+        op(ir.SWAP, target=1 << 31, width=2),
+        op(ir.X, target=2, mask=1 << 10),                  # control qubit >= n
+        op(ir.X, target=2, mask=1, val=2),                 # value outside the mask
+    ]
+    for rec in bad:
+        assert _plan_create_rc(n, rec, params) == sv.SV_EINVAL, rec
+        assert sv.sv_last_error()
+    assert _plan_create_rc(n, op(ir.U, target=3, param=0), params) != sv.SV_EINVAL
+
+
+def test_sequence_entries_are_checked_against_the_plan_count():
+    lib = sv.load_library()
+    plans = (ctypes.c_void_p * 1)(None)
+    for bad in ([1], [-1], [0, 5]):
+        seq = np.asarray(bad, dtype=np.int32)
+        rc = lib.sv_plan_execute_seq(plans, 1, seq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(seq), None)
+        assert rc == sv.SV_EINVAL
+        assert "outside the plan array" in sv.sv_last_error()
