@@ -396,6 +396,13 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
 
 }  // namespace
 
+// When set, complex64 plans run with their parameters rounded to float, as
+// the library uploads them (tile and dense parameters, plain-op matrices and
+// phase angles' cosines and sines are then computed from the rounded values
+// only where the kernels do the same); the arithmetic stays double.
+static int g_round_params_f32 = 0;
+extern "C" void emu_set_param_rounding(int on) { g_round_params_f32 = on; }
+
 extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode,
                        int tile_qubits, int reg_qubits, double *psi_io, uint64_t *stats, int dense_min_ops)
 {
@@ -406,6 +413,13 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     std::string err;
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;
+    if (g_round_params_f32 && dtype == SV_C64) {
+        for (double &v : p.tparams) v = (double)(float)v;
+        for (double &v : p.dparams) v = (double)(float)v;
+        for (PlainOp &op : p.plain)
+            if (op.kind == SV_OP_U)
+                for (double &v : op.m) v = (double)(float)v;
+    }
     cd *psi = reinterpret_cast<cd *>(psi_io);
     std::vector<int> rd(1ull << n), wr(1ull << n);
     for (const auto &st : p.steps) {

@@ -16,3 +16,23 @@ def require_gpu():
     from paper_2606_12770_amd import sv
     sv.load_library()  # raises if the library was not built: never a silent fallback
     return sv
+
+
+def max_rel_err(got, want):
+    """Largest amplitude error relative to the largest reference amplitude."""
+    import numpy as np
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+# Element-wise bar for complex64 against the FP64 oracle: every amplitude
+# within 1e-5 of the largest one.  Each gate rounds an amplitude it touches to
+# about 2^-24 relative (and its parameters are rounded once); over a few
+# thousand gates that stays near 1e-6 of the amplitudes involved, while one
+# wrong amplitude of a typical size is off by about its own magnitude.
+C64_REL = 1e-5
+
+
+def assert_c64_close(got, want, rel=C64_REL, what=""):
+    err = max_rel_err(got, want)
+    print(f"{what} complex64 max |err| / max |want| = {err:.2e} (bar {rel:.0e})", flush=True)
+    assert err < rel, f"{what}: complex64 amplitude error {err:.2e} above {rel:.0e}"

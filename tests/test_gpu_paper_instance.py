@@ -7,10 +7,13 @@ complex64 plan.
 Checks on the system amplitudes with the ancillas and the signal at 0:
 * against the oracle's singular-value transform of the same phases (its own
   Chebyshev coefficients from plain 2x2 products of the phases): infidelity
-  below 1e-6, and the element-wise error after removing the one global factor
-  that FP32 Hadamards leave (fp32(1/sqrt 2) is 1.7e-8 low; the ladder holds
-  ten label Hadamards per call, 7.1e5 in all), which must itself stay inside
-  that bound;
+  below 1e-6, and every amplitude within 1e-3 of the largest one with no
+  global factor removed (the ladder holds ten label Hadamards per call, 7.1e5
+  in all; complex64 plans store them in exact pairs, so fp32(1/sqrt 2), 1.7e-8
+  low, no longer shrinks the state);
+* the FP64 norm (drift at most 1e-5) and the FP64 post-selection probability of
+  the final-time rows (sv_postselect on the device) against the same quantity
+  from the oracle's transform, to 1e-4 relative;
 * the final-time rows against the classical N_K = 3 Taylor solution:
   1 - F below twice the square of the polynomial's relative error (plus 1e-9
   for FP32);
@@ -30,7 +33,8 @@ from oracle import qsvt as oq
 from paper_2606_12770_amd.circuits import carleman_circuit as cc
 from paper_2606_12770_amd.circuits import qsp
 from tests.gpu_util import require_gpu
-from tests.test_gpu_carleman import infid, system_to_reg
+from tests.carleman_ref import system_to_reg
+from tests.test_gpu_carleman import infid
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +62,9 @@ def test_second_order_run_at_full_degree():
     sv.sv_plan_execute(plan, st.h, 1)
     sys_amp = sv.sv_amplitudes(st.h, 0, 1 << L.n_sys)
     norm2 = st.prob()
-    log(f"GPU ladder: {time.time() - t0:.1f} s, |psi|^2 = {norm2:.6f}")
+    fmask, fval = cc.postselect_condition(L)
+    p_final = st.prob(fmask, fval)
+    log(f"GPU ladder: {time.time() - t0:.1f} s, |psi|^2 = {norm2:.9f}, P_final = {p_final:.6e}")
     st.close()
     sv.sv_plan_free(plan)
 
@@ -77,18 +83,21 @@ def test_second_order_run_at_full_degree():
     got = sys_amp[idx]
     f_tr = infid(want, got)
     s = np.vdot(got, want) / np.vdot(got, got)
-    err = np.max(np.abs(s * got - want)) / np.max(np.abs(want))
-    n_h = 10 * d
-    log(f"vs transform: infidelity {f_tr:.2e}, global factor |s| - 1 = {abs(s) - 1:.2e} "
-        f"(bound {n_h * 2.0 ** -24:.1e}), rel max err after it {err:.2e}")
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    log(f"vs transform: infidelity {f_tr:.2e}, |s| - 1 = {abs(s) - 1:.2e} for the best global factor s, "
+        f"rel max err {err:.2e}, norm drift {abs(norm2 - 1):.2e}")
     assert f_tr < 1e-6
-    assert abs(abs(s) - 1.0) < n_h * 2.0 ** -24
     assert err < 1e-3
+    assert abs(norm2 - 1.0) < 1e-5
+    assert abs(abs(s) - 1.0) < 1e-5
 
     x = oc.forward_substitution(Lm, b, len(y0))
     D = len(y0)
     R = (1 << L.n_m) * (1 << L.n_k)
     fin = slice(R // 2 * D, R * D)
+    p_want = float(np.vdot(want[fin], want[fin]).real)
+    log(f"P_final: device {p_final:.6e}, oracle transform {p_want:.6e}, rel diff {abs(p_final / p_want - 1):.2e}")
+    assert abs(p_final / p_want - 1.0) < 1e-4
     one_minus_f = infid(x[fin], got[fin])
     rest = np.ones(1 << L.n_sys, bool)
     rest[idx] = False

@@ -186,3 +186,43 @@ def test_dense_blocks_match_oracle(emu, n, seed, dtype):
     # without dense blocks the same plan path agrees too
     got2, _ = run_emu(emu, c, psi0, 1, 12, 4, dtype, dense_min_ops=0)
     assert np.max(np.abs(got2 - want)) < 1e-12
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_complex64_hadamards_keep_the_norm(emu, mode):
+    """Uncontrolled Hadamards stored as fp32(1/sqrt 2) would each shrink the
+    state by 1.7e-8 (the rounding of 1/sqrt 2, always downward); complex64
+    plans store them in exact pairs (sqrt 2 H, H / sqrt 2).  With the plan's
+    parameters rounded to float as the library uploads them, 4,000 Hadamards
+    (interleaved with CNOTs so that none fold together) keep the norm to
+    1e-12, where the rounded matrix alone would lose 1.4e-4; with an odd
+    count, the one left over costs its single 3.4e-8."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    n = 12
+    emu.emu_set_param_rounding.argtypes = [ctypes.c_int]
+    emu.emu_set_param_rounding.restype = None
+    for extra in (0, 1):
+        c = Circuit(n)
+        for layer in range(4000 // n):
+            for q in range(n):
+                c.h(q)
+            for q in range(n):
+                c.x((q + 1 + layer) % n, {q: 1})
+        for q in range(4000 - (4000 // n) * n + extra):
+            c.h(q)
+        n_h = sum(1 for r in c.arrays()[0] if r["kind"] == 0)
+        assert n_h == 4000 + extra
+        psi0 = random_state(n, 2)
+        want = osv.run(c, psi0)
+        emu.emu_set_param_rounding(1)
+        try:
+            got, _ = run_emu(emu, c, psi0, mode, 12, 4, 0)
+        finally:
+            emu.emu_set_param_rounding(0)
+        drift = abs(np.vdot(got, got).real - 1.0)
+        print(f"mode {mode}: {n_h} Hadamards, norm drift {drift:.2e}")
+        assert drift < (1e-12 if extra == 0 else 1e-7)
+        assert np.max(np.abs(got - want)) < 1e-12 + extra * 1e-7
+        # without the pairing the rounded Hadamard loses this much per gate
+        h32 = np.float32(1 / np.sqrt(2))
+        assert 1.0 - 2 * float(h32) ** 2 > 3e-8
