@@ -25,14 +25,21 @@ def max_rel_err(got, want):
 
 
 # Element-wise bar for complex64 against the FP64 oracle: every amplitude
-# within 1e-5 of the largest one.  Each gate rounds an amplitude it touches to
-# about 2^-24 relative (and its parameters are rounded once); over a few
-# thousand gates that stays near 1e-6 of the amplitudes involved, while one
-# wrong amplitude of a typical size is off by about its own magnitude.
+# within 1e-5 of the largest one per 1,000 gates applied (at least 1e-5).
+# Each gate rounds the amplitudes it touches to about 2^-24 relative and its
+# parameters are rounded once; lowered circuits add uncontrolled rotation
+# pairs that cancel only up to that rounding, so the error grows with the
+# gate count.  One wrong amplitude of a typical size is off by about its own
+# magnitude, far above the bar.
 C64_REL = 1e-5
 
 
-def assert_c64_close(got, want, rel=C64_REL, what=""):
+def c64_bar(n_ops=None):
+    return C64_REL * max(1.0, (n_ops or 0) / 1000.0)
+
+
+def assert_c64_close(got, want, n_ops=None, what=""):
+    rel = c64_bar(n_ops)
     err = max_rel_err(got, want)
-    print(f"{what} complex64 max |err| / max |want| = {err:.2e} (bar {rel:.0e})", flush=True)
-    assert err < rel, f"{what}: complex64 amplitude error {err:.2e} above {rel:.0e}"
+    print(f"{what} complex64 max |err| / max |want| = {err:.2e} (bar {rel:.1e}, {n_ops} ops)", flush=True)
+    assert err < rel, f"{what}: complex64 amplitude error {err:.2e} above {rel:.1e}"

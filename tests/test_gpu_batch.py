@@ -246,7 +246,7 @@ def test_batched_workload_matches_oracle():
         print(f"instance {i}: {L.n} qubits (N_x {cfg.nx}, N_K {cfg.nk}, N_t {cfg.nt}), infidelity {f:.1e}, "
               f"rel max err {err:.1e}", flush=True)
         assert f < 1e-6
-        assert_c64_close(got, want, what=f"batched instance {i}")
+        assert_c64_close(got, want, len(circs[i]), what=f"batched instance {i}")
     print(f"worst over 64 instances: infidelity {worst_f:.1e}, rel max err {worst_e:.1e}", flush=True)
     sv.sv_batch_free(batch)
     for p in plans:

@@ -77,7 +77,7 @@ def test_c1_ladder_matches_oracle(form, dtype, mode):
         # 22 qubits: the gate-run kernel (runs of value encodings sorted by tile
         # value) and the complex64 LDS exchange, element by element
         assert f < 1e-6
-        assert_c64_close(got, want, what=f"C1 d=13 {form}")
+        assert_c64_close(got, want, len(circ), what=f"C1 d=13 {form}")
         assert abs(np.vdot(got, got).real - 1.0) < 1e-6
 
 
@@ -250,4 +250,4 @@ def test_c1_ladder_persistent_tile_launch(dtype):
         assert np.max(np.abs(outs[0] - want)) < 1e-12
     else:
         assert infid(want, outs[0]) < 1e-6
-        assert_c64_close(outs[0], want, what="C1 persistent")
+        assert_c64_close(outs[0], want, len(circ), what="C1 persistent")
