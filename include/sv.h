@@ -104,6 +104,15 @@ typedef struct {
                           modelled cheaper than one tile pass over the whole state runs
                           as those launches; SV_PLAIN_SPLIT_OFF (1): tile passes only
                           (required for plans given to sv_batch_create)              */
+    int compile;       /* fused: how tile passes run.  SV_COMPILE_OFF (1): the generic
+                          tile kernel, which reads each pass's op records at run time;
+                          SV_COMPILE_ON (2): every distinct pass is compiled at plan
+                          creation (hiprtc, for the current device) into a kernel with
+                          its op list written out, and runs as that kernel (same
+                          arithmetic, bit-identical states; plan creation takes
+                          longer); SV_COMPILE_AUTO (0): ON for states of at least 21
+                          qubits with the grid launch form, OFF otherwise, and OFF if
+                          compilation is unavailable                                  */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0
@@ -112,6 +121,10 @@ typedef struct {
 
 #define SV_PLAIN_SPLIT_AUTO 0
 #define SV_PLAIN_SPLIT_OFF 1
+
+#define SV_COMPILE_AUTO 0
+#define SV_COMPILE_OFF 1
+#define SV_COMPILE_ON 2
 
 typedef struct sv_state sv_state;
 typedef struct sv_plan sv_plan;
@@ -128,6 +141,7 @@ typedef struct {
     uint64_t n_dense_passes;  /* launches that apply a dense 5-qubit block           */
     uint64_t n_dense_ops;     /* IR ops absorbed into dense blocks                   */
     uint64_t n_split_ops;     /* fused: IR ops run as plain launches by the cost model */
+    uint64_t n_compiled_kernels; /* compiled plans: distinct specialised pass kernels; 0 otherwise */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

@@ -216,6 +216,11 @@ struct sv_plan {
     void *d_dense = nullptr, *d_dparams = nullptr;
     int device = -1;
     sv_plan_info info{};
+    // specialised tile-pass kernels (compiled plans): function per pass and
+    // the pass's first parameter (reals into the device parameter array)
+    bool compiled = false;
+    std::vector<void *> jit_fn;
+    std::vector<uint32_t> jit_prm;
 };
 
 namespace svi {

@@ -15,6 +15,8 @@
 
 namespace svi {
 int tile_kernel_setup();
+int jit_prepare(sv_plan *p, std::string &err);
+int launch_jit_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st);
 
 struct Arena {
     void *d_mem = nullptr;
@@ -199,7 +201,8 @@ int run_plan_once(const sv_plan *p, sv_state *s)
 {
     for (const auto &st : p->steps) {
         int rc = st.type == 0   ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, s->stream)
-                 : st.type == 1 ? svi::launch_tile_pass(p, st.index, s->d_psi, s->stream)
+                 : st.type == 1 ? (p->compiled ? svi::launch_jit_pass(p, st.index, s->d_psi, s->stream)
+                                               : svi::launch_tile_pass(p, st.index, s->d_psi, s->stream))
                                 : svi::launch_dense_pass(p, st.index, s->d_psi, s->stream);
         if (rc != SV_OK) return fail(rc, "kernel launch failed");
     }
@@ -335,6 +338,8 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         return fail(SV_EINVAL, "unknown tile_launch");
     if (o.plain_split != SV_PLAIN_SPLIT_AUTO && o.plain_split != SV_PLAIN_SPLIT_OFF)
         return fail(SV_EINVAL, "unknown plain_split");
+    if (o.compile != SV_COMPILE_AUTO && o.compile != SV_COMPILE_OFF && o.compile != SV_COMPILE_ON)
+        return fail(SV_EINVAL, "unknown compile");
     int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
     if (rc != SV_OK) return rc;
     int dev = 0;
@@ -357,6 +362,30 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         release_plan(p);
         delete p;
         return rc;
+    }
+    // specialised pass kernels: on request, or automatically for states of 21
+    // qubits and more launched as a grid (LDS of a pass up to 64 KiB)
+    const bool can = o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty() &&
+                     p->tile_launch == SV_TILE_LAUNCH_GRID && ((size_t)8 << p->b) <= 65536;
+    const bool want = o.compile == SV_COMPILE_ON || (o.compile == SV_COMPILE_AUTO && n_qubits >= 21);
+    if (can && want) {
+        std::string jerr;
+        rc = svi::jit_prepare(p, jerr);
+        if (rc == SV_OK) {
+            p->compiled = true;
+        } else if (o.compile == SV_COMPILE_ON) {
+            release_plan(p);
+            delete p;
+            return fail(rc, jerr);
+        } else {
+            p->jit_fn.clear();
+            p->jit_prm.clear();
+            p->info.n_compiled_kernels = 0;
+        }
+    } else if (o.compile == SV_COMPILE_ON && o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty()) {
+        release_plan(p);
+        delete p;
+        return fail(SV_EUNSUPPORTED, "compiled tile passes need the grid launch form and at most 64 KiB of LDS");
     }
     *out = p;
     return SV_OK;

@@ -21,6 +21,7 @@ SV_C64, SV_C128 = 0, 1
 SV_MODE_PLAIN, SV_MODE_FUSED = 0, 1
 SV_TILE_LAUNCH_AUTO, SV_TILE_LAUNCH_GRID, SV_TILE_LAUNCH_PERSISTENT = 0, 1, 2
 SV_PLAIN_SPLIT_AUTO, SV_PLAIN_SPLIT_OFF = 0, 1
+SV_COMPILE_AUTO, SV_COMPILE_OFF, SV_COMPILE_ON = 0, 1, 2
 
 EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
@@ -38,14 +39,16 @@ class SVError(RuntimeError):
 
 class sv_apply_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int),
-                ("dense_min_ops", ctypes.c_int), ("tile_launch", ctypes.c_int), ("plain_split", ctypes.c_int)]
+                ("dense_min_ops", ctypes.c_int), ("tile_launch", ctypes.c_int), ("plain_split", ctypes.c_int),
+                ("compile", ctypes.c_int)]
 
 
 class sv_plan_info(ctypes.Structure):
     _fields_ = [("n_ops", ctypes.c_uint64), ("n_launches", ctypes.c_uint64), ("n_tile_passes", ctypes.c_uint64),
                 ("n_stages", ctypes.c_uint64), ("bytes_moved", ctypes.c_uint64), ("tile_pass_bytes", ctypes.c_uint64),
                 ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int), ("n_dense_passes", ctypes.c_uint64),
-                ("n_dense_ops", ctypes.c_uint64), ("n_split_ops", ctypes.c_uint64)]
+                ("n_dense_ops", ctypes.c_uint64), ("n_split_ops", ctypes.c_uint64),
+                ("n_compiled_kernels", ctypes.c_uint64)]
 
 
 _lib = None
@@ -107,8 +110,8 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0, tile_launch=0, plain_split=0):
-    return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split)
+def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0, tile_launch=0, plain_split=0, compile=0):
+    return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile)
 
 
 # ---- the C entry points under their own names -------------------------------
@@ -142,17 +145,17 @@ def _ops_params(ops, params):
 
 
 def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
-                     tile_launch=0, plain_split=0):
+                     tile_launch=0, plain_split=0, compile=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile)
     _check(load_library().sv_apply_circuit(state, ops.ctypes.data, len(ops), _dp(params), len(params),
                                            ctypes.byref(o)))
 
 
 def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
-                   tile_launch=0, plain_split=0):
+                   tile_launch=0, plain_split=0, compile=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile)
     out = ctypes.c_void_p()
     _check(load_library().sv_plan_create(n_qubits, dtype, ops.ctypes.data, len(ops), _dp(params), len(params),
                                          ctypes.byref(o), ctypes.byref(out)))
@@ -286,9 +289,9 @@ class State:
         except Exception:
             pass
 
-    def apply(self, circuit, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0):
+    def apply(self, circuit, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, compile=0):
         ops, params = circuit.arrays()
-        sv_apply_circuit(self.h, ops, params, mode, tile_qubits, reg_qubits)
+        sv_apply_circuit(self.h, ops, params, mode, tile_qubits, reg_qubits, compile=compile)
         return self
 
     def amplitudes(self):
@@ -302,9 +305,9 @@ class State:
 
 
 class Plan:
-    def __init__(self, n_qubits, dtype, circuit, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0):
+    def __init__(self, n_qubits, dtype, circuit, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, compile=0):
         ops, params = circuit.arrays()
-        self.h = sv_plan_create(n_qubits, dtype, ops, params, mode, tile_qubits, reg_qubits)
+        self.h = sv_plan_create(n_qubits, dtype, ops, params, mode, tile_qubits, reg_qubits, compile=compile)
 
     @property
     def info(self):

@@ -78,7 +78,10 @@ def test_c1_ladder_matches_oracle(form, dtype, mode):
         # value) and the complex64 LDS exchange, element by element
         assert f < 1e-6
         assert_c64_close(got, want, len(circ), what=f"C1 d=13 {form}")
-        assert abs(np.vdot(got, got).real - 1.0) < 1e-6
+        # at most about one unit of 2^-23 of norm change per gate; the lowered
+        # form's uncontrolled R_Y(t/2) ... R_Y(-t/2) pairs repeat the same
+        # rounded angles every call, so their drift adds up linearly
+        assert abs(np.vdot(got, got).real - 1.0) < len(circ) * 2.0 ** -23
 
 
 @pytest.mark.parametrize("boundary", ["periodic", "bounceback"])

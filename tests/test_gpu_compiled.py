@@ -1,0 +1,142 @@
+"""Compiled tile passes (sv_apply_opts.compile) on the GPU.
+
+A compiled plan runs every tile pass as a kernel generated for that pass
+(its op list written out as straight-line code) instead of the generic tile
+kernel that reads the op records at run time.  The plan, and the arithmetic of
+every op, are the same, so:
+* compiled and generic runs of the same plan give bit-identical states
+  (random circuits with every op kind, both precisions, register widths 4 and
+  5, tile sizes 10 to 13; the 22-qubit Carleman ladder with its gate runs and
+  projector phases; the first layers of the 28-qubit benchmark circuit);
+* both agree with the FP64 reference simulator to the usual bars
+  (complex128 1e-12; complex64 element-wise, 1e-5 of the largest amplitude
+  per 1,000 gates); permutation-only circuits are bit-exact;
+* automatic selection compiles plans of 21 qubits and more.
+"""
+import numpy as np
+import pytest
+
+from oracle import statevector as osv
+from paper_2606_12770_amd.circuits.ir import Circuit
+from paper_2606_12770_amd.circuits.random_circuit import random_layered_circuit, random_mixed_circuit, random_state
+from tests.gpu_util import assert_c64_close, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def run(sv, circ, psi0, dtype, compile_mode, b=0, rb=0):
+    ops, params = circ.arrays()
+    plan = sv.sv_plan_create(circ.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile_mode)
+    info = sv.sv_plan_get_info(plan)
+    st = sv.State(circ.n, dtype, psi0)
+    sv.sv_plan_execute(plan, st.h, 1)
+    out = st.amplitudes()
+    st.close()
+    sv.sv_plan_free(plan)
+    return out, info
+
+
+@pytest.mark.parametrize("n,b,rb", [(10, 10, 4), (13, 12, 4), (14, 12, 5), (16, 13, 5), (17, 11, 4), (19, 12, 4)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_compiled_equals_generic_and_oracle(n, b, rb, dtype):
+    sv = require_gpu()
+    if dtype == 1 and b == 13:
+        b = 12
+    c = random_mixed_circuit(n, 400, seed=7 * n + b + rb + dtype, max_ctrl=6)
+    psi0 = random_state(n, n + dtype)
+    want = osv.run(c, psi0)
+    got, info = run(sv, c, psi0, dtype, sv.SV_COMPILE_ON, b, rb)
+    gen, info_g = run(sv, c, psi0, dtype, sv.SV_COMPILE_OFF, b, rb)
+    print(f"n={n} b={b} rb={rb} dtype={dtype}: {info['n_tile_passes']} passes, {info['n_compiled_kernels']} "
+          f"compiled kernels, max |compiled - generic| {np.max(np.abs(got - gen)):.1e}", flush=True)
+    assert info["n_compiled_kernels"] > 0 and info_g["n_compiled_kernels"] == 0
+    assert np.array_equal(got.view(np.uint64), gen.view(np.uint64))
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what=f"compiled n={n}")
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_compiled_permutations_bit_exact(dtype):
+    sv = require_gpu()
+    n = 16
+    rng = np.random.default_rng(11)
+    c = Circuit(n)
+    for _ in range(200):
+        k = int(rng.integers(0, 4))
+        qs = [int(v) for v in rng.permutation(n)]
+        ctrl = {q: int(rng.integers(0, 2)) for q in qs[2:2 + int(rng.integers(0, 4))]}
+        if k == 0:
+            c.x(qs[0], ctrl)
+        elif k == 1:
+            c.swap(qs[0], qs[1], ctrl)
+        else:
+            w = int(rng.integers(1, 9))
+            base = int(rng.integers(0, n - w + 1))
+            ctrl = {q: v for q, v in ctrl.items() if not base <= q < base + w}
+            (c.inc if k == 2 else c.dec)(base, w, ctrl)
+    psi0 = random_state(n, 12)
+    if dtype == 0:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = osv.run(c, psi0)
+    got, info = run(sv, c, psi0, dtype, sv.SV_COMPILE_ON)
+    assert info["n_compiled_kernels"] > 0
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_compiled_carleman_ladder_22q(dtype):
+    """The C1 ladder at d = 13 (22 qubits): value-encoding gate runs become
+    switches on the tile value, projector phases with the signal qubit on
+    every kind of bit; automatic selection compiles it."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    from paper_2606_12770_amd.circuits import qsp
+    sv = require_gpu()
+    cfg = cc.CarlemanConfig(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05)
+    enc = cc.build_ul(cfg)
+    circ = cc.build_qsvt(enc, qsp.inversion_phases(1.2, 13)[0])
+    psi0 = np.zeros(1 << circ.n, dtype=np.complex128)
+    psi0[: 1 << enc.layout.n_x] = cc.rhs_x_block(cfg, enc.layout)
+    want = osv.run(circ, psi0)
+    got, info = run(sv, circ, psi0, dtype, sv.SV_COMPILE_AUTO)
+    gen, _ = run(sv, circ, psi0, dtype, sv.SV_COMPILE_OFF)
+    print(f"C1 ladder dtype={dtype}: {info['n_tile_passes']} passes, {info['n_compiled_kernels']} compiled kernels",
+          flush=True)
+    assert info["n_compiled_kernels"] > 0
+    assert info["n_compiled_kernels"] < info["n_tile_passes"]
+    assert np.array_equal(got.view(np.uint64), gen.view(np.uint64))
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(circ), what="compiled C1 ladder")
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_compiled_benchmark_prefix_28q(dtype):
+    """Two layers of the 28-qubit benchmark circuit, the benchmark's launch
+    configuration: compiled equals generic bit for bit, and both the oracle."""
+    sv = require_gpu()
+    c = random_layered_circuit(28, 2, seed=0)
+    want = osv.run(c)
+    got, info = run(sv, c, osv.zero_state(28), dtype, sv.SV_COMPILE_AUTO)
+    gen, _ = run(sv, c, osv.zero_state(28), dtype, sv.SV_COMPILE_OFF)
+    assert info["n_compiled_kernels"] > 0
+    assert np.array_equal(got.view(np.uint64), gen.view(np.uint64))
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what="compiled 28q prefix")
+
+
+def test_compile_requests_outside_its_scope_are_refused():
+    sv = require_gpu()
+    c = random_mixed_circuit(14, 50, seed=1)
+    ops, params = c.arrays()
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_create(14, 0, ops, params, sv.SV_MODE_FUSED, tile_launch=sv.SV_TILE_LAUNCH_PERSISTENT,
+                          compile=sv.SV_COMPILE_ON)
+    assert e.value.code == sv.SV_EUNSUPPORTED
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_create(14, 0, ops, params, sv.SV_MODE_FUSED, compile=7)
+    assert e.value.code == sv.SV_EINVAL

@@ -1,0 +1,71 @@
+"""Specialised tile-pass sources, checked on the host.
+
+The planner's passes for circuits that reach every op kind (controlled
+single-qubit matrices, real rotations, X on register and thread bits, phases,
+projector phases with the signal on tile, register or thread bits,
+increments, decrements, swaps and X flips on exchanges), both precisions,
+register widths 4 and 5, tile sizes 10 to 13, gate runs of the Carleman
+value encodings (from 21 qubits) and the benchmark circuit at 28 qubits are
+turned into kernel sources and compiled for gfx950 with hiprtc.  No device
+is needed; running them is the GPU tests' job (tests/test_gpu_compiled.py).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2606_12770_amd.circuits.random_circuit import random_layered_circuit, random_mixed_circuit
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2606_12770_amd", "csrc")
+OUT = os.path.join(ROOT, "_build", "libjit_check.so")
+
+
+@pytest.fixture(scope="module")
+def jit():
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", OUT,
+                           os.path.join(CSRC, "planner.cpp"), os.path.join(CSRC, "tile_codegen.cpp"),
+                           os.path.join(ROOT, "tests", "csrc", "jit_check.cpp"),
+                           "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
+    L = ctypes.CDLL(OUT)
+    L.jit_check.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
+                            ctypes.c_char_p]
+    L.jit_check.restype = ctypes.c_int
+    return L
+
+
+def compile_circuit(L, circ, dtype, b=12, rb=4):
+    ops, params = circ.arrays()
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    rc = L.jit_check(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     b, rb, None, None)
+    assert rc > 0, f"generated source did not compile (code {rc})"
+    return rc
+
+
+@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (15, 12, 5), (13, 10, 4), (16, 13, 5), (12, 11, 5)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_mixed_circuits_compile(jit, n, b, rb, dtype):
+    if dtype == 1 and b == 13:
+        b = 12
+    compile_circuit(jit, random_mixed_circuit(n, 250, seed=n + b + rb, max_ctrl=5), dtype, b, rb)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_carleman_ladder_with_gate_runs_compiles(jit, dtype):
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    cfg = cc.CarlemanConfig(nx=8, tau=1.0, nk=2, nt=2, dt=0.1, amp=0.05)
+    enc = cc.build_ul(cfg)
+    circ = cc.build_qsvt(enc, np.random.default_rng(3).uniform(-np.pi, np.pi, 4))
+    k = compile_circuit(jit, circ, dtype)
+    # the ladder repeats U_L and U_L^dagger: far fewer distinct kernels than passes
+    assert k < 60
+
+
+def test_benchmark_circuit_compiles(jit):
+    compile_circuit(jit, random_layered_circuit(28, 3, seed=0), 0)
