@@ -8,10 +8,13 @@ once to a state resident in HBM.
 value      : gates/s of the fused complex64 path (FP32 arithmetic), warmup W
              steps untimed, then K steps timed with HIP events.
 extra      : fused complex128, the plain per-gate FP64 path (one launch per
-             gate, complex128), the infidelity of the fused complex64 result
-             against the plain complex128 result (both on the GPU, FP64 inner
-             product), roofline of the dominant kernel (the fused tile pass)
-             and the FP64 CPU reference simulator on a bounded prefix.
+             gate, complex128), the generic tile kernel on the same plan, the
+             infidelity of the fused complex64 result against the plain
+             complex128 result (both on the GPU, FP64 inner product), roofline
+             of the dominant kernel (the compiled tile passes), the Carleman
+             workloads, and in the CPU-baseline leg the FP64 reference
+             simulator on a bounded prefix and the Carleman runs against the
+             oracle's singular-value transform.
 """
 from __future__ import annotations
 
@@ -69,22 +72,44 @@ def host_cpu_model():
     return None
 
 
-def measured_traffic(kernel_name, qubits):
+def measured_traffic(kernel_name, qubits, source):
     """HBM bytes per launch of `kernel_name` from the committed rocprofv3 counter
     summary (profiles/tile_pass_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by
     the same counters on the copy kernel), or None when the summary is missing,
-    was taken at another size, or the kernel source has changed since."""
+    was taken at another size, or the kernel's source file (under
+    paper_2606_12770_amd/csrc) has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tile_pass_traffic.json")
-    src = os.path.join(ROOT, "paper_2606_12770_amd", "csrc", "kernels_tile.hip")
+    src = os.path.join(ROOT, "paper_2606_12770_amd", "csrc", source)
     try:
         rec = json.load(open(path))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel") != kernel_name or rec.get("qubits") != qubits or rec.get("kernels_tile_sha256") != digest:
+    if (rec.get("kernel") != kernel_name or rec.get("qubits") != qubits or rec.get("source") != source
+            or rec.get("source_sha256") != digest):
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+# System amplitudes of the Carleman runs, compared with the oracle in the
+# CPU-baseline leg (the only part of this script that runs the oracle).
+ORACLE_CHECKS = []
+
+
+def oracle_checks(checks):
+    """Infidelity and largest amplitude error (relative to the largest
+    amplitude) of each recorded run's system amplitudes (ancillas and signal at
+    0) against the oracle's singular-value transform of the same phases."""
+    import numpy as np
+    from tests.carleman_ref import ladder_reference
+    for chk in checks:
+        want, idx = ladder_reference(chk["cfg"], chk["layout"], chk["lam"], chk["phases"])
+        got = chk["sys"][idx]
+        f = 1.0 - abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)
+        err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        chk["out"].setdefault("vs_oracle", {})[chk["name"]] = {"infidelity": float(f), "rel_max_err": err}
+        log(f"oracle check {chk['name']}: infidelity {f:.2e}, rel max err {err:.2e}")
 
 
 def copy_bandwidth(sv, n, reps=10):
@@ -122,9 +147,13 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
         st = sv.sv_alloc(circ.n, dtype)
         sv.sv_set_amplitudes(st, rhs, 0)
         sv.sv_plan_execute(plan, st, 1)
+        if mode == sv.SV_MODE_FUSED and not elementary:
+            ORACLE_CHECKS.append({"out": out, "name": name, "cfg": cfg, "layout": enc.layout, "lam": enc.lam,
+                                  "phases": phases, "sys": sv.sv_amplitudes(st, 0, 1 << enc.layout.n_sys)})
         ms = sv.sv_plan_time(plan, st, reps) / reps
         out[name] = {"gates": len(ops), "gates_per_s": len(ops) / (ms / 1e3), "ms": ms,
                      "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
+                     "compiled_kernels": info["n_compiled_kernels"],
                      "GBps_algorithmic": info["bytes_moved"] / (ms / 1e3) / 1e9}
         log(f"carleman {enc.layout.n}q {name}: {out[name]['gates_per_s']:.0f} gates/s, {ms:.2f} ms, "
             f"{info['n_launches']} launches")
@@ -165,6 +194,17 @@ def batched_carleman(sv, count=64, d=3, reps=3):
     ms_seq = 0.0
     for p, st in zip(plans, states):
         ms_seq += sv.sv_plan_time(p, st, reps) / reps
+    for st in states:
+        sv.sv_free(st)
+    # one batched application from b on fresh states, every instance read back
+    # for the oracle
+    states = sv.sv_alloc_batch([c.n for c in circs], sv.SV_C64)
+    for st, cfg, e in zip(states, cfgs, encs):
+        sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
+    check = sv.sv_batch_create(states, plans, True, 0)
+    sv.sv_batch_execute(check, 1)
+    sv.sv_batch_free(check)
+    systems = [sv.sv_amplitudes(st, 0, 1 << e.layout.n_sys) for st, e in zip(states, encs)]
     for p in plans:
         sv.sv_plan_free(p)
     for st in states:
@@ -177,6 +217,9 @@ def batched_carleman(sv, count=64, d=3, reps=3):
            "batched_ms": ms_batch, "batched_gates_per_s": gates / (ms_batch / 1e3),
            "one_at_a_time_ms": ms_seq, "one_at_a_time_gates_per_s": gates / (ms_seq / 1e3),
            "speedup": ms_seq / ms_batch}
+    for i, (cfg, e, sysamp) in enumerate(zip(cfgs, encs, systems)):
+        ORACLE_CHECKS.append({"out": out, "name": f"instance_{i}", "cfg": cfg, "layout": e.layout, "lam": e.lam,
+                              "phases": phases, "sys": sysamp})
     log(f"batch: {out['batched_gates_per_s']:.0f} gates/s batched vs {out['one_at_a_time_gates_per_s']:.0f} "
         f"one at a time ({out['speedup']:.2f}x), {levels} launches in {groups} groups, geometry {b}/{rb}; "
         f"single level-synchronous group {ms_one_group:.1f} ms")
@@ -208,17 +251,21 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     return out
 
 
-def largest_state(sv, d=1, reps=1):
-    """N_x = 256, N_K = 4, N_t = 4 (tau 0.8, A 0.08, u0 0.02): the QSVT ladder at
-    degree d on 34 qubits in complex64 (128 GiB); FP64 norm drift and the
-    post-selection probability of the final-time rows."""
+def largest_state(sv, d=101, kappa_q=10.0, reps=1):
+    """N_x = 256, N_K = 4, N_t = 4 (tau 0.8, A 0.08, u0 0.02): the QSVT ladder on
+    34 qubits in complex64 (128 GiB) from b; FP64 norm drift, the probability
+    of the ancilla-zero block and of its final-time rows.  The final-time rows
+    lie 20 chain steps from b (N_t steps of N_K + 1), so they fill only at
+    degrees above 20: d = 101 with the inversion polynomial for kappa_QSVT = 10
+    (the instance's own kappa is about 1,100, whose working degree would take
+    about 45 minutes here)."""
     from paper_2606_12770_amd.circuits import carleman_circuit as cc, qsp
     cfg = cc.CarlemanConfig(nx=256, tau=0.8, nk=4, nt=4, dt=0.1, amp=0.08, u0=0.02)
     enc = cc.build_ul(cfg)
     L = enc.layout
     import numpy as np
     # d = 1: zero phases give Re p(x) = T_1(x) = x, one call of U_L^dagger
-    phases = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)[0] if d > 1 else np.zeros(2)
+    phases = qsp.inversion_phases(kappa_q, d)[0] if d > 1 else np.zeros(2)
     circ = cc.build_qsvt(enc, phases)
     ops, params = circ.arrays()
     plan = sv.sv_plan_create(L.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, tile_launch=TILE_LAUNCH)
@@ -227,9 +274,7 @@ def largest_state(sv, d=1, reps=1):
     sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)
     ms = sv.sv_plan_time(plan, st, reps) / reps
     norm2 = sv.sv_postselect(st, 0, 0, keep=False, renormalize=False)
-    # ancillas and signal 0 (the block-encoded result); the final-time rows are
-    # reached only at degrees of a few times N_t (N_K + 1), so at d = 1 their
-    # probability is exactly 0
+    # ancillas and signal 0 (the block-encoded result), and its final-time rows
     mask, val = cc.postselect_condition(L, final_time=False)
     P = sv.sv_postselect(st, mask, val, keep=False, renormalize=False)
     fmask, fval = cc.postselect_condition(L)
@@ -237,11 +282,12 @@ def largest_state(sv, d=1, reps=1):
     sv.sv_free(st)
     sv.sv_plan_free(plan)
     gb = info["bytes_moved"] / (ms / 1e3) / 1e9
-    out = {"qubits": L.n, "state_GiB": (8 << L.n) / 2 ** 30, "degree": d, "gates": len(circ), "ms": ms,
+    out = {"qubits": L.n, "state_GiB": (8 << L.n) / 2 ** 30, "degree": d, "kappa_qsvt": kappa_q,
+           "gates": len(circ), "ms": ms, "compiled_kernels": info["n_compiled_kernels"],
            "gates_per_s": len(circ) / (ms / 1e3), "launches": info["n_launches"], "GBps_algorithmic": gb,
            "norm_drift": abs(norm2 - 1.0), "postselect_prob_ancilla_zero": P, "postselect_prob_final_rows": P_final}
     log(f"largest {L.n}q: {out['gates_per_s']:.0f} gates/s, {ms:.1f} ms, {gb:.0f} GB/s, norm drift "
-        f"{out['norm_drift']:.2e}, P {P:.3e}")
+        f"{out['norm_drift']:.2e}, P {P:.3e}, P_final {P_final:.3e}")
     return out
 
 
@@ -390,15 +436,26 @@ def main():
     log(f"circuit: {n} qubits, {args.layers} layers, {n_gates} gates")
 
     # ---- fused complex64 (the headline) ----
+    t0 = time.time()
     plan64 = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits,
                                tile_launch=TILE_LAUNCH)
+    plan_s = time.time() - t0
     info64 = sv.sv_plan_get_info(plan64)
-    log(f"fused c64 plan: {info64}")
+    log(f"fused c64 plan ({plan_s:.1f} s, compiling included): {info64}")
     st64 = sv.sv_alloc(n, sv.SV_C64)
     for _ in range(args.warmup):
         sv.sv_plan_execute(plan64, st64, 1)
     ms64 = sv.sv_plan_time(plan64, st64, args.steps)
     log(f"fused c64: {ms64 / args.steps:.2f} ms/step")
+
+    # the generic tile kernel (op records read at run time) on the same plan
+    plan_g = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, args.tile_qubits, args.reg_qubits,
+                               tile_launch=TILE_LAUNCH, compile=sv.SV_COMPILE_OFF)
+    sv.sv_plan_execute(plan_g, st64, 1)
+    g_steps = min(args.steps, 3)
+    ms_g = sv.sv_plan_time(plan_g, st64, g_steps) / g_steps
+    sv.sv_plan_free(plan_g)
+    log(f"fused c64, generic tile kernel: {ms_g:.2f} ms/step")
 
     # fresh single application for the parity figure
     sv.sv_free(st64)
@@ -454,9 +511,14 @@ def main():
     avg_launch_ms = ms_t / info_t["n_tile_passes"]
     log(f"tile passes only: {ms_t:.2f} ms/step, {info_t['n_tile_passes']} launches, {avg_launch_ms * 1e3:.1f} us each")
     achieved = info_t["tile_pass_bytes"] / (avg_launch_ms / 1e3) / 1e9
+    if info_t["n_compiled_kernels"]:
+        kname, ksrc = "compiled tile passes (tile_pass_*)", "tile_codegen.cpp"
+    else:
+        kname, ksrc = "k_tile_pass<float,4,false,true>", "kernels_tile.hip"
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_tile_pass<float,4,false,true>", n),
-            "kernel": "k_tile_pass<float,4,false,true>", "launches_per_step": info64["n_launches"],
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, n, ksrc),
+            "kernel": kname, "compiled_kernels": info_t["n_compiled_kernels"],
+            "launches_per_step": info64["n_launches"],
             "tile_pass_launches_per_step": info64["n_tile_passes"], "avg_launch_us": avg_launch_ms * 1e3,
             "timed_on": "the same circuit planned with tile passes only",
             "tile_only_ms_per_step": ms_t}
@@ -493,6 +555,14 @@ def main():
     if not args.skip_cpu:
         log("cpu baseline ...")
         cpu = cpu_baseline(circ, args.cpu_seconds)
+        if ORACLE_CHECKS:
+            log("oracle checks of the Carleman runs ...")
+            oracle_checks(ORACLE_CHECKS)
+            if carleman and "batched_64" in carleman and "vs_oracle" in carleman["batched_64"]:
+                res = carleman["batched_64"]["vs_oracle"].values()
+                carleman["batched_64"]["worst_vs_oracle"] = {
+                    "infidelity": max(r["infidelity"] for r in res), "rel_max_err": max(r["rel_max_err"] for r in res)}
+                del carleman["batched_64"]["vs_oracle"]
 
     out = {
         "metric": "gates/s + HBM GB/s per state pass (fused FP32 vs plain FP64, infidelity <=1e-6)",
@@ -514,6 +584,8 @@ def main():
         "infidelity_fused_c64_vs_plain_c128": infid,
         "fused_c128": {"gates_per_s": n_gates / (ms128 / 1e3), "ms_per_step": ms128,
                        "launches": info128["n_launches"]},
+        "fused_c64_generic_kernel": {"gates_per_s": n_gates / (ms_g / 1e3), "ms_per_step": ms_g},
+        "plan_s": plan_s,
         "plain_fp64": plain,
         "copy_GBps": copy_gbs,
         "carleman_qsvt": carleman,

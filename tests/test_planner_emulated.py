@@ -226,3 +226,4 @@ def test_complex64_hadamards_keep_the_norm(emu, mode):
         # without the pairing the rounded Hadamard loses this much per gate
         h32 = np.float32(1 / np.sqrt(2))
         assert 1.0 - 2 * float(h32) ** 2 > 3e-8
+
