@@ -243,6 +243,19 @@ int sv_postselect(sv_state *s, uint64_t mask, uint64_t value, int keep, int reno
  * range outside the state. */
 int sv_amplitudes(const sv_state *s, uint64_t offset, uint64_t count, double *out);
 
+/* sv_amplitudes_noalloc — sv_amplitudes for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): it calls no allocating routine and stages through a
+ * fixed device array of 262144 complex128 amplitudes (4 MiB), which each
+ * device holds from the library's set-up (the first sv_alloc or
+ * sv_plan_create on it) until the process ends.  Same arguments, layout and
+ * result as sv_amplitudes; count may be at most 262144 (a larger count, or a
+ * range outside the state, gives SV_EINVAL and copies nothing).  Every call on
+ * one device shares that array: calls that overlap in time on one device
+ * (from several host threads, or on several streams) race and must not be
+ * made. */
+int sv_amplitudes_noalloc(const sv_state *s, uint64_t offset, uint64_t count, double *out);
+
 /* sv_set_amplitudes — overwrites amplitudes [offset, offset+count) from the
  * caller's host interleaved complex128 values: the right-hand side b, f(0) in
  * the m = 0 block (Sec. II.D.5).  SV_EINVAL for a range outside the state. */

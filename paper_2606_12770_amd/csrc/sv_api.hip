@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <set>
@@ -65,16 +66,36 @@ int hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+// Staging buffer of sv_amplitudes_noalloc: a fixed device array, so that call
+// allocates nothing.  Each device holds its own copy until the process ends;
+// host code must use the per-device address from hipGetSymbolAddress, never
+// the array's name (on the host that name is only a stand-in).
+constexpr uint64_t kScratchAmps = 1ull << 18;  // complex128 amplitudes: 4 MiB
+__device__ __align__(256) double2 scratch[kScratchAmps];
+
+std::mutex g_setup_mu;
+std::map<int, void *> g_scratch;  // device -> address of `scratch` on it
+
 int ensure_device_setup(int dev)
 {
-    static std::mutex mu;
     static std::set<int> ready;
-    std::lock_guard<std::mutex> lk(mu);
+    std::lock_guard<std::mutex> lk(g_setup_mu);
     if (ready.count(dev)) return SV_OK;
     int rc = svi::tile_kernel_setup();
     if (rc != SV_OK) return fail(rc, "could not raise the LDS limit of the tile kernels");
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = ptr;
     ready.insert(dev);
     return SV_OK;
+}
+
+void *scratch_on(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_setup_mu);
+    auto it = g_scratch.find(dev);
+    return it == g_scratch.end() ? nullptr : it->second;
 }
 
 int validate_ops(int n, const sv_op *ops, size_t n_ops, const double *params, size_t n_params)
@@ -509,6 +530,23 @@ int sv_amplitudes(const sv_state *s, uint64_t offset, uint64_t count, double *ou
     }
     (void)hipFree(stage);
     return rc;
+}
+
+int sv_amplitudes_noalloc(const sv_state *s, uint64_t offset, uint64_t count, double *out)
+{
+    if (!s || (!out && count)) return fail(SV_EINVAL, "NULL argument");
+    const uint64_t dim = 1ull << s->n;
+    if (offset > dim || count > dim - offset) return fail(SV_EINVAL, "range outside the state");
+    if (count > kScratchAmps)
+        return fail(SV_EINVAL, "count exceeds the static staging buffer of sv_amplitudes_noalloc (262144 amplitudes)");
+    if (!count) return SV_OK;
+    void *stage = scratch_on(s->device);  // set when the state was allocated on its device
+    if (!stage) return fail(SV_EDEVICE, "the static staging buffer was not set up on the state's device");
+    int rc = svi::launch_to_c128(s->d_psi, s->dtype, stage, offset, count, s->stream);
+    if (rc != SV_OK) return fail(rc, "conversion launch failed");
+    HIP_TRY(hipMemcpyAsync(out, stage, count * 16, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SV_OK;
 }
 
 int sv_set_amplitudes(sv_state *s, uint64_t offset, uint64_t count, const double *in)

@@ -26,7 +26,7 @@ SV_COMPILE_AUTO, SV_COMPILE_OFF, SV_COMPILE_ON = 0, 1, 2
 EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
     "sv_plan_get_info", "sv_plan_execute", "sv_plan_execute_seq", "sv_plan_time", "sv_postselect",
-    "sv_amplitudes", "sv_set_amplitudes", "sv_copy", "sv_inner", "sv_strerror", "sv_last_error",
+    "sv_amplitudes", "sv_amplitudes_noalloc", "sv_set_amplitudes", "sv_copy", "sv_inner", "sv_strerror", "sv_last_error",
     "sv_alloc_batch", "sv_batch_create", "sv_batch_execute", "sv_batch_time", "sv_batch_levels", "sv_batch_free",
 ]
 
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "sv_plan_time": [vp, vp, ctypes.c_int, dp],
         "sv_postselect": [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp],
         "sv_amplitudes": [vp, ctypes.c_uint64, ctypes.c_uint64, dp],
+        "sv_amplitudes_noalloc": [vp, ctypes.c_uint64, ctypes.c_uint64, dp],
         "sv_set_amplitudes": [vp, ctypes.c_uint64, ctypes.c_uint64, dp],
         "sv_copy": [vp, vp],
         "sv_inner": [vp, vp, dp, dp],
@@ -201,6 +202,12 @@ def sv_amplitudes(state, offset: int = 0, count: int | None = None) -> np.ndarra
         count = (1 << n) - offset
     out = np.empty(count, dtype=np.complex128)
     _check(load_library().sv_amplitudes(state, offset, count, _dp(out)))
+    return out
+
+
+def sv_amplitudes_noalloc(state, offset: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.complex128)
+    _check(load_library().sv_amplitudes_noalloc(state, offset, count, _dp(out)))
     return out
 
 
