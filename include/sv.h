@@ -110,8 +110,8 @@ typedef struct {
                           creation (hiprtc, for the current device) into a kernel with
                           its op list written out, and runs as that kernel (same
                           arithmetic, bit-identical states; plan creation takes
-                          longer); SV_COMPILE_AUTO (0): ON for states of at least 21
-                          qubits with the grid launch form, OFF otherwise, and OFF if
+                          longer), in either launch form; SV_COMPILE_AUTO (0): ON for
+                          states of at least 21 qubits, OFF otherwise, and OFF if
                           compilation is unavailable                                  */
 } sv_apply_opts;
 

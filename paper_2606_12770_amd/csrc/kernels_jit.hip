@@ -23,8 +23,8 @@
 namespace svi {
 
 std::string jit_preamble(int dtype);
-std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base);
-std::string jit_kernel(const std::string &name, const std::string &body, int threads);
+std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base, bool persistent);
+std::string jit_kernel(const std::string &name, const std::string &body, int threads, bool persistent);
 
 namespace {
 
@@ -89,13 +89,14 @@ int jit_prepare(sv_plan *p, std::string &err)
     p->jit_prm.assign(np, 0);
     if (!np) return SV_OK;
     const int threads = 1 << (p->b - p->rb);
+    const bool persistent = p->tile_launch == SV_TILE_LAUNCH_PERSISTENT;
     // distinct bodies of this plan
     std::vector<std::string> bodies;
     std::unordered_map<std::string, uint32_t> index;
     std::vector<uint32_t> pass_body(np);
     for (size_t pi = 0; pi < np; ++pi) {
         uint32_t pb = 0;
-        std::string body = jit_pass_body(*p, (uint32_t)pi, &pb);
+        std::string body = jit_pass_body(*p, (uint32_t)pi, &pb, persistent);
         p->jit_prm[pi] = pb;
         auto it = index.find(body);
         if (it == index.end()) {
@@ -151,7 +152,8 @@ int jit_prepare(sv_plan *p, std::string &err)
                     }
                     std::string src = pre;
                     for (size_t j = u * per_unit; j < std::min(todo.size(), (u + 1) * per_unit); ++j)
-                        src += jit_kernel(names[todo[j]], bodies[todo[j]], threads);
+                        src += jit_kernel(names[todo[j]], bodies[todo[j]], threads,
+                                          bodies[todo[j]].compare(0, 13, "// persistent") == 0);
                     ok[u] = compile_unit(src, arch, code[u], errs[u]) ? 1 : 0;
                 }
             });
@@ -188,18 +190,39 @@ int jit_prepare(sv_plan *p, std::string &err)
     return SV_OK;
 }
 
-// Launch the specialised kernel of tile pass `pi` on `psi`.
+// Resident workgroups of a persistent compiled pass kernel on the whole device.
+static uint64_t resident_grid(hipFunction_t f, uint32_t block)
+{
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, (int)block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    (void)hipGetLastError();
+    return (uint64_t)cus * (uint64_t)per_cu;
+}
+
+// Launch the specialised kernel of tile pass `pi` on `psi`: one workgroup per
+// tile, or (persistent plans) the device's resident workgroups walking them.
 int launch_jit_pass(const sv_plan *p, uint32_t pi, void *psi, hipStream_t st)
 {
     const TilePass &P = p->passes[pi];
     const uint64_t tiles = 1ull << P.ntile;
-    const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
-    const uint32_t gy = (uint32_t)(tiles / gx);
     const size_t es = p->dtype == SV_C64 ? sizeof(float) : sizeof(double);
     void *prm = (char *)p->d_tparams + (size_t)p->jit_prm[pi] * es;
-    void *args[] = {&psi, &prm};
-    hipError_t e = hipModuleLaunchKernel((hipFunction_t)p->jit_fn[pi], gx, gy, 1, 1u << P.nthr, 1, 1, 0, st, args,
-                                         nullptr);
+    hipFunction_t f = (hipFunction_t)p->jit_fn[pi];
+    const uint32_t block = 1u << P.nthr;
+    hipError_t e;
+    if (p->tile_launch == SV_TILE_LAUNCH_PERSISTENT) {
+        uint64_t n_tiles = tiles;
+        const uint64_t g = std::min<uint64_t>(tiles, resident_grid(f, block));
+        void *args[] = {&psi, &prm, &n_tiles};
+        e = hipModuleLaunchKernel(f, (uint32_t)g, 1, 1, block, 1, 1, 0, st, args, nullptr);
+    } else {
+        const uint32_t gx = tiles > 65536 ? 65536u : (uint32_t)tiles;
+        const uint32_t gy = (uint32_t)(tiles / gx);
+        void *args[] = {&psi, &prm};
+        e = hipModuleLaunchKernel(f, gx, gy, 1, block, 1, 1, 0, st, args, nullptr);
+    }
     return e == hipSuccess ? SV_OK : SV_EDEVICE;
 }
 

@@ -385,9 +385,8 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         return rc;
     }
     // specialised pass kernels: on request, or automatically for states of 21
-    // qubits and more launched as a grid (LDS of a pass up to 64 KiB)
-    const bool can = o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty() &&
-                     p->tile_launch == SV_TILE_LAUNCH_GRID && ((size_t)8 << p->b) <= 65536;
+    // qubits and more (LDS of a pass up to 64 KiB)
+    const bool can = o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty() && ((size_t)8 << p->b) <= 65536;
     const bool want = o.compile == SV_COMPILE_ON || (o.compile == SV_COMPILE_AUTO && n_qubits >= 21);
     if (can && want) {
         std::string jerr;
@@ -406,7 +405,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     } else if (o.compile == SV_COMPILE_ON && o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty()) {
         release_plan(p);
         delete p;
-        return fail(SV_EUNSUPPORTED, "compiled tile passes need the grid launch form and at most 64 KiB of LDS");
+        return fail(SV_EUNSUPPORTED, "compiled tile passes need at most 64 KiB of LDS per tile");
     }
     *out = p;
     return SV_OK;

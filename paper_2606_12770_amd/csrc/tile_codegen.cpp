@@ -271,32 +271,71 @@ struct Gen {
         }
     }
 
-    void body()
+    // absolute index bits of tile `t` (runs of the tile counter)
+    std::string base_expr(const char *t)
     {
-        const int b = P.b, nthr = P.nthr;
+        std::string e = "0ull";
+        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
+            const uint32_t sh = P.tile_shift[r];
+            e += " | ((" + std::string(t) + " >> " + std::to_string(sh & 0xffu) + ") & " + hex64(P.tile_mask[r]) +
+                 ") << " + std::to_string(sh >> 8);
+        }
+        return e;
+    }
+
+    void loads(const char *dst, const char *ptr)
+    {
+        for (int s = 0; s < NR; ++s)
+            o << " " << dst << "[" << s << "] = " << (P.stream ? "ldnt" : "ld") << "(" << ptr << " + "
+              << hex64(P.goff[s]) << ");\n";
+    }
+
+    // persistent: one resident set of workgroups walks the tiles (tile, tile +
+    // gridDim.x, ...) and issues the loads of its next tile before computing
+    // the current one; the tiles are disjoint, so a prefetch never reads what
+    // another workgroup writes, and the first LDS exchange of every tile starts
+    // with a barrier that orders it after the previous tile's LDS reads
+    void body(bool persistent)
+    {
+        const int b = P.b;
         o << " __shared__ " << (dbl ? "double" : "C") << " lds[" << (1u << b) << "];\n";
         o << " unsigned char *const lb = (unsigned char *)lds;\n";
         o << " const u32 tid = threadIdx.x;\n";
-        if (P.ntile > 16)
-            o << " const u64 tile = (u64)blockIdx.x + (u64)blockIdx.y * (u64)gridDim.x;\n";
-        else
-            o << " const u64 tile = (u64)blockIdx.x;\n";
-        o << " const u64 base = 0ull";
-        for (uint32_t r = 0; r < P.n_tile_runs; ++r) {
-            const uint32_t sh = P.tile_shift[r];
-            o << " | ((tile >> " << (sh & 0xffu) << ") & " << hex64(P.tile_mask[r]) << ") << " << (sh >> 8);
-        }
-        o << ";\n";
         o << " const u64 gthr = 0ull";
         for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
             const uint32_t sh = P.gthr_shift[r];
             o << " | ((u64)((tid >> " << (sh & 0xffu) << ") & " << hex32(P.gthr_mask[r]) << ") << " << (sh >> 8) << ")";
         }
         o << ";\n";
+        if (persistent) {
+            o << " u64 tile = (u64)blockIdx.x;\n";
+            o << " if (tile >= n_tiles) return;\n";
+            o << " u64 base_n = " << base_expr("tile") << ";\n";
+            o << " C xn[" << NR << "];\n";
+            o << " { C *const q = psi + (base_n | gthr);\n";
+            loads("xn", "q");
+            o << " }\n";
+            o << " for (;;) {\n";
+            o << " C x[" << NR << "];\n";
+            for (int s = 0; s < NR; ++s) o << " x[" << s << "] = xn[" << s << "];\n";
+            o << " const u64 base = base_n;\n";
+            o << " const u64 next = tile + (u64)gridDim.x;\n";
+            o << " if (next < n_tiles) {\n  base_n = " << base_expr("next") << ";\n";
+            o << "  C *const q = psi + (base_n | gthr);\n";
+            loads("xn", "q");
+            o << " }\n";
+        } else {
+            if (P.ntile > 16)
+                o << " const u64 tile = (u64)blockIdx.x + (u64)blockIdx.y * (u64)gridDim.x;\n";
+            else
+                o << " const u64 tile = (u64)blockIdx.x;\n";
+            o << " const u64 base = " << base_expr("tile") << ";\n";
+            o << " C x[" << NR << "];\n";
+            o << " { C *const q = psi + (base | gthr);\n";
+            loads("x", "q");
+            o << " }\n";
+        }
         o << " C *const pt = psi + (base | gthr);\n";
-        o << " C x[" << NR << "];\n";
-        for (int s = 0; s < NR; ++s)
-            o << " x[" << s << "] = " << (P.stream ? "ldnt" : "ld") << "(pt + " << hex64(P.goff[s]) << ");\n";
         o << " u32 thr = tid;\n";
         o << " u32 l[" << NR << "];\n (void)l;\n";
         for (uint32_t st = P.stage_begin; st < P.stage_end; ++st) {
@@ -322,6 +361,7 @@ struct Gen {
         }
         for (int s = 0; s < NR; ++s)
             o << " " << (P.stream ? "stnt" : "st") << "(pt + " << hex64(P.goff[s]) << ", x[" << s << "]);\n";
+        if (persistent) o << " if (next >= n_tiles) break;\n tile = next;\n }\n";
     }
 };
 
@@ -372,24 +412,26 @@ std::string jit_preamble(int dtype)
     return o.str();
 }
 
-// Kernel body (between the braces) of tile pass `pi`, and its parameter base.
-std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base)
+// Kernel body (between the braces) of tile pass `pi`, and its parameter base;
+// `persistent` selects the form that walks the tiles with a prefetch.
+std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base, bool persistent)
 {
     const TilePass &P = p.passes[pi];
     uint32_t lo = p.stages[P.stage_begin].op_begin;
     const uint32_t pb = lo * (uint32_t)kParamStride;
     Gen g(p, P, pb);
-    g.body();
+    g.body(persistent);
     if (param_base) *param_base = pb;
-    return g.o.str();
+    return (persistent ? "// persistent\n" : "") + g.o.str();
 }
 
-// Full kernel definition named `name` around a body of jit_pass_body.
-std::string jit_kernel(const std::string &name, const std::string &body, int threads)
+// Full kernel definition named `name` around a body of jit_pass_body; the
+// persistent form takes the tile count as a third argument.
+std::string jit_kernel(const std::string &name, const std::string &body, int threads, bool persistent)
 {
     std::ostringstream o;
     o << "extern \"C\" __global__ void __launch_bounds__(" << threads << ") " << name
-      << "(C *__restrict__ psi, const R *__restrict__ prm) {\n"
+      << "(C *__restrict__ psi, const R *__restrict__ prm" << (persistent ? ", const u64 n_tiles" : "") << ") {\n"
       << body << "}\n";
     return o.str();
 }

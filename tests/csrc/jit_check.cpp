@@ -14,14 +14,14 @@
 
 namespace svi {
 std::string jit_preamble(int dtype);
-std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base);
-std::string jit_kernel(const std::string &name, const std::string &body, int threads);
+std::string jit_pass_body(const sv_plan &p, uint32_t pi, uint32_t *param_base, bool persistent);
+std::string jit_kernel(const std::string &name, const std::string &body, int threads, bool persistent);
 }  // namespace svi
 
 using namespace svi;
 
 extern "C" int jit_check(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int tile_qubits,
-                         int reg_qubits, const char *src_out, const char *code_out)
+                         int reg_qubits, int persistent, const char *src_out, const char *code_out)
 {
     sv_plan p;
     p.n = n;
@@ -37,9 +37,9 @@ extern "C" int jit_check(int n, int dtype, const sv_op *ops, size_t n_ops, const
     int k = 0;
     for (uint32_t pi = 0; pi < p.passes.size(); ++pi) {
         uint32_t pb = 0;
-        const std::string body = jit_pass_body(p, pi, &pb);
+        const std::string body = jit_pass_body(p, pi, &pb, persistent != 0);
         if (!bodies.insert(body).second) continue;
-        src += jit_kernel("tile_pass_" + std::to_string(k++), body, 1 << (p.b - p.rb));
+        src += jit_kernel("tile_pass_" + std::to_string(k++), body, 1 << (p.b - p.rb), persistent != 0);
     }
     if (src_out) std::ofstream(src_out) << src;
     hiprtcProgram prog;

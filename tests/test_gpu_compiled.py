@@ -129,14 +129,39 @@ def test_compiled_benchmark_prefix_28q(dtype):
         assert_c64_close(got, want, len(c), what="compiled 28q prefix")
 
 
-def test_compile_requests_outside_its_scope_are_refused():
+@pytest.mark.parametrize("n,b,rb", [(12, 12, 4), (18, 12, 4), (20, 11, 5), (26, 12, 4)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_persistent_compiled_equals_grid_compiled(n, b, rb, dtype):
+    """The persistent compiled form (resident workgroups walking the tiles, the
+    next tile's loads in flight) gives the grid form's state bit for bit; at
+    26 qubits each workgroup handles several tiles."""
+    sv = require_gpu()
+    c = random_mixed_circuit(n, 300, seed=3 * n + rb + dtype, max_ctrl=6)
+    psi0 = random_state(n, 40 + n) if n <= 20 else osv.zero_state(n)
+    ops, params = c.arrays()
+    outs = []
+    for form in (sv.SV_TILE_LAUNCH_PERSISTENT, sv.SV_TILE_LAUNCH_GRID):
+        plan = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=form,
+                                 compile=sv.SV_COMPILE_ON)
+        assert sv.sv_plan_get_info(plan)["n_compiled_kernels"] > 0
+        st = sv.State(n, dtype, psi0)
+        sv.sv_plan_execute(plan, st.h, 1)
+        outs.append(st.amplitudes())
+        st.close()
+        sv.sv_plan_free(plan)
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    if n <= 20:
+        want = osv.run(c, psi0)
+        if dtype == 1:
+            assert np.max(np.abs(outs[0] - want)) < 1e-12
+        else:
+            assert_c64_close(outs[0], want, len(c), what=f"persistent compiled n={n}")
+
+
+def test_invalid_compile_mode_is_refused():
     sv = require_gpu()
     c = random_mixed_circuit(14, 50, seed=1)
     ops, params = c.arrays()
-    with pytest.raises(sv.SVError) as e:
-        sv.sv_plan_create(14, 0, ops, params, sv.SV_MODE_FUSED, tile_launch=sv.SV_TILE_LAUNCH_PERSISTENT,
-                          compile=sv.SV_COMPILE_ON)
-    assert e.value.code == sv.SV_EUNSUPPORTED
     with pytest.raises(sv.SVError) as e:
         sv.sv_plan_create(14, 0, ops, params, sv.SV_MODE_FUSED, compile=7)
     assert e.value.code == sv.SV_EINVAL

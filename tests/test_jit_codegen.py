@@ -33,17 +33,17 @@ def jit():
                            "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
     L = ctypes.CDLL(OUT)
     L.jit_check.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
-                            ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
-                            ctypes.c_char_p]
+                            ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_char_p, ctypes.c_char_p]
     L.jit_check.restype = ctypes.c_int
     return L
 
 
-def compile_circuit(L, circ, dtype, b=12, rb=4):
+def compile_circuit(L, circ, dtype, b=12, rb=4, persistent=0):
     ops, params = circ.arrays()
     params = np.ascontiguousarray(params, dtype=np.float64)
     rc = L.jit_check(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                     b, rb, None, None)
+                     b, rb, persistent, None, None)
     assert rc > 0, f"generated source did not compile (code {rc})"
     return rc
 
@@ -67,5 +67,11 @@ def test_carleman_ladder_with_gate_runs_compiles(jit, dtype):
     assert k < 60
 
 
-def test_benchmark_circuit_compiles(jit):
-    compile_circuit(jit, random_layered_circuit(28, 3, seed=0), 0)
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_benchmark_circuit_compiles(jit, persistent):
+    compile_circuit(jit, random_layered_circuit(28, 3, seed=0), 0, persistent=persistent)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_persistent_form_compiles(jit, dtype):
+    compile_circuit(jit, random_mixed_circuit(16, 250, seed=9, max_ctrl=5), dtype, 12, 4, persistent=1)
