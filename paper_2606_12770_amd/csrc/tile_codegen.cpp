@@ -122,7 +122,7 @@ struct Gen {
     void exchange(bool perms, const uint32_t *wswz, const uint32_t *rruns, uint32_t nrruns, const uint32_t *rswz,
                   bool to_load_mapping)
     {
-        o << "  __syncthreads();\n";
+        o << "  bar();\n";
         const std::string t2 = to_load_mapping ? std::string("tid") : thr_expr(rruns, nrruns);
         if (!dbl) {
             if (perms) {
@@ -133,7 +133,7 @@ struct Gen {
                     o << "    *(C *)(lb + (tw ^ " << hex32(wswz[s] * 8u) << ")) = x[" << s << "];\n";
                 o << "  }\n";
             }
-            o << "  __syncthreads();\n";
+            o << "  bar();\n";
             o << "  thr = " << t2 << ";\n";
             o << "  { const u32 tr = opq(swz(thr) * 8u);\n";
             for (int s = 0; s < NR; ++s)
@@ -153,14 +153,14 @@ struct Gen {
         }
         for (int half = 0; half < 2; ++half) {
             const char *f = half ? "y" : "x";
-            if (half) o << "    __syncthreads();\n";
+            if (half) o << "    bar();\n";
             for (int s = 0; s < NR; ++s) {
                 if (perms)
                     o << "    *(double *)(lb + wa[" << s << "]) = x[" << s << "]." << f << ";\n";
                 else
                     o << "    *(double *)(lb + (tw ^ " << hex32(wswz[s] * 8u) << ")) = x[" << s << "]." << f << ";\n";
             }
-            o << "    __syncthreads();\n";
+            o << "    bar();\n";
             for (int s = 0; s < NR; ++s)
                 o << "    x[" << s << "]." << f << " = *(const double *)(lb + (tr ^ " << hex32(rswz[s] * 8u) << "));\n";
         }
@@ -378,6 +378,15 @@ std::string jit_preamble(int dtype)
     // fused multiply-add in the amplitude precision (no promotion to double)
     o << "#define FMA " << (dbl ? "__builtin_fma" : "__builtin_fmaf") << "\n";
     o << "__device__ __forceinline__ u32 opq(u32 v) { asm volatile(\"\" : \"+v\"(v)); return v; }\n";
+    // Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+    // fences global memory, which makes every wave wait for its outstanding
+    // global loads at the barrier: in the persistent form those are the next
+    // tile's prefetch.  The tiles' global accesses are disjoint, so the LDS is
+    // all a barrier here has to order.
+    o << "__device__ __forceinline__ void bar() {\n"
+         "  __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"workgroup\", \"local\");\n"
+         "  __builtin_amdgcn_s_barrier();\n"
+         "  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\", \"local\");\n}\n";
     o << "__device__ __forceinline__ u32 swz(u32 l) {\n"
          "  const u32 h = (l >> 4) ^ (l >> 8) ^ (l >> 12) ^ (l >> 16);\n"
          "  return l ^ (h & 15u);\n}\n";
