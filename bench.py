@@ -164,65 +164,99 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
 
 def batched_carleman(sv, count=64, d=3, reps=3):
     """The batched workload: `count` seeded Carleman-LBM instances (21-28 qubits,
-    complex64) at QSVT degree d in one arena, geometry from the autotuner, one
-    graph-captured launch per level; against the same plans run one at a time."""
-    from paper_2606_12770_amd import autotune
+    complex64) at QSVT degree d.  Compiled plans run as one graph-captured
+    batch (instances on side streams forked from one stream) and one at a
+    time; the level-synchronous form of generic-kernel plans (one launch per
+    level over all instances' tiles) for reference; the instances below 24
+    qubits also as a batch of their own."""
     from paper_2606_12770_amd.circuits import batch_workload, carleman_circuit as cc, qsp
     cfgs = batch_workload.batch_configs(count)
     phases = qsp.inversion_phases(max(1.2, (d - 1) / 10.0), d)[0]
     encs = [cc.build_ul(cfg) for cfg in cfgs]
     circs = [cc.build_qsvt(e, phases) for e in encs]
-    states = sv.sv_alloc_batch([c.n for c in circs], sv.SV_C64)
-    (b, rb), tune_ms = autotune.tune_batch(circs, states, sv.SV_C64)
-    log(f"batch autotune: {tune_ms}")
+    qubits = [c.n for c in circs]
+    t0 = time.time()
     plans = []
     for c in circs:
         ops, params = c.arrays()
-        plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, b, rb,
-                                       plain_split=sv.SV_PLAIN_SPLIT_OFF))
-    for st, cfg, e in zip(states, cfgs, encs):
-        sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
-    batch = sv.sv_batch_create(states, plans, True, 0)
-    sv.sv_batch_execute(batch, 1)
-    ms_batch = sv.sv_batch_time(batch, reps) / reps
-    levels, groups, gates = sv.sv_batch_levels(batch)
-    sv.sv_batch_free(batch)
-    one = sv.sv_batch_create(states, plans, True, (1 << 64) - 1)   # all instances level by level
-    sv.sv_batch_execute(one, 1)
-    ms_one_group = sv.sv_batch_time(one, reps) / reps
-    sv.sv_batch_free(one)
-    ms_seq = 0.0
-    for p, st in zip(plans, states):
-        ms_seq += sv.sv_plan_time(p, st, reps) / reps
+        plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4,
+                                       compile=sv.SV_COMPILE_ON))
+    plan_s = time.time() - t0
+    kernels = sum(sv.sv_plan_get_info(p)["n_compiled_kernels"] for p in plans)
+    log(f"batch: 64 compiled plans in {plan_s:.1f} s ({kernels} kernels, shared across plans where equal)")
+    states = [sv.sv_alloc(c.n, sv.SV_C64) for c in circs]
+
+    def timed_batch(idx):
+        b = sv.sv_batch_create([states[i] for i in idx], [plans[i] for i in idx], True, 0)
+        sv.sv_batch_execute(b, 1)
+        ms = sv.sv_batch_time(b, reps) / reps
+        lv = sv.sv_batch_levels(b)
+        sv.sv_batch_free(b)
+        return ms, lv
+
+    def one_at_a_time(idx):
+        tot = 0.0
+        for i in idx:
+            sv.sv_plan_execute(plans[i], states[i], 1)
+            tot += sv.sv_plan_time(plans[i], states[i], reps) / reps
+        return tot
+
+    every = list(range(count))
+    small = [i for i in every if qubits[i] < 24]
+    ms_batch, (launches, streams, gates) = timed_batch(every)
+    ms_seq = one_at_a_time(every)
+    ms_small_batch, _ = timed_batch(small)
+    ms_small_seq = one_at_a_time(small)
+    gates_small = sum(len(circs[i]) for i in small)
+    # one batched application from b on fresh states, read back for the oracle
     for st in states:
         sv.sv_free(st)
-    # one batched application from b on fresh states, every instance read back
-    # for the oracle
-    states = sv.sv_alloc_batch([c.n for c in circs], sv.SV_C64)
+    states = [sv.sv_alloc(c.n, sv.SV_C64) for c in circs]
     for st, cfg, e in zip(states, cfgs, encs):
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
     check = sv.sv_batch_create(states, plans, True, 0)
     sv.sv_batch_execute(check, 1)
     sv.sv_batch_free(check)
     systems = [sv.sv_amplitudes(st, 0, 1 << e.layout.n_sys) for st, e in zip(states, encs)]
-    for p in plans:
-        sv.sv_plan_free(p)
     for st in states:
         sv.sv_free(st)
-    qubits = [c.n for c in circs]
+    for p in plans:
+        sv.sv_plan_free(p)
+
+    # level-synchronous form: generic-kernel plans (tile passes only) in one arena
+    arena = sv.sv_alloc_batch(qubits, sv.SV_C64)
+    gplans = []
+    for c in circs:
+        ops, params = c.arrays()
+        gplans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4,
+                                        plain_split=sv.SV_PLAIN_SPLIT_OFF, compile=sv.SV_COMPILE_OFF))
+    lb = sv.sv_batch_create(arena, gplans, True, 0)
+    sv.sv_batch_execute(lb, 1)
+    ms_level = sv.sv_batch_time(lb, reps) / reps
+    level_launches, level_groups, _ = sv.sv_batch_levels(lb)
+    sv.sv_batch_free(lb)
+    for p in gplans:
+        sv.sv_plan_free(p)
+    for st in arena:
+        sv.sv_free(st)
+
     out = {"instances": count, "degree": d, "qubits_min": min(qubits), "qubits_max": max(qubits),
-           "arena_GiB": sum(8 << q for q in qubits) / 2 ** 30, "gates": gates, "launches": levels,
-           "groups": groups, "single_group_ms": ms_one_group,
-           "tile_qubits": b, "reg_qubits": rb, "autotune_ms": {f"{k[0]}/{k[1]}": v for k, v in tune_ms.items()},
+           "state_GiB": sum(8 << q for q in qubits) / 2 ** 30, "gates": gates, "launches": launches,
+           "side_streams": streams, "plan_s": plan_s, "compiled_kernels": kernels, "tile_qubits": 12, "reg_qubits": 4,
            "batched_ms": ms_batch, "batched_gates_per_s": gates / (ms_batch / 1e3),
            "one_at_a_time_ms": ms_seq, "one_at_a_time_gates_per_s": gates / (ms_seq / 1e3),
-           "speedup": ms_seq / ms_batch}
+           "speedup": ms_seq / ms_batch,
+           "below_24_qubits": {"instances": len(small), "gates": gates_small, "batched_ms": ms_small_batch,
+                               "one_at_a_time_ms": ms_small_seq, "speedup": ms_small_seq / ms_small_batch},
+           "level_synchronous_generic": {"ms": ms_level, "launches": level_launches, "groups": level_groups,
+                                         "gates_per_s": gates / (ms_level / 1e3)}}
     for i, (cfg, e, sysamp) in enumerate(zip(cfgs, encs, systems)):
         ORACLE_CHECKS.append({"out": out, "name": f"instance_{i}", "cfg": cfg, "layout": e.layout, "lam": e.lam,
                               "phases": phases, "sys": sysamp})
     log(f"batch: {out['batched_gates_per_s']:.0f} gates/s batched vs {out['one_at_a_time_gates_per_s']:.0f} "
-        f"one at a time ({out['speedup']:.2f}x), {levels} launches in {groups} groups, geometry {b}/{rb}; "
-        f"single level-synchronous group {ms_one_group:.1f} ms")
+        f"one at a time ({out['speedup']:.2f}x); below 24 qubits {len(small)} instances "
+        f"{ms_small_batch:.1f} vs {ms_small_seq:.1f} ms ({out['below_24_qubits']['speedup']:.2f}x); "
+        f"level-synchronous generic form {ms_level:.1f} ms")
     return out
 
 
@@ -377,8 +411,9 @@ def first_order_scan(sv, dtypes=("c64", "c128")):
     from paper_2606_12770_amd import autotune
     for name in dtypes:
         dt = sv.SV_C64 if name == "c64" else sv.SV_C128
-        (b, rb), _tuned = autotune.tune_ladder(enc, dt)
-        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=TILE_LAUNCH)
+        (b, rb), _tuned = autotune.tune_ladder(enc, dt, compile=sv.SV_COMPILE_ON)
+        plan = sv.sv_plan_create(L.n, dt, ops, params, sv.SV_MODE_FUSED, b, rb, tile_launch=TILE_LAUNCH,
+                                 compile=sv.SV_COMPILE_ON)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(L.n, dt)
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, L), 0)

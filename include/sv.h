@@ -287,16 +287,24 @@ int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_s
 typedef struct sv_batch sv_batch;
 
 /* sv_batch_create — binds plans[i] (each the ladder or oracle of one instance
- * of Sec. II.D.5) to states[i] for i < count.  Every plan must be fused
- * (tile passes only), with one tile geometry and precision across the batch;
- * the states must be distinct and come from one sv_alloc_batch arena.
- * Instances, ordered by size, are packed into groups of at most group_bytes
- * of state (0: 192 MiB, about what the last-level cache holds; UINT64_MAX: one
- * group); a group runs level by level, each level one launch over the tiles of
- * all its instances.  use_graph != 0 captures all launches in a HIP graph on
- * first execution and replays it afterwards.  The batch keeps its own copy of
- * the plans' tables (the plans may be freed) and points into the arena: free
- * it before the states. */
+ * of Sec. II.D.5) to states[i] for i < count; the states must be distinct and
+ * on one device.  Two forms:
+ *  - compiled plans (sv_apply_opts.compile): every instance runs its own plan,
+ *    the instances spread over four side streams (largest first, each to the
+ *    least-loaded stream by modelled work) that fork from and join back to the
+ *    first state's stream, so small instances run alongside each other and the
+ *    large ones.  The batch holds the plans until sv_batch_free (sv_plan_free
+ *    may be called earlier); group_bytes is not used.
+ *  - otherwise: every plan must be fused (tile passes only), with one tile
+ *    geometry and precision across the batch, and the states must come from
+ *    one sv_alloc_batch arena.  Instances, ordered by size, are packed into
+ *    groups of at most group_bytes of state (0: 192 MiB, about what the
+ *    last-level cache holds; UINT64_MAX: one group); a group runs level by
+ *    level, each level one launch over the tiles of all its instances.  The
+ *    batch keeps its own copy of the plans' tables (the plans may be freed).
+ * use_graph != 0 captures one execution in a HIP graph on first execution and
+ * replays it afterwards.  The batch points into the states: free it before
+ * them. */
 int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
                     uint64_t group_bytes, sv_batch **out);
 

@@ -32,9 +32,9 @@ def _valid(n, b, rb):
     return b <= n and 6 <= b - rb <= 8
 
 
-def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1):
+def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1, compile=0):
     """Fastest (b, rb) for one circuit on one state; returns ((b, rb), {geometry: ms})."""
-    key = ("plan", circuit_digest([circuit]), circuit.n, dtype)
+    key = ("plan", circuit_digest([circuit]), circuit.n, dtype, compile)
     if key in _cache:
         return _cache[key]
     ops, params = circuit.arrays()
@@ -42,7 +42,7 @@ def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1):
     for b, rb in candidates:
         if not _valid(circuit.n, b, rb):
             continue
-        p = sv.sv_plan_create(circuit.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb)
+        p = sv.sv_plan_create(circuit.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile)
         try:
             sv.sv_plan_execute(p, state, 1)
             times[(b, rb)] = sv.sv_plan_time(p, state, repeat) / repeat
@@ -54,7 +54,8 @@ def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1):
 
 
 def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_graph=True):
-    """Fastest common (b, rb) for a batch; returns ((b, rb), {geometry: ms})."""
+    """Fastest common (b, rb) for a level-synchronous batch of generic-kernel
+    plans (states from one arena); returns ((b, rb), {geometry: ms})."""
     key = ("batch", circuit_digest(circuits), dtype)
     if key in _cache:
         return _cache[key]
@@ -64,7 +65,8 @@ def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_gra
     for b, rb in candidates:
         if not _valid(nmin, b, rb):
             continue
-        plans = [sv.sv_plan_create(c.n, dtype, o, p, sv.SV_MODE_FUSED, b, rb, plain_split=sv.SV_PLAIN_SPLIT_OFF)
+        plans = [sv.sv_plan_create(c.n, dtype, o, p, sv.SV_MODE_FUSED, b, rb, plain_split=sv.SV_PLAIN_SPLIT_OFF,
+                                   compile=sv.SV_COMPILE_OFF)
                  for c, (o, p) in zip(circuits, arrays)]
         batch = None
         try:
@@ -85,7 +87,7 @@ def tune_batch(circuits, states, dtype, candidates=CANDIDATES, repeat=1, use_gra
     return _cache[key]
 
 
-def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES):
+def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES, compile=0):
     """Fastest (b, rb) for a QSVT ladder of the block encoding `enc`, timed on a
     proxy ladder of `proxy_degree` calls (the pass structure repeats every two
     calls, so a short ladder ranks the geometries as the full one does) on a
@@ -94,7 +96,7 @@ def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES):
     from .circuits import carleman_circuit as cc
     n = enc.layout.n
     ops, params = cc.build_qsvt_arrays(enc, np.zeros(proxy_degree + 1))
-    key = ("ladder", hashlib.sha1(ops.tobytes()).hexdigest(), n, dtype)
+    key = ("ladder", hashlib.sha1(ops.tobytes()).hexdigest(), n, dtype, compile)
     if key in _cache:
         return _cache[key]
     state = sv.sv_alloc(n, dtype)
@@ -103,7 +105,7 @@ def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES):
         for b, rb in candidates:
             if not _valid(n, b, rb):
                 continue
-            p = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb)
+            p = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile)
             try:
                 sv.sv_plan_execute(p, state, 1)
                 times[(b, rb)] = sv.sv_plan_time(p, state, 1)

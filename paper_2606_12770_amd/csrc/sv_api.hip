@@ -28,6 +28,16 @@ struct Arena {
 }  // namespace svi
 
 struct sv_batch {
+    // concurrent form (compiled plans): instance i runs its own plan's launches
+    // on side stream stream_of[i]; the side streams fork from and join back to
+    // `stream`, so one execution is one graph with a branch per stream
+    bool concurrent = false;
+    std::vector<sv_plan *> plans;
+    std::vector<hipStream_t> side;
+    std::vector<uint32_t> stream_of;
+    std::vector<hipEvent_t> events;     // fork event, then one join event per side stream
+    uint64_t launches = 0;
+    // level-synchronous form
     svi::BatchTables tables{};
     std::vector<void *> d_tables;       // concatenated plan tables owned by the batch
     hipStream_t stream = nullptr;
@@ -218,16 +228,27 @@ void release_plan(sv_plan *p)
     p->d_passes = p->d_stages = p->d_tops = p->d_tparams = p->d_dense = p->d_dparams = nullptr;
 }
 
-int run_plan_once(const sv_plan *p, sv_state *s)
+int run_plan_on(const sv_plan *p, sv_state *s, hipStream_t stream)
 {
     for (const auto &st : p->steps) {
-        int rc = st.type == 0   ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, s->stream)
-                 : st.type == 1 ? (p->compiled ? svi::launch_jit_pass(p, st.index, s->d_psi, s->stream)
-                                               : svi::launch_tile_pass(p, st.index, s->d_psi, s->stream))
-                                : svi::launch_dense_pass(p, st.index, s->d_psi, s->stream);
+        int rc = st.type == 0   ? svi::launch_plain(p->plain[st.index], s->n, s->dtype, s->d_psi, stream)
+                 : st.type == 1 ? (p->compiled ? svi::launch_jit_pass(p, st.index, s->d_psi, stream)
+                                               : svi::launch_tile_pass(p, st.index, s->d_psi, stream))
+                                : svi::launch_dense_pass(p, st.index, s->d_psi, stream);
         if (rc != SV_OK) return fail(rc, "kernel launch failed");
     }
     return SV_OK;
+}
+
+int run_plan_once(const sv_plan *p, sv_state *s) { return run_plan_on(p, s, s->stream); }
+
+// A plan is released when its last holder lets go: the caller (sv_plan_free)
+// and every concurrent batch that runs it.
+void plan_release(sv_plan *p)
+{
+    if (--p->refs > 0) return;
+    release_plan(p);
+    delete p;
 }
 
 int check_plan_state(const sv_plan *p, const sv_state *s)
@@ -414,8 +435,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
 int sv_plan_free(sv_plan *p)
 {
     if (!p) return SV_OK;
-    release_plan(p);
-    delete p;
+    plan_release(p);
     return SV_OK;
 }
 
@@ -678,11 +698,99 @@ int sv_alloc_batch(int count, const int *n_qubits, int dtype, void *stream, sv_s
     return SV_OK;
 }
 
+namespace {
+// Concurrent form: instances assigned to side streams largest first, each to
+// the stream with the least modelled work so far (its plans' algorithmic
+// bytes plus a fixed cost per launch), so small instances overlap the large
+// ones and each other instead of running one after another.
+int batch_create_concurrent(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
+                            sv_batch **out)
+{
+    constexpr size_t kSideStreams = 4;  // the device's hardware queues per process
+    sv_batch *B = new (std::nothrow) sv_batch();
+    if (!B) return fail(SV_ENOMEM, "host allocation failed");
+    B->concurrent = true;
+    B->stream = states[0]->stream;
+    B->use_graph = use_graph != 0;
+    B->states.assign(states, states + count);
+    B->plans.assign(plans, plans + count);
+    const size_t k = std::min(count, kSideStreams);
+    auto cleanup = [&]() {
+        for (hipStream_t st : B->side) (void)hipStreamDestroy(st);
+        for (hipEvent_t e : B->events) (void)hipEventDestroy(e);
+        delete B;
+    };
+    for (size_t j = 0; j < k; ++j) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            cleanup();
+            return fail(SV_EDEVICE, "hipStreamCreateWithFlags failed");
+        }
+        B->side.push_back(st);
+    }
+    for (size_t j = 0; j <= k; ++j) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            cleanup();
+            return fail(SV_EDEVICE, "hipEventCreateWithFlags failed");
+        }
+        B->events.push_back(e);
+    }
+    std::vector<size_t> order(count);
+    for (size_t i = 0; i < count; ++i) order[i] = i;
+    auto cost = [&](size_t i) { return (double)plans[i]->info.bytes_moved / 4.0e6 + 8.0 * plans[i]->steps.size(); };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost(a) > cost(b); });
+    std::vector<double> load(k, 0.0);
+    B->stream_of.assign(count, 0);
+    for (size_t i : order) {
+        const size_t j = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->stream_of[i] = (uint32_t)j;
+        load[j] += cost(i);
+    }
+    for (size_t i = 0; i < count; ++i) {
+        B->gates += plans[i]->info.n_ops;
+        B->launches += plans[i]->steps.size();
+    }
+    for (size_t i = 0; i < count; ++i) plans[i]->refs += 1;  // released with the batch
+    B->groups = k;
+    *out = B;
+    return SV_OK;
+}
+
+int batch_launch_concurrent(sv_batch *B)
+{
+    HIP_TRY(hipEventRecord(B->events[0], B->stream));
+    for (hipStream_t st : B->side) HIP_TRY(hipStreamWaitEvent(st, B->events[0], 0));
+    // instances in submission order of each stream (largest first, as assigned)
+    for (size_t j = 0; j < B->side.size(); ++j)
+        for (size_t i = 0; i < B->plans.size(); ++i)
+            if (B->stream_of[i] == j) {
+                int rc = run_plan_on(B->plans[i], B->states[i], B->side[j]);
+                if (rc != SV_OK) return rc;
+            }
+    for (size_t j = 0; j < B->side.size(); ++j) {
+        HIP_TRY(hipEventRecord(B->events[j + 1], B->side[j]));
+        HIP_TRY(hipStreamWaitEvent(B->stream, B->events[j + 1], 0));
+    }
+    return SV_OK;
+}
+}  // namespace
+
 int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count, int use_graph,
                     uint64_t group_bytes, sv_batch **out)
 {
     if (!states || !plans || !out || count == 0) return fail(SV_EINVAL, "NULL argument or empty batch");
     *out = nullptr;
+    bool all_compiled = true;
+    for (size_t i = 0; i < count; ++i) {
+        int rc = check_plan_state(plans[i], states[i]);
+        if (rc != SV_OK) return rc;
+        all_compiled = all_compiled && plans[i]->compiled;
+        for (size_t j = 0; j < i; ++j)
+            if (states[j] == states[i]) return fail(SV_EINVAL, "a state appears twice in the batch");
+        if (states[i]->device != states[0]->device) return fail(SV_EINVAL, "batched states must share one device");
+    }
+    if (all_compiled) return batch_create_concurrent(states, plans, count, use_graph, out);
     const sv_plan *p0 = plans[0];
     svi::Arena *arena = states[0] ? states[0]->arena : nullptr;
     if (!arena) return fail(SV_EINVAL, "batched states must come from one sv_alloc_batch arena");
@@ -843,6 +951,7 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
 namespace {
 int batch_launch_all(sv_batch *B)
 {
+    if (B->concurrent) return batch_launch_concurrent(B);
     for (size_t lv = 0; lv < B->d_items.size(); ++lv) {
         int rc = svi::launch_tile_batch(B->tables, B->d_items[lv], B->n_items[lv], B->total[lv], B->gate_runs[lv] != 0,
                                         B->stream_state[lv] != 0, B->stream);
@@ -915,7 +1024,7 @@ int sv_batch_time(sv_batch *B, int repeat, double *ms)
 int sv_batch_levels(const sv_batch *B, uint64_t *launches, uint64_t *groups, uint64_t *gates)
 {
     if (!B) return fail(SV_EINVAL, "NULL batch");
-    if (launches) *launches = B->d_items.size();
+    if (launches) *launches = B->concurrent ? B->launches : B->d_items.size();
     if (groups) *groups = B->groups;
     if (gates) *gates = B->gates;
     return SV_OK;
@@ -929,6 +1038,12 @@ int sv_batch_free(sv_batch *B)
     if (B->graph) (void)hipGraphDestroy(B->graph);
     for (auto *d : B->d_items) (void)hipFree(d);
     for (void *d : B->d_tables) (void)hipFree(d);
+    for (hipStream_t st : B->side) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : B->events) (void)hipEventDestroy(e);
+    for (sv_plan *p : B->plans) plan_release(p);
     delete B;
     return SV_OK;
 }

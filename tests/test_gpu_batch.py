@@ -9,6 +9,10 @@
 * Graph replays, with the program's own eager work between them, match the
   eager result after every replay.
 * Invalid batches are refused on the host.
+* Compiled plans run in the concurrent form (instances on side streams that
+  fork from and join back to one stream, one graph): bit-identical to each
+  plan run alone, graph and eager alike, with plain launches among the steps,
+  states outside an arena, and plans freed before the batch runs.
 * The 64-instance batched workload itself (21-28 qubits, complex64, d = 3):
   every instance's system amplitudes against the oracle's singular-value
   transform of its own L, amplitude by amplitude.
@@ -26,12 +30,12 @@ from tests.gpu_util import assert_c64_close, require_gpu
 pytestmark = pytest.mark.gpu
 
 
-def _plans(sv, circs, dtype, b=12, rb=4):
+def _plans(sv, circs, dtype, b=12, rb=4, compile=0):
     out = []
     for c in circs:
         ops, params = c.arrays()
         out.append(sv.sv_plan_create(c.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb,
-                                      plain_split=sv.SV_PLAIN_SPLIT_OFF))
+                                      plain_split=sv.SV_PLAIN_SPLIT_OFF, compile=compile))
     return out
 
 
@@ -251,5 +255,41 @@ def test_batched_workload_matches_oracle():
     sv.sv_batch_free(batch)
     for p in plans:
         sv.sv_plan_free(p)
+    for st in states:
+        sv.sv_free(st)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_concurrent_batch_of_compiled_plans(dtype, use_graph):
+    sv = require_gpu()
+    circs, inits = _mixed_batch(10 + dtype)
+    # compiled plans with the automatic plain split (plain launches among the steps)
+    plans = []
+    for c in circs:
+        ops, params = c.arrays()
+        plans.append(sv.sv_plan_create(c.n, dtype, ops, params, sv.SV_MODE_FUSED, compile=sv.SV_COMPILE_ON))
+    refs = []
+    for c, v, p in zip(circs, inits, plans):
+        ref = sv.sv_alloc(c.n, dtype, v)
+        sv.sv_plan_execute(p, ref, 2)
+        refs.append(sv.sv_amplitudes(ref))
+        sv.sv_free(ref)
+    states = [sv.sv_alloc(c.n, dtype, v) for c, v in zip(circs, inits)]   # not an arena
+    batch = sv.sv_batch_create(states, plans, use_graph, 0)
+    launches, groups, gates = sv.sv_batch_levels(batch)
+    assert gates == sum(len(c) for c in circs)
+    assert launches == sum(sv.sv_plan_get_info(p)["n_launches"] for p in plans)
+    assert groups == 4
+    for p in plans:  # the batch holds the plans
+        sv.sv_plan_free(p)
+    sv.sv_batch_execute(batch, 1)
+    sv.sv_batch_execute(batch, 1)   # a replay when captured
+    for i, (c, st) in enumerate(zip(circs, states)):
+        got = sv.sv_amplitudes(st)
+        print(f"concurrent instance {i}: n={c.n} dtype={dtype} graph={use_graph} "
+              f"maxabs={np.max(np.abs(got - refs[i])):.1e}", flush=True)
+        assert np.array_equal(got.view(np.uint64), refs[i].view(np.uint64))
+    sv.sv_batch_free(batch)
     for st in states:
         sv.sv_free(st)
