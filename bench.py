@@ -263,21 +263,22 @@ def batched_carleman(sv, count=64, d=3, reps=3):
 def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     """Deep five-qubit runs: fused tile passes (VALU, gate by gate) against dense
     32 x 32 blocks on matrix cores (FP32 for complex64, FP64 for complex128),
-    same circuit and state size."""
+    chosen by the planner's cost model, same circuit and state size."""
     from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
     c = random_dense_block_circuit(n, blocks, depth, seed=7)
     ops, params = c.arrays()
     out = {"qubits": n, "gates": len(c), "blocks": blocks, "depth": depth}
     for dt, dname in ((sv.SV_C64, "complex64"), (sv.SV_C128, "complex128")):
         res = out if dt == sv.SV_C64 else out.setdefault(dname, {})
-        for name, dmin in (("tile_vALU", 0), ("dense_mfma", 16)):
+        for name, dmin in (("tile_vALU", 0), ("dense_mfma", sv.SV_DENSE_AUTO)):
             plan = sv.sv_plan_create(n, dt, ops, params, sv.SV_MODE_FUSED, 12, 4, dmin, tile_launch=TILE_LAUNCH)
             info = sv.sv_plan_get_info(plan)
             st = sv.sv_alloc(n, dt)
             sv.sv_plan_execute(plan, st, 1)
             ms = sv.sv_plan_time(plan, st, reps) / reps
             res[name] = {"gates_per_s": len(c) / (ms / 1e3), "ms": ms, "launches": info["n_launches"],
-                         "dense_passes": info["n_dense_passes"], "dense_ops": info["n_dense_ops"]}
+                         "dense_passes": info["n_dense_passes"], "dense_ops": info["n_dense_ops"],
+                         "dense_min_ops": info["dense_min_ops"]}
             log(f"dense-block circuit {dname} {name}: {res[name]['gates_per_s']:.0f} gates/s, {ms:.1f} ms, "
                 f"{info['n_launches']} launches ({info['n_dense_passes']} dense)")
             sv.sv_free(st)

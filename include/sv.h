@@ -93,7 +93,9 @@ typedef struct {
     int dense_min_ops; /* fused: a run of at least this many consecutive ops acting
                           inside 5 qubits (targets and controls) becomes one dense
                           32 x 32 block applied on matrix cores (FP32 for complex64,
-                          FP64 for complex128); 0 = never                              */
+                          FP64 for complex128); 0 = never; negative = the planner's
+                          cost model picks the length (one dense sweep of the state
+                          against the run's ops inside tile passes)               */
     int tile_launch;   /* fused: how tile passes are launched. SV_TILE_LAUNCH_AUTO (0),
                           SV_TILE_LAUNCH_GRID (1): one workgroup per tile,
                           SV_TILE_LAUNCH_PERSISTENT (2): one resident workgroup set that
@@ -142,6 +144,7 @@ typedef struct {
     uint64_t n_dense_ops;     /* IR ops absorbed into dense blocks                   */
     uint64_t n_split_ops;     /* fused: IR ops run as plain launches by the cost model */
     uint64_t n_compiled_kernels; /* compiled plans: distinct specialised pass kernels; 0 otherwise */
+    int      dense_min_ops;   /* fused: the run length that makes a dense block (0: none) */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

@@ -156,6 +156,10 @@ constexpr double kPlainFixedUs = 4.0, kPlainBytesPerUs = 4.0e6;
 // 0.3 ns per tile and op), and the amplitudes it applies to cost about 0.32 ps
 // each (the VALU work of a complex 2 x 2 gate in the fused kernel).
 constexpr double kOpPerTileUs = 0.31e-3, kOpPerAmpUs = 0.32e-6;
+// A dense 5-qubit block pass: a fixed cost per launch plus one sweep of the
+// state at the rate the matrix-core pass sustains (measured 4.7 TB/s complex64
+// and 4.9 TB/s complex128 on 28 qubits).
+constexpr double kDenseFixedUs = 8.0, kDenseBytesPerUs = 4.7e6;
 constexpr int kLookahead = 8;  // candidate resident-set widenings compared per step
 constexpr int kMinGateRun = 6;  // shortest run of ops with one tile mask worth a bisection
 double plain_us(const OpInfo &o, int n, int s)
@@ -432,11 +436,21 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     std::vector<int> dense_id(n_ops, -1);
     std::vector<std::pair<size_t, size_t>> runs;
     std::vector<uint64_t> run_support;
-    if (opts.dense_min_ops > 0 && n >= 12) {
+    // automatic (negative dense_min_ops): a run becomes a block when its ops
+    // inside tile passes (each read by every tile and applied to the
+    // amplitudes it touches) are modelled dearer than one dense pass
+    int dense_min = opts.dense_min_ops;
+    if (dense_min < 0) {
+        const double dense_us = kDenseFixedUs + (double)(2ull << n) * esize / kDenseBytesPerUs;
+        const double op_us = kOpPerTileUs * (double)(1ull << (n > b ? n - b : 0)) + kOpPerAmpUs * (double)(1ull << n);
+        dense_min = (int)std::min(1e6, std::ceil(dense_us / op_us));
+    }
+    p->info.dense_min_ops = dense_min;
+    if (dense_min > 0 && n >= 12) {
         size_t ws = 0;
         uint64_t S = 0;
         auto close = [&](size_t end) {
-            if (end - ws >= (size_t)opts.dense_min_ops && S) {
+            if (end - ws >= (size_t)dense_min && S) {
                 for (size_t k = ws; k < end; ++k) dense_id[k] = (int)runs.size();
                 runs.emplace_back(ws, end);
                 run_support.push_back(S);

@@ -375,7 +375,6 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     o.mode = SV_MODE_FUSED;
     if (opts) o = *opts;
     if (o.mode != SV_MODE_PLAIN && o.mode != SV_MODE_FUSED) return fail(SV_EINVAL, "unknown mode");
-    if (o.dense_min_ops < 0) return fail(SV_EINVAL, "dense_min_ops must be >= 0");
     if (o.tile_launch < SV_TILE_LAUNCH_AUTO || o.tile_launch > SV_TILE_LAUNCH_PERSISTENT)
         return fail(SV_EINVAL, "unknown tile_launch");
     if (o.plain_split != SV_PLAIN_SPLIT_AUTO && o.plain_split != SV_PLAIN_SPLIT_OFF)

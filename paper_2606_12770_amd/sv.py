@@ -22,6 +22,7 @@ SV_MODE_PLAIN, SV_MODE_FUSED = 0, 1
 SV_TILE_LAUNCH_AUTO, SV_TILE_LAUNCH_GRID, SV_TILE_LAUNCH_PERSISTENT = 0, 1, 2
 SV_PLAIN_SPLIT_AUTO, SV_PLAIN_SPLIT_OFF = 0, 1
 SV_COMPILE_AUTO, SV_COMPILE_OFF, SV_COMPILE_ON = 0, 1, 2
+SV_DENSE_AUTO = -1
 
 EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
@@ -48,7 +49,7 @@ class sv_plan_info(ctypes.Structure):
                 ("n_stages", ctypes.c_uint64), ("bytes_moved", ctypes.c_uint64), ("tile_pass_bytes", ctypes.c_uint64),
                 ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int), ("n_dense_passes", ctypes.c_uint64),
                 ("n_dense_ops", ctypes.c_uint64), ("n_split_ops", ctypes.c_uint64),
-                ("n_compiled_kernels", ctypes.c_uint64)]
+                ("n_compiled_kernels", ctypes.c_uint64), ("dense_min_ops", ctypes.c_int)]
 
 
 _lib = None

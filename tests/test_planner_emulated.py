@@ -227,3 +227,21 @@ def test_complex64_hadamards_keep_the_norm(emu, mode):
         h32 = np.float32(1 / np.sqrt(2))
         assert 1.0 - 2 * float(h32) ** 2 > 3e-8
 
+
+
+def test_dense_blocks_chosen_by_cost(emu):
+    """With a negative dense_min_ops the planner's cost model sets the run
+    length that makes a dense block: at 20 qubits the deep five-qubit runs of
+    the dense-block circuit qualify, the random layered circuit's short runs
+    do not; both plans still match the oracle."""
+    from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
+    n = 20
+    c = random_dense_block_circuit(n, 3, 12, 2)
+    psi0 = random_state(n, 5)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=-1)
+    assert np.max(np.abs(got - osv.run(c, psi0))) < 1e-12
+    assert stats[0] > stats[1]  # dense passes among the launches
+    layered = random_layered_circuit(n, 3, seed=2)
+    got, stats = run_emu(emu, layered, osv.zero_state(n), 1, 12, 4, 0, dense_min_ops=-1)
+    assert np.max(np.abs(got - osv.run(layered))) < 1e-12
+    assert stats[0] == stats[1] + stats[4]  # tile passes and split plain launches only
