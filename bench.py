@@ -268,21 +268,40 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     c = random_dense_block_circuit(n, blocks, depth, seed=7)
     ops, params = c.arrays()
     out = {"qubits": n, "gates": len(c), "blocks": blocks, "depth": depth}
-    for dt, dname in ((sv.SV_C64, "complex64"), (sv.SV_C128, "complex128")):
+    ref = None
+    results = {}
+    for dt, dname in ((sv.SV_C128, "complex128"), (sv.SV_C64, "complex64")):
         res = out if dt == sv.SV_C64 else out.setdefault(dname, {})
-        for name, dmin in (("tile_vALU", 0), ("dense_mfma", sv.SV_DENSE_AUTO)):
-            plan = sv.sv_plan_create(n, dt, ops, params, sv.SV_MODE_FUSED, 12, 4, dmin, tile_launch=TILE_LAUNCH)
+        variants = [("tile_vALU", 0, 0), ("dense_mfma", sv.SV_DENSE_AUTO, 0)]
+        if dt == sv.SV_C64:
+            variants.append(("dense_mfma_split_bf16", sv.SV_DENSE_AUTO, 1))
+        for name, dmin, bf16 in variants:
+            plan = sv.sv_plan_create(n, dt, ops, params, sv.SV_MODE_FUSED, 12, 4, dmin, tile_launch=TILE_LAUNCH,
+                                     dense_bf16=bf16)
             info = sv.sv_plan_get_info(plan)
             st = sv.sv_alloc(n, dt)
             sv.sv_plan_execute(plan, st, 1)
+            # infidelity of one application against the complex128 dense run (FP64 matrix cores)
+            if dt == sv.SV_C128 and name == "dense_mfma":
+                ref = st
+            elif ref is not None:
+                ip = sv.sv_inner(ref, st)
+                na = sv.sv_postselect(ref, 0, 0, keep=False, renormalize=False)
+                nb = sv.sv_postselect(st, 0, 0, keep=False, renormalize=False)
+                results[(dname, name)] = 1.0 - abs(ip) ** 2 / (na * nb)
             ms = sv.sv_plan_time(plan, st, reps) / reps
             res[name] = {"gates_per_s": len(c) / (ms / 1e3), "ms": ms, "launches": info["n_launches"],
                          "dense_passes": info["n_dense_passes"], "dense_ops": info["n_dense_ops"],
                          "dense_min_ops": info["dense_min_ops"]}
+            if (dname, name) in results:
+                res[name]["infidelity_vs_c128_dense"] = results[(dname, name)]
             log(f"dense-block circuit {dname} {name}: {res[name]['gates_per_s']:.0f} gates/s, {ms:.1f} ms, "
-                f"{info['n_launches']} launches ({info['n_dense_passes']} dense)")
-            sv.sv_free(st)
+                f"{info['n_launches']} launches ({info['n_dense_passes']} dense), "
+                f"infidelity vs complex128 {results.get((dname, name), 0.0):.2e}")
+            if st is not ref:
+                sv.sv_free(st)
             sv.sv_plan_free(plan)
+    sv.sv_free(ref)
     return out
 
 

@@ -115,6 +115,11 @@ typedef struct {
                           longer), in either launch form; SV_COMPILE_AUTO (0): ON for
                           states of at least 21 qubits, OFF otherwise, and OFF if
                           compilation is unavailable                                  */
+    int dense_bf16;    /* fused, complex64: 0 = dense blocks on FP32 matrix cores;
+                          1 = on BF16 matrix cores with split operands (each FP32
+                          value as a BF16 high part plus a BF16 low part, three
+                          products, FP32 accumulation: about 2^-16 relative
+                          error per block instead of 2^-24)                          */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0

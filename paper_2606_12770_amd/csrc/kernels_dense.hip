@@ -120,6 +120,117 @@ k_dense_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const f
     }
 }
 
+// Complex64 in split BF16: the same product on BF16 matrix cores with
+// v_mfma_f32_32x32x8bf16_1k (K = 8 per instruction, FP32 accumulation).  Each
+// FP32 value v is split into hi = bf16(v) and lo = bf16(v - hi), both rounded
+// to nearest even, and G X is taken as Gh Xh + Gh Xl + Gl Xh: the dropped
+// Gl Xl term and the rounding of the lo parts leave about 2^-16 of each
+// product, against 2^-24 on FP32 matrix cores, for 48 BF16 products per tile
+// and wave instead of 64 FP32 ones.  Operand layout of the instruction
+// (checked on the device with integer operands): lane l holds
+// A[l % 32][4 (l / 32) + j] and B[4 (l / 32) + j][l % 32], j = 0..3; result
+// register t of lane l is D[8 (t / 4) + 4 (l / 32) + t % 4][l % 32], as for
+// the FP32 instruction.  K chunk q (0..7) of the real product covers columns
+// 8 q .. 8 q + 7 of [G_re | -G_im] (rows of Y_re) and [G_im | G_re] (Y_im):
+// chunks 0-3 take X_re, 4-7 X_im, of the amplitudes 8 (q % 4) + 4 h + j.
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rn(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (amplitudes and gates are finite)
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+
+__global__ void __launch_bounds__(256)
+k_dense_pass_bf16(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats,
+                  uint64_t n_tiles)
+{
+    extern __shared__ unsigned char smem_raw[];
+    float2 *lds = reinterpret_cast<float2 *>(smem_raw);
+    const DensePass &D = *dp;
+    const TilePass &P = D.map;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t c = lane & 31u, h = lane >> 5;
+    const float *G = mats + D.mat;
+
+    // A operands, split: [part][chunk] of 4 values (columns 8 q + 4 h + j)
+    s4 ah[2][8], al[2][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t col = 8u * (uint32_t)(q & 3) + 4u * h + (uint32_t)j;  // block value of the column
+            const float gre = G[2 * (32 * c + col)], gim = G[2 * (32 * c + col) + 1];
+            const float v0 = q < 4 ? gre : -gim;  // [G_re | -G_im]
+            const float v1 = q < 4 ? gim : gre;   // [G_im | G_re]
+            ah[0][q][j] = bf16_rn(v0);
+            al[0][q][j] = bf16_rn(v0 - bf16_f(ah[0][q][j]));
+            ah[1][q][j] = bf16_rn(v1);
+            al[1][q][j] = bf16_rn(v1 - bf16_f(ah[1][q][j]));
+        }
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
+    const uint32_t g = wave * 32u + c;
+    uint32_t gl = 0;
+    for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+        const uint32_t w = D.grp_run[r];
+        gl |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+    }
+    const uint32_t tw = lds_swizzle(tid, 4);
+
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        float2 *const pt = psi + (dense_tile_base(P, tile) | gthr);
+        {
+            float2 x[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+        }
+        __syncthreads();
+        // B operands, split: the amplitudes 8 q + 4 h + j of this lane's group
+        s4 bh[8], bl[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 xv = lds[lds_swizzle(gl | D.joff[8 * q + 4 * h + j], 4)];
+                bh[q][j] = bf16_rn(xv.x);
+                bl[q][j] = bf16_rn(xv.x - bf16_f(bh[q][j]));
+                bh[q + 4][j] = bf16_rn(xv.y);
+                bl[q + 4][j] = bf16_rn(xv.y - bf16_f(bh[q + 4][j]));
+            }
+        v16f acc_re = {0.f}, acc_im = {0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[0][q], bh[q], acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[0][q], bl[q], acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[0][q], bh[q], acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[1][q], bh[q], acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[1][q], bl[q], acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[1][q], bh[q], acc_im, 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read its X before Y overwrites it
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            lds[lds_swizzle(gl | D.joff[8u * (t / 4) + 4u * h + (t % 4)], 4)] = make_float2(acc_re[t], acc_im[t]);
+        __syncthreads();
+        float2 y[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) y[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = y[s];
+        __syncthreads();  // the next tile overwrites the LDS
+    }
+}
+
 // Complex128: the same product on FP64 matrix cores, v_mfma_f64_16x16x4f64
 // (M = 16 block rows, N = 16 groups, K = 4 block values per instruction).
 // Operand layout of that instruction (checked on the device): lane l holds
@@ -232,7 +343,10 @@ int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const uint64_t cap = (uint64_t)cus * 2;  // resident workgroups per CU at these kernels' register and LDS use
     const uint32_t grid = (uint32_t)(tiles < cap ? tiles : cap);
-    if (p->dtype == SV_C64)
+    if (p->dtype == SV_C64 && p->dense_bf16)
+        hipLaunchKernelGGL(k_dense_pass_bf16, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                           (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
+    else if (p->dtype == SV_C64)
         hipLaunchKernelGGL(k_dense_pass, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
                            (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
     else

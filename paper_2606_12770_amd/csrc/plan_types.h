@@ -219,6 +219,7 @@ struct sv_plan {
     // specialised tile-pass kernels (compiled plans): function per pass and
     // the pass's first parameter (reals into the device parameter array)
     bool compiled = false;
+    bool dense_bf16 = false;          // complex64 dense blocks on BF16 matrix cores (split operands)
     int refs = 1;                     // the caller's handle, plus each concurrent batch that runs it
     std::vector<void *> jit_fn;
     std::vector<uint32_t> jit_prm;

@@ -381,6 +381,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         return fail(SV_EINVAL, "unknown plain_split");
     if (o.compile != SV_COMPILE_AUTO && o.compile != SV_COMPILE_OFF && o.compile != SV_COMPILE_ON)
         return fail(SV_EINVAL, "unknown compile");
+    if (o.dense_bf16 != 0 && o.dense_bf16 != 1) return fail(SV_EINVAL, "dense_bf16 must be 0 or 1");
     int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
     if (rc != SV_OK) return rc;
     int dev = 0;
@@ -392,6 +393,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     p->n = n_qubits;
     p->dtype = dtype;
     p->tile_launch = o.tile_launch == SV_TILE_LAUNCH_AUTO ? svi::kDefaultTileLaunch : o.tile_launch;
+    p->dense_bf16 = o.dense_bf16 == 1 && dtype == SV_C64;
     std::string err;
     rc = svi::build_plan(p, ops, n_ops, params, o, err);
     if (rc != SV_OK) {

@@ -41,3 +41,34 @@ def test_dense_blocks_match_oracle(n, blocks, depth, dtype):
         assert np.max(np.abs(got - want)) < 1e-5
     else:
         assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("n,blocks,depth", [(12, 3, 4), (16, 6, 5), (20, 8, 6), (23, 4, 8)])
+def test_split_bf16_dense_blocks_match_oracle(n, blocks, depth):
+    """Complex64 dense blocks on BF16 matrix cores with split operands (hi + lo
+    BF16 parts, three products, FP32 accumulation): infidelity within the
+    complex64 bar of 1e-6; every amplitude within 2^-14 of the largest per
+    block applied (the split leaves about 2^-16 of each block product)."""
+    sv = require_gpu()
+    c = random_dense_block_circuit(n, blocks, depth, seed=n)
+    psi0 = random_state(n, n + 1)
+    want = osv.run(c, psi0)
+    ops, params = c.arrays()
+    outs = {}
+    for bf16 in (0, 1):
+        plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4, 16, dense_bf16=bf16)
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(n, sv.SV_C64, psi0)
+        sv.sv_plan_execute(plan, st, 1)
+        outs[bf16] = sv.sv_amplitudes(st)
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+        assert info["n_dense_passes"] == blocks
+    got = outs[1]
+    f = infid(want, got)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    err32 = np.max(np.abs(outs[0] - want)) / np.max(np.abs(want))
+    print(f"split-BF16 dense n={n} blocks={blocks}: infidelity {f:.2e} (FP32 {infid(want, outs[0]):.2e}), "
+          f"rel max err {err:.2e} (FP32 {err32:.2e})", flush=True)
+    assert f < 1e-6
+    assert err < blocks * 2.0 ** -14
