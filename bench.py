@@ -162,6 +162,9 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
     return out
 
 
+BATCH_GRAPH = True   # capture batches in HIP graphs (--batch-eager: launch them eagerly)
+
+
 def batched_carleman(sv, count=64, d=3, reps=3):
     """The batched workload: `count` seeded Carleman-LBM instances (21-28 qubits,
     complex64) at QSVT degree d.  Compiled plans run as one graph-captured
@@ -187,7 +190,7 @@ def batched_carleman(sv, count=64, d=3, reps=3):
     states = [sv.sv_alloc(c.n, sv.SV_C64) for c in circs]
 
     def timed_batch(idx):
-        b = sv.sv_batch_create([states[i] for i in idx], [plans[i] for i in idx], True, 0)
+        b = sv.sv_batch_create([states[i] for i in idx], [plans[i] for i in idx], BATCH_GRAPH, 0)
         sv.sv_batch_execute(b, 1)
         ms = sv.sv_batch_time(b, reps) / reps
         lv = sv.sv_batch_levels(b)
@@ -214,7 +217,7 @@ def batched_carleman(sv, count=64, d=3, reps=3):
     states = [sv.sv_alloc(c.n, sv.SV_C64) for c in circs]
     for st, cfg, e in zip(states, cfgs, encs):
         sv.sv_set_amplitudes(st, cc.rhs_x_block(cfg, e.layout), 0)
-    check = sv.sv_batch_create(states, plans, True, 0)
+    check = sv.sv_batch_create(states, plans, BATCH_GRAPH, 0)
     sv.sv_batch_execute(check, 1)
     sv.sv_batch_free(check)
     systems = [sv.sv_amplitudes(st, 0, 1 << e.layout.n_sys) for st, e in zip(states, encs)]
@@ -230,7 +233,7 @@ def batched_carleman(sv, count=64, d=3, reps=3):
         ops, params = c.arrays()
         gplans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4,
                                         plain_split=sv.SV_PLAIN_SPLIT_OFF, compile=sv.SV_COMPILE_OFF))
-    lb = sv.sv_batch_create(arena, gplans, True, 0)
+    lb = sv.sv_batch_create(arena, gplans, BATCH_GRAPH, 0)
     sv.sv_batch_execute(lb, 1)
     ms_level = sv.sv_batch_time(lb, reps) / reps
     level_launches, level_groups, _ = sv.sv_batch_levels(lb)
@@ -469,13 +472,16 @@ def main():
     ap.add_argument("--skip-carleman", action="store_true")
     ap.add_argument("--tile-launch", choices=["auto", "grid", "persistent"], default="auto",
                     help="how fused tile passes are launched (sv_apply_opts.tile_launch)")
+    ap.add_argument("--batch-eager", action="store_true",
+                    help="launch batches eagerly instead of replaying a captured HIP graph (for kernel tracing)")
     ap.add_argument("--sections", default="small,grid64,batch,dense,largest",
                     help="comma list of the secondary workloads to run (empty: none); "
                          "'paper' adds the full-degree second-order run (about 2 minutes), "
                          "'first_order' the longest ladder of the first-order degree scan")
     args = ap.parse_args()
-    global TILE_LAUNCH
+    global TILE_LAUNCH, BATCH_GRAPH
     TILE_LAUNCH = {"auto": 0, "grid": 1, "persistent": 2}[args.tile_launch]
+    BATCH_GRAPH = not args.batch_eager
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the simulator runs on a "
               f"single MI355X and has no multi-GPU path)", file=sys.stderr)

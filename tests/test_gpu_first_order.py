@@ -2,7 +2,8 @@
 N_t = 32, N_K = 1, dt = 0.1, nu = 2, bounce-back walls, rho in [0.8, 1.2];
 19 qubits, lambda_L = 8, kappa about 800.  Six ladders: kappa_QSVT in
 {400, 1000} (under- and overshoot) times d / kappa_QSVT in {5, 10, 15}, run
-as fused complex128 plans.
+as fused complex128 plans with compiled tile passes (below the automatic
+threshold of 21 qubits, so requested).
 
 For every run the system amplitudes with the ancillas and the signal at 0 must
 equal the oracle's singular-value transform of the same phases (relative max
@@ -64,7 +65,7 @@ def test_first_order_degree_scan():
         coefs, c, _err = qsp.inverse_polynomial(kq, d)
         phases, _it, _r = qsp.solve_phases(coefs)
         ops, params = cc.build_qsvt_arrays(enc, phases)
-        plan = sv.sv_plan_create(L.n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED)
+        plan = sv.sv_plan_create(L.n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED, compile=sv.SV_COMPILE_ON)
         st = sv.State(L.n, sv.SV_C128)
         sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
         t0 = time.time()
@@ -122,7 +123,7 @@ def test_taylor_order_comparison():
         D = len(y0)
         r0 = (1 << L.n_m) * (1 << L.n_k) // 2 * D
         ops, params = cc.build_qsvt_arrays(enc, phases)
-        plan = sv.sv_plan_create(L.n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED)
+        plan = sv.sv_plan_create(L.n, sv.SV_C128, ops, params, sv.SV_MODE_FUSED, compile=sv.SV_COMPILE_ON)
         st = sv.State(L.n, sv.SV_C128)
         sv.sv_set_amplitudes(st.h, cc.rhs_x_block(cfg, L), 0)
         t0 = time.time()
