@@ -286,7 +286,8 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
             sv.sv_plan_execute(plan, st, 1)
             # infidelity of one application against the complex128 dense run (FP64 matrix cores)
             if dt == sv.SV_C128 and name == "dense_mfma":
-                ref = st
+                ref = sv.sv_alloc(n, dt)   # kept apart: the timing below applies the circuit again
+                sv.sv_copy(ref, st)
             elif ref is not None:
                 ip = sv.sv_inner(ref, st)
                 na = sv.sv_postselect(ref, 0, 0, keep=False, renormalize=False)
@@ -301,8 +302,7 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
             log(f"dense-block circuit {dname} {name}: {res[name]['gates_per_s']:.0f} gates/s, {ms:.1f} ms, "
                 f"{info['n_launches']} launches ({info['n_dense_passes']} dense), "
                 f"infidelity vs complex128 {results.get((dname, name), 0.0):.2e}")
-            if st is not ref:
-                sv.sv_free(st)
+            sv.sv_free(st)
             sv.sv_plan_free(plan)
     sv.sv_free(ref)
     return out
