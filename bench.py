@@ -265,8 +265,10 @@ def batched_carleman(sv, count=64, d=3, reps=3):
 
 def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
     """Deep five-qubit runs: fused tile passes (VALU, gate by gate) against dense
-    32 x 32 blocks on matrix cores (FP32 for complex64, FP64 for complex128),
-    chosen by the planner's cost model, same circuit and state size."""
+    32 x 32 blocks on matrix cores (FP32 or split BF16 for complex64, FP64 for
+    complex128), chosen by the planner's cost model, same circuit and state
+    size; then deep six-qubit runs as 64 x 64 complex64 blocks, FP32 against
+    split BF16."""
     from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
     c = random_dense_block_circuit(n, blocks, depth, seed=7)
     ops, params = c.arrays()
@@ -305,6 +307,42 @@ def dense_blocks(sv, n=28, blocks=24, depth=8, reps=2):
             sv.sv_free(st)
             sv.sv_plan_free(plan)
     sv.sv_free(ref)
+
+    # six-qubit runs: 64 x 64 blocks (complex64 only), FP32 against split BF16;
+    # reference: the complex128 run in tile passes
+    c6 = random_dense_block_circuit(n, blocks, depth, seed=8, width=6)
+    ops6, params6 = c6.arrays()
+    six = out.setdefault("six_qubit_blocks", {"gates": len(c6), "blocks": blocks, "depth": depth})
+    ref6 = None
+    for dt, name, dmin, bf16, dq in ((sv.SV_C128, "complex128_tile_vALU", 0, 0, 0),
+                                     (sv.SV_C64, "tile_vALU", 0, 0, 0),
+                                     (sv.SV_C64, "dense6_mfma", sv.SV_DENSE_AUTO, 0, 6),
+                                     (sv.SV_C64, "dense6_mfma_split_bf16", sv.SV_DENSE_AUTO, 1, 6)):
+        plan = sv.sv_plan_create(n, dt, ops6, params6, sv.SV_MODE_FUSED, 12, 4, dmin, tile_launch=TILE_LAUNCH,
+                                 dense_bf16=bf16, dense_qubits=dq)
+        info = sv.sv_plan_get_info(plan)
+        st = sv.sv_alloc(n, dt)
+        sv.sv_plan_execute(plan, st, 1)
+        f = 0.0
+        if ref6 is None:
+            ref6 = sv.sv_alloc(n, dt)
+            sv.sv_copy(ref6, st)
+        else:
+            ip = sv.sv_inner(ref6, st)
+            na = sv.sv_postselect(ref6, 0, 0, keep=False, renormalize=False)
+            nb = sv.sv_postselect(st, 0, 0, keep=False, renormalize=False)
+            f = 1.0 - abs(ip) ** 2 / (na * nb)
+        ms = sv.sv_plan_time(plan, st, reps) / reps
+        six[name] = {"gates_per_s": len(c6) / (ms / 1e3), "ms": ms, "launches": info["n_launches"],
+                     "dense_passes": info["n_dense_passes"], "dense_ops": info["n_dense_ops"],
+                     "dense_min_ops": info["dense_min_ops"]}
+        if dt == sv.SV_C64:
+            six[name]["infidelity_vs_c128"] = f
+        log(f"six-qubit block circuit {name}: {six[name]['gates_per_s']:.0f} gates/s, {ms:.1f} ms, "
+            f"{info['n_launches']} launches ({info['n_dense_passes']} dense), infidelity vs complex128 {f:.2e}")
+        sv.sv_free(st)
+        sv.sv_plan_free(plan)
+    sv.sv_free(ref6)
     return out
 
 

@@ -91,11 +91,11 @@ typedef struct {
     int tile_qubits;   /* fused: qubits resident per tile, 0 = automatic                   */
     int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic        */
     int dense_min_ops; /* fused: a run of at least this many consecutive ops acting
-                          inside 5 qubits (targets and controls) becomes one dense
-                          32 x 32 block applied on matrix cores (FP32 for complex64,
-                          FP64 for complex128); 0 = never; negative = the planner's
-                          cost model picks the length (one dense sweep of the state
-                          against the run's ops inside tile passes)               */
+                          inside dense_qubits qubits (targets and controls) becomes one
+                          dense block applied on matrix cores (FP32 or split BF16 for
+                          complex64, FP64 for complex128); 0 = never; negative = the
+                          planner's cost model picks the length (one dense sweep of the
+                          state against the run's ops inside tile passes)            */
     int tile_launch;   /* fused: how tile passes are launched. SV_TILE_LAUNCH_AUTO (0),
                           SV_TILE_LAUNCH_GRID (1): one workgroup per tile,
                           SV_TILE_LAUNCH_PERSISTENT (2): one resident workgroup set that
@@ -120,6 +120,18 @@ typedef struct {
                           value as a BF16 high part plus a BF16 low part, three
                           products, FP32 accumulation: about 2^-16 relative
                           error per block instead of 2^-24)                          */
+    int peephole;      /* cancellation of adjacent inverse pairs (Sec. III.F.2: identical
+                          Toffoli pairs and X-X pairs, here every multi-controlled X, and
+                          also SWAP pairs and an INC next to the DEC of the same register,
+                          all with identical controls), adjacent meaning that no op in
+                          between acts on any of the pair's qubits: the pair is the
+                          identity and is dropped before planning.  SV_PEEPHOLE_AUTO (0):
+                          on in fused mode, off in plain mode (which keeps one launch per
+                          op); SV_PEEPHOLE_OFF (1); SV_PEEPHOLE_ON (2): on in both modes */
+    int dense_qubits;  /* fused: qubits per dense block: 0 or 5 = five (32 x 32 blocks);
+                          6 = six (64 x 64 blocks, complex64 only: SV_EUNSUPPORTED for
+                          complex128), on FP32 or split-BF16 matrix cores as dense_bf16
+                          says                                                       */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0
@@ -132,6 +144,10 @@ typedef struct {
 #define SV_COMPILE_AUTO 0
 #define SV_COMPILE_OFF 1
 #define SV_COMPILE_ON 2
+
+#define SV_PEEPHOLE_AUTO 0
+#define SV_PEEPHOLE_OFF 1
+#define SV_PEEPHOLE_ON 2
 
 typedef struct sv_state sv_state;
 typedef struct sv_plan sv_plan;
@@ -150,6 +166,7 @@ typedef struct {
     uint64_t n_split_ops;     /* fused: IR ops run as plain launches by the cost model */
     uint64_t n_compiled_kernels; /* compiled plans: distinct specialised pass kernels; 0 otherwise */
     int      dense_min_ops;   /* fused: the run length that makes a dense block (0: none) */
+    uint64_t n_cancelled_ops; /* IR ops dropped as adjacent inverse pairs (peephole)  */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

@@ -99,16 +99,17 @@ def random_state(n: int, seed: int = 0) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
-def random_dense_block_circuit(n: int, blocks: int, depth: int, seed: int = 0, between: int = 3) -> Circuit:
-    """Deep gate runs confined to five qubits at a time (the case dense block
-    fusion is for): per block, five distinct qubits; per layer a Haar U(2) on
-    each, a CX between two of them, a doubly controlled phase and a controlled
-    increment (or controlled swap) inside the block; `between` Haar gates on
-    random qubits separate the blocks."""
+def random_dense_block_circuit(n: int, blocks: int, depth: int, seed: int = 0, between: int = 3,
+                               width: int = 5) -> Circuit:
+    """Deep gate runs confined to `width` (5 or 6) qubits at a time (the case
+    dense block fusion is for): per block, `width` distinct qubits; per layer a
+    Haar U(2) on each, a CX between two of them, a doubly controlled phase and a
+    controlled increment (or controlled swap) inside the block; `between` Haar
+    gates on random qubits separate the blocks."""
     rng = np.random.default_rng(seed)
     c = Circuit(n)
     for _ in range(blocks):
-        blk = sorted(int(q) for q in rng.choice(n, 5, replace=False))
+        blk = sorted(int(q) for q in rng.choice(n, width, replace=False))
         for _ in range(depth):
             for q in blk:
                 c.u(q, haar_u2(rng))
@@ -122,3 +123,60 @@ def random_dense_block_circuit(n: int, blocks: int, depth: int, seed: int = 0, b
         for _ in range(between):
             c.u(int(rng.integers(n)), haar_u2(rng))
     return c
+
+
+def random_circuit_with_inverse_pairs(n: int, seed: int = 0):
+    """A random mixed circuit with inverse pairs spliced in, and the number of
+    ops a peephole pass must drop: adjacent MCX pairs (X, CNOT, Toffoli, more
+    controls, open controls), nested pairs A B B^-1 A^-1, SWAP(a, b) SWAP(b, a),
+    INC then DEC and DEC then INC of one register; and decoys that must stay: a
+    pair split by an op on one of its control qubits, a pair whose controls
+    differ in polarity, INC followed by INC."""
+    rng = np.random.default_rng(seed)
+    base = random_mixed_circuit(n, 120, seed=seed, max_ctrl=4)
+    c = Circuit(n)
+    recs = list(base.iter_ops())
+    expect = 0
+    for i, (rec, prm) in enumerate(recs):
+        c.append_op(rec, prm)
+        if i % 12 != 5:
+            continue
+        q = [int(v) for v in rng.permutation(n)]
+        k = i // 12 % 6
+        if k == 0:    # MCX pair with mixed-polarity controls
+            ctrl = {q[1]: 1, q[2]: 0}
+            c.x(q[0], ctrl)
+            c.x(q[0], ctrl)
+            expect += 2
+        elif k == 1:  # nested: Toffoli, CNOT, CNOT, Toffoli
+            c.x(q[0], [q[1], q[2]])
+            c.x(q[1], [q[3]])
+            c.x(q[1], [q[3]])
+            c.x(q[0], [q[1], q[2]])
+            expect += 4
+        elif k == 2:  # swap pair, operands given in the other order
+            c.swap(q[0], q[1], {q[2]: 1})
+            c.swap(q[1], q[0], {q[2]: 1})
+            expect += 2
+        elif k == 3:  # INC then DEC of one register under a control, then the reverse
+            w = 3
+            lo = int(rng.integers(0, n - w + 1))
+            rest = [v for v in q if v < lo or v >= lo + w]
+            c.inc(lo, w, {rest[0]: 0})
+            c.dec(lo, w, {rest[0]: 0})
+            c.dec(lo, w)
+            c.inc(lo, w)
+            expect += 4
+        elif k == 4:  # decoy: an op on a control qubit in between
+            c.x(q[0], [q[1]])
+            c.h(q[1])
+            c.x(q[0], [q[1]])
+        else:         # decoys: polarity differs; two increments; plain X-X (dropped)
+            c.x(q[0], {q[1]: 1})
+            c.x(q[0], {q[1]: 0})
+            c.inc(0, 2)
+            c.inc(0, 2)
+            c.x(q[3])
+            c.x(q[3])
+            expect += 2
+    return c, expect

@@ -1,5 +1,6 @@
-// Dense 5-qubit block passes on matrix cores: FP32 for complex64 states,
-// FP64 for complex128 states (second kernel below).
+// Dense block passes on matrix cores: five-qubit blocks in FP32 or split BF16
+// for complex64 states and in FP64 for complex128 states; six-qubit blocks in
+// FP32 or split BF16 for complex64 states.
 //
 // A workgroup stages one tile of 2^12 amplitudes in LDS (five block qubits and
 // seven others, loaded through the coalesced tile mapping).  Each of the four
@@ -231,6 +232,190 @@ k_dense_pass_bf16(float2 *__restrict__ psi, const DensePass *__restrict__ dp, co
     }
 }
 
+// Six-qubit blocks (complex64): a tile holds 64 groups (values of the six other
+// local qubits) of 64 amplitudes, and Y = G X is a real 64 x 128 by 128 x 64
+// product per part.  Wave w takes the 32 x 32 corner of rows 32 (w >> 1) ..
+// 32 (w >> 1) + 31 and groups 32 (w & 1) .. 32 (w & 1) + 31, for Y_re and for
+// Y_im: 64 K-steps of v_mfma_f32_32x32x2f32 per part (the operand layout of
+// the five-qubit kernel).  [G_im | G_re] is [G_re | -G_im] with its halves
+// exchanged and one negated, so a lane keeps only the 64 values of the latter
+// in registers for the whole persistent launch and negates X_re instead:
+//   Y_re = G_re X_re + (-G_im) X_im,   Y_im = (-G_im)(-X_re) + G_re X_im.
+// At 512 flop per amplitude this form is bound by the FP32 matrix cores.
+__global__ void __launch_bounds__(256)
+k_dense6_pass(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats,
+              uint64_t n_tiles)
+{
+    extern __shared__ unsigned char smem_raw[];
+    float2 *lds = reinterpret_cast<float2 *>(smem_raw);
+    const DensePass &D = *dp;
+    const TilePass &P = D.map;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t c = lane & 31u, h = lane >> 5;
+    const uint32_t mb = wave >> 1, nb = wave & 1u;
+    const uint32_t row = 32u * mb + c;
+    const float *G = mats + D.mat;
+    float a1[64];  // columns 2 kk + h of [G_re | -G_im]
+#pragma unroll
+    for (int kk = 0; kk < 64; ++kk) {
+        const uint32_t q = 2u * kk + h;
+        a1[kk] = kk < 32 ? G[2 * (64 * row + q)] : -G[2 * (64 * row + q - 64) + 1];
+    }
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
+    const uint32_t g = 32u * nb + c;
+    uint32_t gl = 0;
+    for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+        const uint32_t w = D.grp_run[r];
+        gl |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+    }
+    const uint32_t tw = lds_swizzle(tid, 4);
+
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        float2 *const pt = psi + (dense_tile_base(P, tile) | gthr);
+        {
+            float2 x[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+        }
+        __syncthreads();
+        v16f acc_re = {0.f}, acc_im = {0.f};
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            // amplitudes 2 i + h of the group, i in [16 half, 16 half + 16)
+            float2 xb[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xb[i] = lds[lds_swizzle(gl | D.joff[2 * (16 * half + i) + h], 4)];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int kk = 16 * half + i;
+                acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[i].x, acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk + 32], -xb[i].x, acc_im, 0, 0, 0);
+                acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk + 32], xb[i].y, acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], xb[i].y, acc_im, 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read its X before Y overwrites it
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const uint32_t r = 32u * mb + 8u * (t / 4) + 4u * h + (t % 4);
+            lds[lds_swizzle(gl | D.joff[r], 4)] = make_float2(acc_re[t], acc_im[t]);
+        }
+        __syncthreads();
+        float2 y[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) y[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = y[s];
+        __syncthreads();  // the next tile overwrites the LDS
+    }
+}
+
+// Six-qubit blocks in split BF16: the corner of k_dense6_pass on
+// v_mfma_f32_32x32x8bf16_1k, hi and lo parts as in k_dense_pass_bf16.  K chunk
+// q (0..15) covers columns 8 q .. 8 q + 7 of [G_re | -G_im] and [G_im | G_re]:
+// chunks 0-7 take X_re, 8-15 X_im, of the amplitudes 8 (q % 8) + 4 h + j.
+// As in the FP32 form only the split [G_re | -G_im] stays in registers (the
+// split of a negated value is the negated split), and Y_im takes -X_re.
+// 96 BF16 products per tile and wave replace 256 FP32 ones.
+__global__ void __launch_bounds__(256)
+k_dense6_pass_bf16(float2 *__restrict__ psi, const DensePass *__restrict__ dp, const float *__restrict__ mats,
+                   uint64_t n_tiles)
+{
+    extern __shared__ unsigned char smem_raw[];
+    float2 *lds = reinterpret_cast<float2 *>(smem_raw);
+    const DensePass &D = *dp;
+    const TilePass &P = D.map;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t c = lane & 31u, h = lane >> 5;
+    const uint32_t mb = wave >> 1, nb = wave & 1u;
+    const uint32_t row = 32u * mb + c;
+    const float *G = mats + D.mat;
+
+    s4 ah[16], al[16];  // [G_re | -G_im], chunk q: columns 8 q + 4 h + j
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t col = 8u * (uint32_t)(q & 7) + 4u * h + (uint32_t)j;  // block value of the column
+            const float v0 = q < 8 ? G[2 * (64 * row + col)] : -G[2 * (64 * row + col) + 1];
+            ah[q][j] = bf16_rn(v0);
+            al[q][j] = bf16_rn(v0 - bf16_f(ah[q][j]));
+        }
+    uint64_t gthr = 0;
+    for (uint32_t r = 0; r < P.n_gthr_runs; ++r) {
+        const uint32_t sh = P.gthr_shift[r];
+        gthr |= (uint64_t)((tid >> (sh & 0xffu)) & P.gthr_mask[r]) << (sh >> 8);
+    }
+    const uint32_t g = 32u * nb + c;
+    uint32_t gl = 0;
+    for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
+        const uint32_t w = D.grp_run[r];
+        gl |= ((g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
+    }
+    const uint32_t tw = lds_swizzle(tid, 4);
+
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        float2 *const pt = psi + (dense_tile_base(P, tile) | gthr);
+        {
+            float2 x[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) x[s] = pt[P.goff[s]];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) lds[tw ^ P.swz0[s]] = x[s];
+        }
+        __syncthreads();
+        v16f acc_re = {0.f}, acc_im = {0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            // chunk q (real parts, and their negation for Y_im) and chunk q + 8 (imaginary parts)
+            s4 bhr, blr, nhr, nlr, bhi, bli;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 xv = lds[lds_swizzle(gl | D.joff[8 * q + 4 * h + j], 4)];
+                bhr[j] = bf16_rn(xv.x);
+                blr[j] = bf16_rn(xv.x - bf16_f(bhr[j]));
+                nhr[j] = (short)(bhr[j] ^ (short)0x8000);
+                nlr[j] = (short)(blr[j] ^ (short)0x8000);
+                bhi[j] = bf16_rn(xv.y);
+                bli[j] = bf16_rn(xv.y - bf16_f(bhi[j]));
+            }
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q], bhr, acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q], blr, acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[q], bhr, acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q + 8], nhr, acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q + 8], nlr, acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[q + 8], nhr, acc_im, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q + 8], bhi, acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q + 8], bli, acc_re, 0, 0, 0);
+            acc_re = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[q + 8], bhi, acc_re, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q], bhi, acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah[q], bli, acc_im, 0, 0, 0);
+            acc_im = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al[q], bhi, acc_im, 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read its X before Y overwrites it
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const uint32_t r = 32u * mb + 8u * (t / 4) + 4u * h + (t % 4);
+            lds[lds_swizzle(gl | D.joff[r], 4)] = make_float2(acc_re[t], acc_im[t]);
+        }
+        __syncthreads();
+        float2 y[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) y[s] = lds[tw ^ P.swz0[s]];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pt[P.goff[s]] = y[s];
+        __syncthreads();  // the next tile overwrites the LDS
+    }
+}
+
 // Complex128: the same product on FP64 matrix cores, v_mfma_f64_16x16x4f64
 // (M = 16 block rows, N = 16 groups, K = 4 block values per instruction).
 // Operand layout of that instruction (checked on the device): lane l holds
@@ -343,7 +528,13 @@ int launch_dense_pass(const sv_plan *p, uint32_t di, void *psi, hipStream_t st)
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const uint64_t cap = (uint64_t)cus * 2;  // resident workgroups per CU at these kernels' register and LDS use
     const uint32_t grid = (uint32_t)(tiles < cap ? tiles : cap);
-    if (p->dtype == SV_C64 && p->dense_bf16)
+    if (p->dtype == SV_C64 && D.k == 6 && p->dense_bf16)
+        hipLaunchKernelGGL(k_dense6_pass_bf16, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                           (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
+    else if (p->dtype == SV_C64 && D.k == 6)
+        hipLaunchKernelGGL(k_dense6_pass, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
+                           (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
+    else if (p->dtype == SV_C64 && p->dense_bf16)
         hipLaunchKernelGGL(k_dense_pass_bf16, dim3(grid), dim3(256), sizeof(float2) << 12, st, (float2 *)psi,
                            (const DensePass *)p->d_dense + di, (const float *)p->d_dparams, tiles);
     else if (p->dtype == SV_C64)

@@ -164,18 +164,19 @@ struct Step {
     uint32_t index;
 };
 
-// Dense 5-qubit block: the 2^12 amplitudes of a tile (the five block qubits and
-// seven others) go through LDS; a group is one value of the seven other local
-// qubits, and every group's 32 amplitudes are multiplied by the block matrix.
-// `map` carries the load/store mapping (spos, tpos, runs, goff, swz0) of a tile
-// pass with b = 12 and 4 register qubits; its stage fields are unused.
-constexpr int kDenseK = 5;
+// Dense k-qubit block (k = 5 or 6): the 2^12 amplitudes of a tile (the k block
+// qubits and 12 - k others) go through LDS; a group is one value of the other
+// local qubits, and every group's 2^k amplitudes are multiplied by the block
+// matrix.  `map` carries the load/store mapping (spos, tpos, runs, goff, swz0)
+// of a tile pass with b = 12 and 4 register qubits; its stage fields are unused.
+constexpr int kMaxDenseK = 6;
 struct DensePass {
     TilePass map;
+    uint32_t k;                       // block qubits
     uint32_t mat;                     // offset (reals) of the matrix: (row i, column j), re, im
-    uint32_t n_grp_runs;              // group index (7 bits) -> local offset, as pack_run16 runs
+    uint32_t n_grp_runs;              // group index (12 - k bits) -> local offset, as pack_run16 runs
     uint32_t grp_run[kMaxThrRuns];
-    uint32_t joff[1 << kDenseK];      // local offset of block value j (bit k of j -> block qubit k)
+    uint32_t joff[1 << kMaxDenseK];   // local offset of block value j (bit k of j -> block qubit k)
 };
 
 // One instance of a batched launch: where its state starts in the arena (in
@@ -220,6 +221,7 @@ struct sv_plan {
     // the pass's first parameter (reals into the device parameter array)
     bool compiled = false;
     bool dense_bf16 = false;          // complex64 dense blocks on BF16 matrix cores (split operands)
+    int dense_k = 5;                  // qubits per dense block (5, or 6 for complex64)
     int refs = 1;                     // the caller's handle, plus each concurrent batch that runs it
     std::vector<void *> jit_fn;
     std::vector<uint32_t> jit_prm;

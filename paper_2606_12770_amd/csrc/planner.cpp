@@ -159,7 +159,7 @@ constexpr double kOpPerTileUs = 0.31e-3, kOpPerAmpUs = 0.32e-6;
 // A dense 5-qubit block pass: a fixed cost per launch plus one sweep of the
 // state at the rate the matrix-core pass sustains (measured 4.7 TB/s complex64
 // and 4.9 TB/s complex128 on 28 qubits).
-constexpr double kDenseFixedUs = 8.0, kDenseBytesPerUs = 4.7e6;
+constexpr double kDenseFixedUs = 8.0, kDenseBytesPerUs = 4.7e6, kDenseFp32FlopPerUs = 9.0e7;
 constexpr int kLookahead = 8;  // candidate resident-set widenings compared per step
 constexpr int kMinGateRun = 6;  // shortest run of ops with one tile mask worth a bisection
 double plain_us(const OpInfo &o, int n, int s)
@@ -223,6 +223,57 @@ std::vector<OpInfo> fold_single_qubit_runs(const std::vector<OpInfo> &in)
     return out;
 }
 
+// Peephole cancellation (Sec. III.F.2 post-processes the compiled circuits by
+// dropping adjacent identical Toffoli pairs and X-X pairs).  Here: any two
+// multi-controlled X gates, any two SWAPs, or an INC and a DEC of one register,
+// with identical targets and identical controls (mask and polarity), that are
+// adjacent on their qubits: the later op's qubits (targets and controls) are
+// exactly the earlier op's, and no op in between acts on any of them.  Such a
+// pair is the identity.  Each qubit keeps a stack of the live ops acting on
+// it, so removing a pair exposes the ops before it, and nested pairs (A B B^-1
+// A^-1, the ripples of an INC followed by its DEC) cancel in turn.
+bool inverse_pair(const OpInfo &a, const OpInfo &b)
+{
+    if (a.mask != b.mask || a.val != b.val) return false;
+    if (a.kind == SV_OP_X && b.kind == SV_OP_X) return a.target == b.target;
+    if (a.kind == SV_OP_SWAP && b.kind == SV_OP_SWAP)
+        return (a.target == b.target && a.width == b.width) || (a.target == b.width && a.width == b.target);
+    if ((a.kind == SV_OP_INC && b.kind == SV_OP_DEC) || (a.kind == SV_OP_DEC && b.kind == SV_OP_INC))
+        return a.target == b.target && a.width == b.width;
+    return false;
+}
+
+size_t cancel_inverse_pairs(std::vector<OpInfo> &ops)
+{
+    std::vector<std::vector<uint32_t>> on(64);
+    std::vector<char> live(ops.size(), 1);
+    size_t dropped = 0;
+    for (size_t k = 0; k < ops.size(); ++k) {
+        const uint64_t t = touched_qubits(ops[k]);
+        long top = -2;  // the one op on top of every stack of t, -1 if none
+        for (uint64_t r = t; r; r &= r - 1) {
+            const int q = __builtin_ctzll(r);
+            const long j = on[q].empty() ? -1 : (long)on[q].back();
+            if (top == -2) top = j;
+            else if (top != j) { top = -1; break; }
+        }
+        if (top >= 0 && touched_qubits(ops[top]) == t && inverse_pair(ops[top], ops[k])) {
+            live[top] = live[k] = 0;
+            for (uint64_t r = t; r; r &= r - 1) on[__builtin_ctzll(r)].pop_back();
+            dropped += 2;
+            continue;
+        }
+        for (uint64_t r = t; r; r &= r - 1) on[__builtin_ctzll(r)].push_back((uint32_t)k);
+    }
+    if (dropped) {
+        size_t w = 0;
+        for (size_t k = 0; k < ops.size(); ++k)
+            if (live[k]) ops[w++] = ops[k];
+        ops.resize(w);
+    }
+    return dropped;
+}
+
 // Hadamard-like matrices in complex64 plans.  An uncontrolled 2x2 matrix whose
 // entries are 0, +-1/sqrt(2) or +-i/sqrt(2) (H, and its products with X, Z,
 // S, S^dagger) becomes, rounded to FP32, the same matrix times fp32(1/sqrt 2)
@@ -265,27 +316,27 @@ int exact_hadamard_pairs(std::vector<OpInfo> &ops)
     return (int)(at.size() / 2);
 }
 
-// ---- dense 5-qubit blocks -------------------------------------------------
+// ---- dense k-qubit blocks -------------------------------------------------
 // The block matrix of a run of ops whose qubits (targets and controls) lie in
-// blk[0..4] (ascending): column j is the run applied to the basis vector e_j,
-// bit k of the index standing for qubit blk[k].
+// blk[0..dk-1] (ascending): column j is the run applied to the basis vector
+// e_j, bit k of the index standing for qubit blk[k].
 using cplx = std::complex<double>;
 
-void apply_small(std::vector<cplx> &v, const OpInfo &o, const int *blk)
+void apply_small(std::vector<cplx> &v, const OpInfo &o, const int *blk, int dk)
 {
     auto mapbits = [&](uint64_t m) {
         uint32_t r = 0;
-        for (int k = 0; k < kDenseK; ++k)
+        for (int k = 0; k < dk; ++k)
             if ((m >> blk[k]) & 1ull) r |= 1u << k;
         return r;
     };
     auto pos = [&](int q) {
-        for (int k = 0; k < kDenseK; ++k)
+        for (int k = 0; k < dk; ++k)
             if (blk[k] == q) return k;
         return -1;
     };
     const uint32_t mask = mapbits(o.mask), val = mapbits(o.val);
-    const int N = 1 << kDenseK;
+    const int N = 1 << dk;
     const std::vector<cplx> in = v;
     switch (o.kind) {
     case SV_OP_U: {
@@ -384,6 +435,15 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             return SV_EUNSUPPORTED;
         }
     }
+    if (opts.dense_qubits != 0 && opts.dense_qubits != 5 && opts.dense_qubits != 6) {
+        err = "dense_qubits must be 0, 5 or 6";
+        return SV_EINVAL;
+    }
+    if (opts.dense_qubits == 6 && p->dtype != SV_C64) {
+        err = "six-qubit dense blocks are complex64 only";
+        return SV_EUNSUPPORTED;
+    }
+    p->dense_k = opts.dense_qubits == 6 ? 6 : 5;
     p->b = fused ? b : 0;
     p->rb = fused ? rb : 0;
     p->info.tile_qubits = p->b;
@@ -403,6 +463,12 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->plain.push_back(to_plain(o));
         p->info.bytes_moved += plain_bytes(o, n, esize);
     };
+
+    const bool peephole = opts.peephole == SV_PEEPHOLE_ON || (opts.peephole == SV_PEEPHOLE_AUTO && fused);
+    if (peephole) {
+        p->info.n_cancelled_ops = cancel_inverse_pairs(info);
+        n_ops = info.size();
+    }
 
     if (!fused) {
         if (p->dtype == SV_C64) exact_hadamard_pairs(info);
@@ -431,8 +497,9 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     // X gates as flips of their local bit on exchanges that apply permutations
     const bool x_flips = true;
 
-    // ---- dense 5-qubit runs: maximal runs of consecutive ops whose qubits fit
-    // in five, kept when at least dense_min_ops long ----
+    // ---- dense k-qubit runs: maximal runs of consecutive ops whose qubits fit
+    // in k (5, or 6 for complex64), kept when at least dense_min_ops long ----
+    const int dk = p->dense_k;
     std::vector<int> dense_id(n_ops, -1);
     std::vector<std::pair<size_t, size_t>> runs;
     std::vector<uint64_t> run_support;
@@ -441,7 +508,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     // amplitudes it touches) are modelled dearer than one dense pass
     int dense_min = opts.dense_min_ops;
     if (dense_min < 0) {
-        const double dense_us = kDenseFixedUs + (double)(2ull << n) * esize / kDenseBytesPerUs;
+        double dense_us = kDenseFixedUs + (double)(2ull << n) * esize / kDenseBytesPerUs;
+        // six-qubit blocks on FP32 matrix cores: 512 flop per amplitude, bound by the products
+        if (dk == 6 && !p->dense_bf16)
+            dense_us = std::max(dense_us, kDenseFixedUs + (double)(1ull << n) * 512.0 / kDenseFp32FlopPerUs);
         const double op_us = kOpPerTileUs * (double)(1ull << (n > b ? n - b : 0)) + kOpPerAmpUs * (double)(1ull << n);
         dense_min = (int)std::min(1e6, std::ceil(dense_us / op_us));
     }
@@ -458,31 +528,32 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         };
         for (size_t i = 0; i < n_ops; ++i) {
             const uint64_t T = touched_qubits(info[i]);
-            if (__builtin_popcountll(S | T) <= kDenseK) {
+            if (__builtin_popcountll(S | T) <= dk) {
                 S |= T;
                 continue;
             }
             close(i);
             ws = i;
-            S = __builtin_popcountll(T) <= kDenseK ? T : 0;
+            S = __builtin_popcountll(T) <= dk ? T : 0;
             if (!S) ws = i + 1;  // an op wider than a block starts no run
         }
         close(n_ops);
     }
     auto emit_dense = [&](int rid) {
         const uint64_t S = run_support[rid];
-        int blk[kDenseK];
+        int blk[kMaxDenseK];
         {
             uint64_t B = S;
-            for (int q = 0; q < n && __builtin_popcountll(B) < kDenseK; ++q) B |= 1ull << q;
+            for (int q = 0; q < n && __builtin_popcountll(B) < dk; ++q) B |= 1ull << q;
             int k = 0;
             for (int q = 0; q < n; ++q)
                 if ((B >> q) & 1ull) blk[k++] = q;
         }
         uint64_t R = 0;
-        for (int k = 0; k < kDenseK; ++k) R |= 1ull << blk[k];
+        for (int k = 0; k < dk; ++k) R |= 1ull << blk[k];
         for (int q = 0; q < n && __builtin_popcountll(R) < 12; ++q) R |= 1ull << q;
         DensePass D{};
+        D.k = (uint32_t)dk;
         TilePass &P = D.map;
         P.b = 12;
         P.rb = 4;
@@ -519,9 +590,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             P.gthr_shift[r] = (uint32_t)src | ((uint32_t)dst << 8);
             P.gthr_mask[r] = (1u << w) - 1u;
         });
-        for (int j = 0; j < (1 << kDenseK); ++j) {
+        const int N = 1 << dk;
+        for (int j = 0; j < N; ++j) {
             uint32_t off = 0;
-            for (int k = 0; k < kDenseK; ++k)
+            for (int k = 0; k < dk; ++k)
                 if ((j >> k) & 1) off |= 1u << lpos[blk[k]];
             D.joff[j] = off;
         }
@@ -530,24 +602,24 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             int c = 0;
             for (int l = 0; l < 12; ++l) {
                 bool inblk = false;
-                for (int k = 0; k < kDenseK; ++k) inblk = inblk || lpos[blk[k]] == l;
+                for (int k = 0; k < dk; ++k) inblk = inblk || lpos[blk[k]] == l;
                 if (!inblk) nb[c++] = (uint8_t)l;
             }
         }
         D.n_grp_runs = 0;
-        bit_runs(nb, 7, [&](int src, int dst, int w) {
+        bit_runs(nb, 12 - dk, [&](int src, int dst, int w) {
             D.grp_run[D.n_grp_runs++] = pack_run16((uint32_t)src, (uint32_t)dst, (1u << w) - 1u);
         });
         // the block matrix, column by column
         D.mat = (uint32_t)p->dparams.size();
-        p->dparams.resize(p->dparams.size() + 2 * 32 * 32, 0.0);
-        for (int j = 0; j < 32; ++j) {
-            std::vector<cplx> v(32, cplx(0.0, 0.0));
+        p->dparams.resize(p->dparams.size() + 2 * (size_t)N * N, 0.0);
+        for (int j = 0; j < N; ++j) {
+            std::vector<cplx> v(N, cplx(0.0, 0.0));
             v[j] = 1.0;
-            for (size_t k = runs[rid].first; k < runs[rid].second; ++k) apply_small(v, info[k], blk);
-            for (int i = 0; i < 32; ++i) {
-                p->dparams[D.mat + 2 * (32 * i + j)] = v[i].real();
-                p->dparams[D.mat + 2 * (32 * i + j) + 1] = v[i].imag();
+            for (size_t k = runs[rid].first; k < runs[rid].second; ++k) apply_small(v, info[k], blk, dk);
+            for (int i = 0; i < N; ++i) {
+                p->dparams[D.mat + 2 * (N * i + j)] = v[i].real();
+                p->dparams[D.mat + 2 * (N * i + j) + 1] = v[i].imag();
             }
         }
         p->steps.push_back(Step{2, (uint32_t)p->dense.size()});

@@ -339,17 +339,20 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
         if (P.swz0[s] != lds_swizzle((uint32_t)s << 8, dl)) return 36;
     std::fill(rd.begin(), rd.end(), 0);
     std::fill(wr.begin(), wr.end(), 0);
+    if (D.k != 5 && D.k != 6) return 37;
+    if (D.k == 6 && p.dtype != SV_C64) return 38;
+    const int N = 1 << D.k, NG = 4096 >> D.k;
     // group offsets from the runs, and the exact cover of the local indices
     uint32_t goffl[128];
     std::vector<int> cover(4096, 0);
-    for (int g = 0; g < 128; ++g) {
+    for (int g = 0; g < NG; ++g) {
         uint32_t o = 0;
         for (uint32_t r = 0; r < D.n_grp_runs; ++r) {
             const uint32_t w = D.grp_run[r];
             o |= (((uint32_t)g >> (w & 0xffu)) & (w >> 16)) << ((w >> 8) & 0xffu);
         }
         goffl[g] = o;
-        for (int j = 0; j < 32; ++j) {
+        for (int j = 0; j < N; ++j) {
             const uint32_t l = o | D.joff[j];
             if (l >= 4096 || (o & D.joff[j])) return 31;
             cover[l]++;
@@ -357,7 +360,7 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
     }
     for (int l = 0; l < 4096; ++l)
         if (cover[l] != 1) return 32;
-    if (D.mat + 2048 > p.dparams.size()) return 33;
+    if (D.mat + 2 * (size_t)N * N > p.dparams.size()) return 33;
     const double *G = p.dparams.data() + D.mat;
     std::vector<cd> x(4096), y(4096);
     for (uint64_t tile = 0; tile < (1ull << P.ntile); ++tile) {
@@ -376,11 +379,11 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
             rd[g]++;
             x[l] = psi[g];
         }
-        for (int g = 0; g < 128; ++g)
-            for (int i = 0; i < 32; ++i) {
+        for (int g = 0; g < NG; ++g)
+            for (int i = 0; i < N; ++i) {
                 cd acc(0.0, 0.0);
-                for (int j = 0; j < 32; ++j)
-                    acc += cd(G[2 * (32 * i + j)], G[2 * (32 * i + j) + 1]) * x[goffl[g] | D.joff[j]];
+                for (int j = 0; j < N; ++j)
+                    acc += cd(G[2 * (N * i + j)], G[2 * (N * i + j) + 1]) * x[goffl[g] | D.joff[j]];
                 y[goffl[g] | D.joff[i]] = acc;
             }
         for (uint32_t l = 0; l < 4096; ++l) {
@@ -403,6 +406,18 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
 static int g_round_params_f32 = 0;
 extern "C" void emu_set_param_rounding(int on) { g_round_params_f32 = on; }
 
+// sv_apply_opts.peephole of the plans emu_run builds (SV_PEEPHOLE_AUTO by default).
+static int g_peephole = SV_PEEPHOLE_AUTO;
+extern "C" void emu_set_peephole(int v) { g_peephole = v; }
+
+// sv_apply_opts.dense_qubits of the plans emu_run builds (0: five).
+static int g_dense_qubits = 0;
+extern "C" void emu_set_dense_qubits(int v) { g_dense_qubits = v; }
+
+// Plans the op list and runs the plan on psi_io (interleaved re, im).  stats,
+// when given, receives 7 entries: launches, tile passes, register stages,
+// algorithmic bytes, ops split to plain launches, ops inside gate runs, ops
+// dropped by the peephole pass.
 extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode,
                        int tile_qubits, int reg_qubits, double *psi_io, uint64_t *stats, int dense_min_ops)
 {
@@ -410,6 +425,8 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     p.n = n;
     p.dtype = dtype;
     sv_apply_opts o{mode, tile_qubits, reg_qubits, dense_min_ops};
+    o.peephole = g_peephole;
+    o.dense_qubits = g_dense_qubits;
     std::string err;
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;
@@ -444,6 +461,7 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
             for (uint32_t k = S.op_begin; k < S.op_end; ++k)
                 if (p.tops[k].kind != T_PROJ) in_runs += (uint32_t)p.tops[k].a | ((uint32_t)p.tops[k].b << 8);
         stats[5] = in_runs;
+        stats[6] = p.info.n_cancelled_ops;
     }
     return 0;
 }

@@ -37,7 +37,7 @@ int main(int argc, char **argv)
     if (cnt[1] && std::fread(params.data(), sizeof(double), cnt[1], f) != cnt[1]) return 2;
     if (std::fread(psi.data(), sizeof(double), psi.size(), f) != psi.size()) return 2;
     std::fclose(f);
-    uint64_t stats[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t stats[7] = {0, 0, 0, 0, 0, 0, 0};
     const int rc = emu_run(n, hdr[1], ops.data(), ops.size(), params.data(), hdr[2], hdr[3], hdr[4], psi.data(),
                            stats, hdr[5]);
     if (rc != 0) {

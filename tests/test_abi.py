@@ -143,3 +143,25 @@ def test_sequence_entries_are_checked_against_the_plan_count():
         rc = lib.sv_plan_execute_seq(plans, 1, seq.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(seq), None)
         assert rc == sv.SV_EINVAL
         assert "outside the plan array" in sv.sv_last_error()
+
+
+def test_binding_structs_match_header(tmp_path):
+    """sv_apply_opts and sv_plan_info: the ctypes mirrors have the header's
+    size and every field at the header's offset (a C probe compiled here)."""
+    structs = {"sv_apply_opts": sv.sv_apply_opts, "sv_plan_info": sv.sv_plan_info}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sv.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

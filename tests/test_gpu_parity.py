@@ -13,8 +13,8 @@ import pytest
 
 from oracle import statevector as osv
 from paper_2606_12770_amd.circuits.ir import Circuit
-from paper_2606_12770_amd.circuits.random_circuit import (random_layered_circuit, random_mixed_circuit,
-                                                          random_state)
+from paper_2606_12770_amd.circuits.random_circuit import (random_circuit_with_inverse_pairs, random_layered_circuit,
+                                                          random_mixed_circuit, random_state)
 from tests.gpu_util import assert_c64_close, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -282,3 +282,32 @@ def test_persistent_tile_launch_many_tiles_per_workgroup(dtype):
     p0 = abs(back[0]) ** 2 / np.vdot(back, back).real
     print(f"persistent 26q dtype={dtype}: |<0|U^dagger U|0>|^2 = {p0:.15f}", flush=True)
     assert 1.0 - p0 < (1e-12 if dtype == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("n,mode,compile", [(14, 1, 1), (22, 1, 2), (12, 0, 0)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_peephole_matches_oracle(n, mode, compile, dtype):
+    """Plans with the peephole pass on (Sec. III.F.2: adjacent inverse pairs
+    dropped): the count dropped is the number spliced in, and the state matches
+    the oracle's run of the full op list (complex128 to 1e-12, complex64
+    element-wise to the complex64 bar)."""
+    sv = require_gpu()
+    c, expect = random_circuit_with_inverse_pairs(n, n + dtype)
+    psi0 = random_state(n, 9)
+    want = osv.run(c, psi0)
+    ops, params = c.arrays()
+    plan = sv.sv_plan_create(n, dtype, ops, params, mode, 12 if mode else 0, 4 if mode else 0, compile=compile,
+                             peephole=sv.SV_PEEPHOLE_ON)
+    info = sv.sv_plan_get_info(plan)
+    st = sv.sv_alloc(n, dtype, psi0)
+    sv.sv_plan_execute(plan, st, 1)
+    got = sv.sv_amplitudes(st)
+    sv.sv_free(st)
+    sv.sv_plan_free(plan)
+    print(f"peephole n={n} mode={mode} dtype={dtype}: dropped {info['n_cancelled_ops']} of {len(c)} ops, "
+          f"max abs err {np.max(np.abs(got - want)):.2e}", flush=True)
+    assert info["n_cancelled_ops"] == expect
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what=f"peephole n={n} mode={mode}")

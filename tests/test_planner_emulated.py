@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import statevector as osv
-from paper_2606_12770_amd.circuits.random_circuit import (random_layered_circuit, random_mixed_circuit,
-                                                          random_state)
+from paper_2606_12770_amd.circuits.random_circuit import (random_circuit_with_inverse_pairs, random_layered_circuit,
+                                                          random_mixed_circuit, random_state)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2606_12770_amd", "csrc")
@@ -39,7 +39,7 @@ def emu():
 def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0, dense_min_ops=0):
     ops, params = circ.arrays()
     psi = np.array(psi0, dtype=np.complex128, copy=True)
-    stats = (ctypes.c_uint64 * 6)()
+    stats = (ctypes.c_uint64 * 7)()
     dp = ctypes.POINTER(ctypes.c_double)
     rc = L.emu_run(circ.n, dtype, ops.ctypes.data, len(ops), params.ctypes.data_as(dp), mode, b, rb,
                    psi.ctypes.data_as(dp), stats, dense_min_ops)
@@ -188,6 +188,33 @@ def test_dense_blocks_match_oracle(emu, n, seed, dtype):
     assert np.max(np.abs(got2 - want)) < 1e-12
 
 
+@pytest.mark.parametrize("n,seed", [(12, 0), (14, 1), (17, 2)])
+def test_six_qubit_dense_blocks_match_oracle(emu, n, seed):
+    """dense_qubits = 6: runs confined to six qubits become 64 x 64 blocks
+    (64 groups of 64 amplitudes per tile); the emulated plan matches the oracle,
+    and complex128 plans refuse six-qubit blocks."""
+    from paper_2606_12770_amd.circuits.random_circuit import random_dense_block_circuit
+    c = random_dense_block_circuit(n, 4, 5, seed, width=6)
+    psi0 = random_state(n, seed)
+    want = osv.run(c, psi0)
+    emu.emu_set_dense_qubits(6)
+    try:
+        got, stats = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=16)
+        assert np.max(np.abs(got - want)) < 1e-12
+        assert stats[0] >= stats[1] + 4  # the four deep runs became dense passes
+        ops, params = c.arrays()
+        buf = np.array(psi0, dtype=np.complex128)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = emu.emu_run(c.n, 1, ops.ctypes.data, len(ops), params.ctypes.data_as(dp), 1, 12, 4,
+                         buf.ctypes.data_as(dp), None, 16)
+        assert rc == -5  # SV_EUNSUPPORTED
+    finally:
+        emu.emu_set_dense_qubits(0)
+    # the same circuit with five-qubit blocks
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4, 0, dense_min_ops=16)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_complex64_hadamards_keep_the_norm(emu, mode):
     """Uncontrolled Hadamards stored as fp32(1/sqrt 2) would each shrink the
@@ -245,3 +272,52 @@ def test_dense_blocks_chosen_by_cost(emu):
     got, stats = run_emu(emu, layered, osv.zero_state(n), 1, 12, 4, 0, dense_min_ops=-1)
     assert np.max(np.abs(got - osv.run(layered))) < 1e-12
     assert stats[0] == stats[1] + stats[4]  # tile passes and split plain launches only
+
+
+@pytest.mark.parametrize("mode,n,seed", [(1, 13, 0), (1, 14, 1), (0, 10, 2), (0, 12, 3)])
+def test_peephole_cancels_inverse_pairs(emu, mode, n, seed):
+    """Sec. III.F.2's peephole pass: adjacent inverse pairs are dropped (their
+    count exactly as spliced in), the decoys stay, and the planned circuit still
+    matches the oracle's run of the full op list."""
+    c, expect = random_circuit_with_inverse_pairs(n, seed)
+    psi0 = random_state(n, seed + 7)
+    want = osv.run(c, psi0)
+    emu.emu_set_peephole(2)
+    try:
+        got, stats = run_emu(emu, c, psi0, mode, 12 if mode else 0, 4 if mode else 0)
+    finally:
+        emu.emu_set_peephole(0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[6] == expect
+    if mode == 0:
+        assert stats[0] == len(c) - expect  # one launch per remaining op
+    emu.emu_set_peephole(1)
+    try:
+        got, stats = run_emu(emu, c, psi0, mode, 12 if mode else 0, 4 if mode else 0)
+    finally:
+        emu.emu_set_peephole(0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[6] == 0
+
+
+def test_peephole_default_follows_mode(emu):
+    """SV_PEEPHOLE_AUTO: on in fused plans, off in plain ones."""
+    c, expect = random_circuit_with_inverse_pairs(12, 4)
+    psi0 = random_state(12, 3)
+    _, fused = run_emu(emu, c, psi0, 1, 12, 4)
+    _, plain = run_emu(emu, c, psi0, 0)
+    assert fused[6] == expect and plain[6] == 0 and plain[0] == len(c)
+
+
+def test_peephole_on_first_order_ladder(emu):
+    """On a first-order QSVT ladder the X pairs where one U_L call meets the
+    next are dropped, and the result is unchanged."""
+    from paper_2606_12770_amd.circuits import carleman_circuit as cc
+    cfg = cc.CarlemanConfig(nx=8, order=1, nk=1)
+    enc = cc.build_ul(cfg)
+    c = cc.build_qsvt(enc, np.linspace(0.1, 0.5, 6))
+    psi0 = random_state(c.n, 11)
+    want = osv.run(c, psi0)
+    got, stats = run_emu(emu, c, psi0, 1, 12, 4)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[6] > 0
