@@ -502,6 +502,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=28)
     ap.add_argument("--layers", type=int, default=200)
+    ap.add_argument("--skip-alt-geometry", action="store_true",
+                    help="do not time the complex64 headline circuit at geometry (13,5) beside the default")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--reg-qubits", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -626,6 +628,22 @@ def main():
     roof["frac_vs_copy"] = achieved / copy_gbs
     log(f"copy bandwidth {copy_gbs:.0f} GB/s")
 
+    # the same complex64 circuit at geometry (13,5): fewer, heavier passes
+    alt = None
+    if not args.skip_alt_geometry and args.tile_qubits == 0:
+        t0 = time.time()
+        plan_a = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 13, 5, tile_launch=TILE_LAUNCH)
+        alt_plan_s = time.time() - t0
+        info_a = sv.sv_plan_get_info(plan_a)
+        st_a = sv.sv_alloc(n, sv.SV_C64)
+        sv.sv_plan_execute(plan_a, st_a, 1)
+        ms_a = sv.sv_plan_time(plan_a, st_a, args.steps) / args.steps
+        sv.sv_free(st_a)
+        sv.sv_plan_free(plan_a)
+        alt = {"tile_qubits": 13, "reg_qubits": 5, "ms_per_step": ms_a, "gates_per_s": n_gates / (ms_a / 1e3),
+               "launches": info_a["n_launches"], "tile_passes": info_a["n_tile_passes"], "plan_s": alt_plan_s}
+        log(f"fused c64 at geometry (13,5): {ms_a:.2f} ms/step, {info_a['n_tile_passes']} passes")
+
     carleman = None
     sections = set(x for x in args.sections.strip("=").split(",") if x) if not args.skip_carleman else set()
     if sections:
@@ -684,6 +702,7 @@ def main():
         "fused_c128": {"gates_per_s": n_gates / (ms128 / 1e3), "ms_per_step": ms128,
                        "launches": info128["n_launches"]},
         "fused_c64_generic_kernel": {"gates_per_s": n_gates / (ms_g / 1e3), "ms_per_step": ms_g},
+        "fused_c64_geometry_13_5": alt,
         "plan_s": plan_s,
         "plain_fp64": plain,
         "copy_GBps": copy_gbs,
