@@ -13,7 +13,7 @@ import hashlib
 
 from . import sv
 
-CANDIDATES = ((12, 4), (11, 4), (10, 4), (12, 5), (13, 5))
+CANDIDATES = ((12, 4), (11, 4), (10, 4), (12, 5), (13, 5), (13, 4))
 
 _cache: dict = {}
 
@@ -28,8 +28,13 @@ def circuit_digest(circuits) -> str:
     return h.hexdigest()
 
 
-def _valid(n, b, rb):
-    return b <= n and 6 <= b - rb <= 8
+def _valid(n, b, rb, compiled=False):
+    """Tiles of 512 threads (b - rb = 9) run only as compiled passes."""
+    return b <= n and 6 <= b - rb <= (9 if compiled else 8)
+
+
+def _compiled(n, compile):
+    return compile == sv.SV_COMPILE_ON or (compile == sv.SV_COMPILE_AUTO and n >= 21)
 
 
 def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1, compile=0):
@@ -40,7 +45,7 @@ def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1, compile=0)
     ops, params = circuit.arrays()
     times = {}
     for b, rb in candidates:
-        if not _valid(circuit.n, b, rb):
+        if not _valid(circuit.n, b, rb, _compiled(circuit.n, compile)):
             continue
         p = sv.sv_plan_create(circuit.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile)
         try:
@@ -103,7 +108,7 @@ def tune_ladder(enc, dtype, proxy_degree=1001, candidates=CANDIDATES, compile=0)
     times = {}
     try:
         for b, rb in candidates:
-            if not _valid(n, b, rb):
+            if not _valid(n, b, rb, _compiled(n, compile)):
                 continue
             p = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile)
             try:

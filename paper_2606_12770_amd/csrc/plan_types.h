@@ -70,7 +70,7 @@ static_assert(sizeof(TileOp) == 40, "TileOp layout");
 
 constexpr int kMaxRB = 5;
 constexpr int kMaxB = 14;
-constexpr int kMaxThrRuns = 8;
+constexpr int kMaxThrRuns = 10;  // runs of up to nine thread bits (512 threads)
 constexpr int kMaxTileRuns = 16;
 constexpr int kParamStride = 8;
 constexpr int kDefaultTileLaunch = SV_TILE_LAUNCH_GRID;  // what SV_TILE_LAUNCH_AUTO resolves to  // reals of parameters reserved per tile op (op k at k * 8)

@@ -425,8 +425,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             err = "tile_qubits too large for LDS";
             return SV_EINVAL;
         }
-        if (b - rb > 8) {
-            err = "tile_qubits - reg_qubits must be at most 8 (256 threads)";
+        // 512 threads (nine thread bits) only as compiled passes: the generic
+        // tile kernels are built for at most 256
+        if (b - rb > 9 || (b - rb == 9 && opts.compile == SV_COMPILE_OFF)) {
+            err = "tile_qubits - reg_qubits must be at most 8 (256 threads), or 9 (512) with compiled passes";
             return SV_EINVAL;
         }
         if (b - rb < 6) fused = false;  // fewer than 64 threads: use plain launches

@@ -431,6 +431,11 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         delete p;
         return fail(SV_EUNSUPPORTED, "compiled tile passes need at most 64 KiB of LDS per tile");
     }
+    if (!p->compiled && p->b > 0 && p->b - p->rb > 8 && !p->passes.empty()) {
+        release_plan(p);
+        delete p;
+        return fail(SV_EUNSUPPORTED, "tiles of 512 threads run only as compiled passes (compilation unavailable)");
+    }
     *out = p;
     return SV_OK;
 }
@@ -803,6 +808,8 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
         const sv_plan *p = plans[i];
         if (p->b == 0 || p->b != p0->b || p->rb != p0->rb || p->dtype != p0->dtype)
             return fail(SV_EINVAL, "batched plans must be fused with one tile geometry and one precision");
+        if (p->b - p->rb > 8)
+            return fail(SV_EUNSUPPORTED, "the level-synchronous batch runs tiles of at most 256 threads");
         for (const auto &st : p->steps)
             if (st.type != 1) return fail(SV_EUNSUPPORTED, "batched plans must consist of tile passes only");
         if (states[i]->arena != arena) return fail(SV_EINVAL, "batched states must come from one sv_alloc_batch arena");

@@ -165,3 +165,50 @@ def test_invalid_compile_mode_is_refused():
     with pytest.raises(sv.SVError) as e:
         sv.sv_plan_create(14, 0, ops, params, sv.SV_MODE_FUSED, compile=7)
     assert e.value.code == sv.SV_EINVAL
+
+
+@pytest.mark.parametrize("n,persistent", [(14, 0), (17, 0), (20, 0), (22, 1)])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_512_thread_tiles_match_oracle(n, persistent, dtype):
+    """Geometry (13,4): 2^13 amplitudes per workgroup of 512 threads, 16 per
+    thread, which only compiled passes run.  Every op kind against the
+    oracle (complex128 to 1e-12, complex64 element-wise), in the grid and the
+    persistent launch forms; the same plan without compilation is refused."""
+    sv = require_gpu()
+    c = random_mixed_circuit(n, 400, seed=11 * n + dtype, max_ctrl=6)
+    psi0 = random_state(n, 70 + n)
+    want = osv.run(c, psi0)
+    ops, params = c.arrays()
+    form = sv.SV_TILE_LAUNCH_PERSISTENT if persistent else sv.SV_TILE_LAUNCH_GRID
+    plan = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, 13, 4, tile_launch=form,
+                             compile=sv.SV_COMPILE_ON)
+    info = sv.sv_plan_get_info(plan)
+    st = sv.State(n, dtype, psi0)
+    sv.sv_plan_execute(plan, st.h, 1)
+    got = st.amplitudes()
+    st.close()
+    sv.sv_plan_free(plan)
+    print(f"(13,4) n={n} dtype={dtype} persistent={persistent}: {info['n_tile_passes']} passes, "
+          f"max abs err {np.max(np.abs(got - want)):.2e}", flush=True)
+    assert info["tile_qubits"] == 13 and info["reg_qubits"] == 4 and info["n_compiled_kernels"] > 0
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what=f"(13,4) n={n}")
+    with pytest.raises(sv.SVError):
+        sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, 13, 4, compile=sv.SV_COMPILE_OFF)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_512_thread_tiles_benchmark_prefix_28q(dtype):
+    """Two layers of the 28-qubit benchmark circuit at geometry (13,4) against
+    the oracle."""
+    sv = require_gpu()
+    c = random_layered_circuit(28, 2, seed=0)
+    want = osv.run(c)
+    got, info = run(sv, c, osv.zero_state(28), dtype, sv.SV_COMPILE_ON, 13, 4)
+    assert info["n_compiled_kernels"] > 0
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what="(13,4) 28q prefix")

@@ -48,7 +48,7 @@ def compile_circuit(L, circ, dtype, b=12, rb=4, persistent=0):
     return rc
 
 
-@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (15, 12, 5), (13, 10, 4), (16, 13, 5), (12, 11, 5)])
+@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (15, 12, 5), (13, 10, 4), (16, 13, 5), (12, 11, 5), (15, 13, 4)])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_mixed_circuits_compile(jit, n, b, rb, dtype):
     if dtype == 1 and b == 13:
@@ -68,8 +68,9 @@ def test_carleman_ladder_with_gate_runs_compiles(jit, dtype):
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
-def test_benchmark_circuit_compiles(jit, persistent):
-    compile_circuit(jit, random_layered_circuit(28, 3, seed=0), 0, persistent=persistent)
+@pytest.mark.parametrize("b,rb", [(12, 4), (13, 4)])
+def test_benchmark_circuit_compiles(jit, persistent, b, rb):
+    compile_circuit(jit, random_layered_circuit(28, 3, seed=0), 0, b, rb, persistent=persistent)
 
 
 @pytest.mark.parametrize("dtype", [0, 1])

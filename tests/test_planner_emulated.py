@@ -48,7 +48,8 @@ def run_emu(L, circ, psi0, mode=1, b=0, rb=0, dtype=0, dense_min_ops=0):
 
 
 @pytest.mark.parametrize("n,b,rb,seed", [(10, 10, 4, 0), (11, 10, 4, 1), (12, 12, 4, 2), (13, 12, 4, 3),
-                                         (14, 12, 5, 4), (14, 11, 5, 5), (15, 12, 4, 6), (12, 11, 5, 7)])
+                                         (14, 12, 5, 4), (14, 11, 5, 5), (15, 12, 4, 6), (12, 11, 5, 7),
+                                         (15, 13, 4, 8), (14, 13, 4, 9)])
 def test_fused_plan_matches_oracle_mixed(emu, n, b, rb, seed):
     c = random_mixed_circuit(n, 400, seed=seed, max_ctrl=5)
     psi0 = random_state(n, seed)
@@ -58,7 +59,7 @@ def test_fused_plan_matches_oracle_mixed(emu, n, b, rb, seed):
     assert stats[1] >= 1
 
 
-@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (16, 12, 4), (16, 13, 5)])
+@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (16, 12, 4), (16, 13, 5), (17, 13, 4)])
 def test_fused_plan_matches_oracle_layered(emu, n, b, rb):
     c = random_layered_circuit(n, 6, seed=n, n_mcx=10, max_ctrl=8, inc_width=6)
     want = osv.run(c)
@@ -159,7 +160,8 @@ def test_plain_split_matches_oracle(emu, seed):
     assert stats[4] > 0 and stats[1] > 0  # some ops went to plain launches, some stayed in tile passes
 
 
-@pytest.mark.parametrize("dtype,b,rb", [(0, 12, 4), (0, 12, 5), (0, 13, 5), (1, 12, 4), (1, 11, 5)])
+@pytest.mark.parametrize("dtype,b,rb", [(0, 12, 4), (0, 12, 5), (0, 13, 5), (0, 13, 4), (1, 12, 4), (1, 11, 5),
+                                        (1, 13, 4)])
 def test_precomputed_pass_fields_at_benchmark_size(emu, dtype, b, rb):
     """Run maps, swizzle tables and LDS addressing of every pass of the
     28-qubit benchmark circuit (first 20 layers), checked without emulation."""
