@@ -128,9 +128,10 @@ def copy_bandwidth(sv, n, reps=10):
     return 2.0 * (8 << n) / best / 1e9
 
 
-def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
+def carleman_ladder(sv, cfg_kw, d, variants, reps=3, geometry=(0, 0)):
     """The QSVT ladder of one Carleman-LBM instance at degree d from b: gates/s
-    per (name, dtype, mode, elementary) variant, timed with HIP events."""
+    per (name, dtype, mode, elementary) variant, timed with HIP events; fused
+    variants at tile geometry `geometry` ((0, 0): the library default)."""
     from paper_2606_12770_amd.circuits import carleman_circuit as cc
     from paper_2606_12770_amd.circuits import qsp
     cfg = cc.CarlemanConfig(**cfg_kw)
@@ -142,7 +143,8 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
     for name, dtype, mode, elementary in variants:
         circ = cc.lower_to_elementary(native) if elementary else native
         ops, params = circ.arrays()
-        plan = sv.sv_plan_create(circ.n, dtype, ops, params, mode, tile_launch=TILE_LAUNCH)
+        b, rb = geometry if mode == sv.SV_MODE_FUSED else (0, 0)
+        plan = sv.sv_plan_create(circ.n, dtype, ops, params, mode, b, rb, tile_launch=TILE_LAUNCH)
         info = sv.sv_plan_get_info(plan)
         st = sv.sv_alloc(circ.n, dtype)
         sv.sv_set_amplitudes(st, rhs, 0)
@@ -154,6 +156,7 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3):
         out[name] = {"gates": len(ops), "gates_per_s": len(ops) / (ms / 1e3), "ms": ms,
                      "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
                      "compiled_kernels": info["n_compiled_kernels"],
+                     "geometry": [info["tile_qubits"], info["reg_qubits"]],
                      "GBps_algorithmic": info["bytes_moved"] / (ms / 1e3) / 1e9}
         log(f"carleman {enc.layout.n}q {name}: {out[name]['gates_per_s']:.0f} gates/s, {ms:.2f} ms, "
             f"{info['n_launches']} launches")
@@ -657,9 +660,10 @@ def main():
                 ("plain_c128", C128, P, False), ("fused_c128", C128, F, False), ("fused_c64", C64, F, False),
                 ("plain_c128_elementary", C128, P, True), ("fused_c64_elementary", C64, F, True)])
         if "grid64" in sections:
+            # geometry (13,5): 362 ms against 405 ms at (12,4) and 374 ms at (13,4), one box
             carleman["grid64_31q"] = carleman_ladder(
                 sv, dict(nx=64, tau=0.8, nk=4, nt=8, dt=0.1, amp=0.08, u0=0.02), 13,
-                [("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1)
+                [("plain_c128", C128, P, False), ("fused_c64", C64, F, False)], reps=1, geometry=(13, 5))
         if "batch" in sections:
             carleman["batched_64"] = batched_carleman(sv)
         if "dense" in sections:
