@@ -89,7 +89,9 @@ typedef struct {
 typedef struct {
     int mode;          /* SV_MODE_PLAIN or SV_MODE_FUSED                                  */
     int tile_qubits;   /* fused: qubits resident per tile, 0 = automatic                   */
-    int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic        */
+    int reg_qubits;    /* fused: qubits held in registers per thread, 0 = automatic; the
+                          workgroup has 2^(tile_qubits - reg_qubits) threads, 64 to 256,
+                          or 512 for compiled plans                                  */
     int dense_min_ops; /* fused: a run of at least this many consecutive ops acting
                           inside dense_qubits qubits (targets and controls) becomes one
                           dense block applied on matrix cores (FP32 or split BF16 for
@@ -113,8 +115,9 @@ typedef struct {
                           its op list written out, and runs as that kernel (same
                           arithmetic, bit-identical states; plan creation takes
                           longer), in either launch form; SV_COMPILE_AUTO (0): ON for
-                          states of at least 21 qubits, OFF otherwise, and OFF if
-                          compilation is unavailable                                  */
+                          states of at least 21 qubits and for tiles of 512 threads,
+                          OFF otherwise, and OFF if compilation is unavailable (then a
+                          512-thread plan is refused with SV_EUNSUPPORTED)            */
     int dense_bf16;    /* fused, complex64: 0 = dense blocks on FP32 matrix cores;
                           1 = on BF16 matrix cores with split operands (each FP32
                           value as a BF16 high part plus a BF16 low part, three

@@ -34,7 +34,9 @@ def _valid(n, b, rb, compiled=False):
 
 
 def _compiled(n, compile):
-    return compile == sv.SV_COMPILE_ON or (compile == sv.SV_COMPILE_AUTO and n >= 21)
+    """Whether plans under this compile mode may compile (automatic mode
+    compiles 512-thread tiles at any size)."""
+    return compile != sv.SV_COMPILE_OFF
 
 
 def tune_plan(circuit, state, dtype, candidates=CANDIDATES, repeat=1, compile=0):

@@ -411,7 +411,9 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     // specialised pass kernels: on request, or automatically for states of 21
     // qubits and more (LDS of a pass up to 64 KiB)
     const bool can = o.mode == SV_MODE_FUSED && p->b > 0 && !p->passes.empty() && ((size_t)8 << p->b) <= 65536;
-    const bool want = o.compile == SV_COMPILE_ON || (o.compile == SV_COMPILE_AUTO && n_qubits >= 21);
+    // (tiles of 512 threads exist only as compiled passes: AUTO compiles them at any size)
+    const bool wide = p->b > 0 && p->b - p->rb > 8;
+    const bool want = o.compile == SV_COMPILE_ON || (o.compile == SV_COMPILE_AUTO && (n_qubits >= 21 || wide));
     if (can && want) {
         std::string jerr;
         rc = svi::jit_prepare(p, jerr);
@@ -431,7 +433,7 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
         delete p;
         return fail(SV_EUNSUPPORTED, "compiled tile passes need at most 64 KiB of LDS per tile");
     }
-    if (!p->compiled && p->b > 0 && p->b - p->rb > 8 && !p->passes.empty()) {
+    if (!p->compiled && wide && !p->passes.empty()) {
         release_plan(p);
         delete p;
         return fail(SV_EUNSUPPORTED, "tiles of 512 threads run only as compiled passes (compilation unavailable)");

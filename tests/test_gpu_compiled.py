@@ -212,3 +212,14 @@ def test_512_thread_tiles_benchmark_prefix_28q(dtype):
         assert np.max(np.abs(got - want)) < 1e-12
     else:
         assert_c64_close(got, want, len(c), what="(13,4) 28q prefix")
+
+
+def test_512_thread_tiles_compile_automatically():
+    """Automatic mode compiles a 512-thread plan at any size (below 21 qubits
+    too), since no generic kernel runs it."""
+    sv = require_gpu()
+    c = random_mixed_circuit(16, 200, seed=21, max_ctrl=5)
+    psi0 = random_state(16, 22)
+    got, info = run(sv, c, psi0, 0, sv.SV_COMPILE_AUTO, 13, 4)
+    assert info["n_compiled_kernels"] > 0
+    assert_c64_close(got, osv.run(c, psi0), len(c), what="(13,4) automatic")
