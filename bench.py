@@ -157,7 +157,8 @@ def carleman_ladder(sv, cfg_kw, d, variants, reps=3, geometry=(0, 0)):
                      "launches": info["n_launches"], "tile_passes": info["n_tile_passes"],
                      "compiled_kernels": info["n_compiled_kernels"],
                      "geometry": [info["tile_qubits"], info["reg_qubits"]],
-                     "GBps_algorithmic": info["bytes_moved"] / (ms / 1e3) / 1e9}
+                     "GBps_algorithmic": info["bytes_moved"] / (ms / 1e3) / 1e9,
+                     "GBps_touched": info["touched_bytes"] / (ms / 1e3) / 1e9}
         log(f"carleman {enc.layout.n}q {name}: {out[name]['gates_per_s']:.0f} gates/s, {ms:.2f} ms, "
             f"{info['n_launches']} launches")
         sv.sv_free(st)
@@ -594,7 +595,8 @@ def main():
         np_ = sv.sv_postselect(stp, 0, 0, keep=False, renormalize=False)
         infid = 1.0 - (re * re + im * im) / (n64 * np_)
         plain = {"gates_per_s": n_gates / (msp / 1e3), "ms_per_step": msp, "launches": infop["n_launches"],
-                 "GBps_algorithmic": infop["bytes_moved"] / (msp / 1e3) / 1e9, "dtype": "f64"}
+                 "GBps_algorithmic": infop["bytes_moved"] / (msp / 1e3) / 1e9,
+                 "GBps_touched": infop["touched_bytes"] / (msp / 1e3) / 1e9, "dtype": "f64"}
         sv.sv_free(stp)
         sv.sv_plan_free(planp)
     sv.sv_free(st64)
@@ -705,6 +707,7 @@ def main():
                                f"complex64 fused", "qubits": n, "layers": args.layers, "gates": n_gates,
                    "tile_qubits": info64["tile_qubits"], "reg_qubits": info64["reg_qubits"]},
         "hbm_GBps_per_state_pass": achieved,
+        "bytes_per_step": {"algorithmic": info64["bytes_moved"], "touched_128B_lines": info64["touched_bytes"]},
         "infidelity_fused_c64_vs_plain_c128": infid,
         "fused_c128": {"gates_per_s": n_gates / (ms128 / 1e3), "ms_per_step": ms128,
                        "launches": info128["n_launches"]},

@@ -170,6 +170,9 @@ typedef struct {
     uint64_t n_compiled_kernels; /* compiled plans: distinct specialised pass kernels; 0 otherwise */
     int      dense_min_ops;   /* fused: the run length that makes a dense block (0: none) */
     uint64_t n_cancelled_ops; /* IR ops dropped as adjacent inverse pairs (peephole)  */
+    uint64_t touched_bytes;   /* HBM bytes per execution at 128-byte line granularity: a
+                                 plain launch whose controls sit on qubits inside a line
+                                 still reads and writes whole lines (>= bytes_moved)   */
 } sv_plan_info;
 
 /* ---- state lifetime ------------------------------------------------------- */

@@ -464,6 +464,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->steps.push_back(Step{0, (uint32_t)p->plain.size()});
         p->plain.push_back(to_plain(o));
         p->info.bytes_moved += plain_bytes(o, n, esize);
+        p->info.touched_bytes += touched_bytes(o, n, esize);
     };
 
     const bool peephole = opts.peephole == SV_PEEPHOLE_ON || (opts.peephole == SV_PEEPHOLE_AUTO && fused);
@@ -629,6 +630,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->info.n_dense_passes += 1;
         p->info.n_dense_ops += runs[rid].second - runs[rid].first;
         p->info.bytes_moved += 2ull * (1ull << n) * esize;
+        p->info.touched_bytes += 2ull * (1ull << n) * esize;
     };
 
     std::vector<char> done(n_ops, 0);
@@ -1170,6 +1172,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         p->info.n_tile_passes += 1;
         p->info.n_stages += P.stage_end - P.stage_begin;
         p->info.bytes_moved += 2ull * (1ull << n) * esize;
+        p->info.touched_bytes += 2ull * (1ull << n) * esize;
         for (uint32_t j : tail_plain) add_plain(info[j]);
     }
     p->tparams.resize(p->tops.size() * kParamStride, 0.0);

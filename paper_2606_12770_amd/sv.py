@@ -52,7 +52,7 @@ class sv_plan_info(ctypes.Structure):
                 ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int), ("n_dense_passes", ctypes.c_uint64),
                 ("n_dense_ops", ctypes.c_uint64), ("n_split_ops", ctypes.c_uint64),
                 ("n_compiled_kernels", ctypes.c_uint64), ("dense_min_ops", ctypes.c_int),
-                ("n_cancelled_ops", ctypes.c_uint64)]
+                ("n_cancelled_ops", ctypes.c_uint64), ("touched_bytes", ctypes.c_uint64)]
 
 
 _lib = None

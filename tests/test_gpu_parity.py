@@ -311,3 +311,25 @@ def test_peephole_matches_oracle(n, mode, compile, dtype):
         assert np.max(np.abs(got - want)) < 1e-12
     else:
         assert_c64_close(got, want, len(c), what=f"peephole n={n} mode={mode}")
+
+
+def test_touched_bytes_count_whole_lines():
+    """sv_plan_info.touched_bytes: a plain launch whose control sits on a qubit
+    inside a 128-byte line still moves whole lines; one controlled above the
+    line moves half the state; a tile pass moves the whole state either way."""
+    sv = require_gpu()
+    n = 20
+    c = Circuit(n)
+    c.x(10, [0])   # control inside a line (complex64: 16 amplitudes per line)
+    c.x(10, [15])  # control above it
+    ops, params = c.arrays()
+    full = 2 * (1 << n) * 8
+    plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_PLAIN)
+    info = sv.sv_plan_get_info(plan)
+    sv.sv_plan_free(plan)
+    assert info["bytes_moved"] == full
+    assert info["touched_bytes"] == full + full // 2
+    plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4, plain_split=sv.SV_PLAIN_SPLIT_OFF)
+    info = sv.sv_plan_get_info(plan)
+    sv.sv_plan_free(plan)
+    assert info["touched_bytes"] == info["bytes_moved"] == info["n_tile_passes"] * full
