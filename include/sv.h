@@ -135,6 +135,12 @@ typedef struct {
                           6 = six (64 x 64 blocks, complex64 only: SV_EUNSUPPORTED for
                           complex128), on FP32 or split-BF16 matrix cores as dense_bf16
                           says                                                       */
+    int coalesce_qubits; /* fused: the lowest qubits kept resident in every tile pass, so that
+                          each tile reads and writes runs of 2^coalesce_qubits contiguous
+                          amplitudes; 0 = automatic (256-byte runs: 5 for complex64, 4
+                          for complex128), else 1 to 8.  Fewer leave more of the tile to
+                          other qubits (fewer passes, each applying more gates); runs
+                          shorter than a 128-byte line cost extra HBM traffic         */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0

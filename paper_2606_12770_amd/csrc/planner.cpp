@@ -437,6 +437,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
             return SV_EUNSUPPORTED;
         }
     }
+    if (opts.coalesce_qubits < 0 || opts.coalesce_qubits > 8) {
+        err = "coalesce_qubits must be 0 (automatic) or 1 to 8";
+        return SV_EINVAL;
+    }
     if (opts.dense_qubits != 0 && opts.dense_qubits != 5 && opts.dense_qubits != 6) {
         err = "dense_qubits must be 0, 5 or 6";
         return SV_EINVAL;
@@ -487,7 +491,9 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     if (p->dtype == SV_C64) exact_hadamard_pairs(info);
 
     const int nthr = b - rb;
-    const int L0 = std::min(nthr, p->dtype == SV_C64 ? 5 : 4);
+    // lowest qubits resident in every pass (each tile's runs of contiguous
+    // amplitudes): 256 bytes by default; fewer leave more room for other qubits
+    const int L0 = std::min(nthr, opts.coalesce_qubits ? opts.coalesce_qubits : (p->dtype == SV_C64 ? 5 : 4));
     const int lowb = 4;  // LDS swizzle width: 8-byte elements (a complex64, or half a complex128)
     const uint64_t lowmask = (1ull << L0) - 1ull;
     const size_t W = 1024;

@@ -414,6 +414,10 @@ extern "C" void emu_set_peephole(int v) { g_peephole = v; }
 static int g_dense_qubits = 0;
 extern "C" void emu_set_dense_qubits(int v) { g_dense_qubits = v; }
 
+// sv_apply_opts.coalesce_qubits of the plans emu_run builds (0: automatic).
+static int g_coalesce_qubits = 0;
+extern "C" void emu_set_coalesce_qubits(int v) { g_coalesce_qubits = v; }
+
 // Plans the op list and runs the plan on psi_io (interleaved re, im).  stats,
 // when given, receives 7 entries: launches, tile passes, register stages,
 // algorithmic bytes, ops split to plain launches, ops inside gate runs, ops
@@ -427,6 +431,7 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     sv_apply_opts o{mode, tile_qubits, reg_qubits, dense_min_ops};
     o.peephole = g_peephole;
     o.dense_qubits = g_dense_qubits;
+    o.coalesce_qubits = g_coalesce_qubits;
     std::string err;
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;

@@ -333,3 +333,26 @@ def test_touched_bytes_count_whole_lines():
     info = sv.sv_plan_get_info(plan)
     sv.sv_plan_free(plan)
     assert info["touched_bytes"] == info["bytes_moved"] == info["n_tile_passes"] * full
+
+
+@pytest.mark.parametrize("dtype,coalesce", [(0, 4), (1, 3), (0, 3)])
+def test_coalesce_width_matches_oracle(dtype, coalesce):
+    """Plans with fewer lowest qubits kept resident (sv_apply_opts.coalesce_qubits:
+    runs of one 128-byte line, or half a line) against the oracle: a layered
+    circuit at 22 qubits, compiled passes."""
+    sv = require_gpu()
+    n = 22
+    c = random_layered_circuit(n, 8, seed=5)
+    want = osv.run(c)
+    ops, params = c.arrays()
+    plan = sv.sv_plan_create(n, dtype, ops, params, sv.SV_MODE_FUSED, 12, 4, compile=sv.SV_COMPILE_ON,
+                             coalesce_qubits=coalesce)
+    st = sv.State(n, dtype)
+    sv.sv_plan_execute(plan, st.h, 1)
+    got = st.amplitudes()
+    st.close()
+    sv.sv_plan_free(plan)
+    if dtype == 1:
+        assert np.max(np.abs(got - want)) < 1e-12
+    else:
+        assert_c64_close(got, want, len(c), what=f"coalesce {coalesce}")

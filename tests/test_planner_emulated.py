@@ -323,3 +323,21 @@ def test_peephole_on_first_order_ladder(emu):
     got, stats = run_emu(emu, c, psi0, 1, 12, 4)
     assert np.max(np.abs(got - want)) < 1e-12
     assert stats[6] > 0
+
+
+@pytest.mark.parametrize("coalesce", [1, 3, 4, 6, 8])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_coalesce_width_matches_oracle(emu, coalesce, dtype):
+    """sv_apply_opts.coalesce_qubits: plans keeping 1 to 8 lowest qubits
+    resident in every pass match the oracle (the emulation also checks every
+    pass's load mapping and LDS addressing)."""
+    n = 16
+    c = random_layered_circuit(n, 6, seed=n, n_mcx=10, max_ctrl=8, inc_width=6)
+    want = osv.run(c)
+    emu.emu_set_coalesce_qubits(coalesce)
+    try:
+        got, stats = run_emu(emu, c, osv.zero_state(n), 1, 12, 4, dtype)
+    finally:
+        emu.emu_set_coalesce_qubits(0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert stats[1] >= 1
