@@ -218,6 +218,30 @@ def test_benchmark_configuration_28q_prefix(dtype):
         assert_c64_close(got, want, len(c), what="28q prefix")
 
 
+def test_benchmark_circuit_20_layer_prefix_elementwise():
+    """The first 20 layers (780 gates) of the 28-qubit benchmark circuit in the
+    benchmark's own configuration (complex64, compiled tile passes, geometry
+    (12,4), plain splits) against the FP64 reference simulator, amplitude by
+    amplitude (about 30 s of host time for the reference)."""
+    sv = require_gpu()
+    n = 28
+    c = random_layered_circuit(n, 20, seed=0)
+    want = osv.run(c)
+    ops, params = c.arrays()
+    plan = sv.sv_plan_create(n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED)
+    info = sv.sv_plan_get_info(plan)
+    st = sv.State(n, sv.SV_C64)
+    sv.sv_plan_execute(plan, st.h, 1)
+    got = st.amplitudes()
+    st.close()
+    sv.sv_plan_free(plan)
+    print(f"28q 20-layer prefix: {info['n_tile_passes']} passes, {info['n_compiled_kernels']} compiled kernels, "
+          f"infidelity {infid(want, got):.2e}", flush=True)
+    assert info["n_compiled_kernels"] > 0 and info["tile_qubits"] == 12 and info["reg_qubits"] == 4
+    assert infid(want, got) < 1e-6
+    assert_c64_close(got, want, len(c), what="28q 20-layer prefix")
+
+
 def test_layered_26q_complex64_elementwise():
     """Six layers of the benchmark's random layered circuit on 26 qubits
     (512 MiB: streamed tile passes with the resident-set lookahead and op
