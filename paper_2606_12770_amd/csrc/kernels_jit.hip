@@ -1,5 +1,7 @@
 // Specialised tile-pass kernels at run time: generate (tile_codegen.cpp),
-// compile for the current device's architecture with hiprtc, load, launch.
+// compile for the current device's architecture (the HIP compiler in child
+// processes, in parallel; hiprtc in this process where that is unavailable),
+// load, launch.
 //
 // Identical pass sources share one kernel (a process-wide cache keyed by the
 // source text, per device), so a QSVT ladder compiles each distinct U_L pass
@@ -7,10 +9,18 @@
 // are compiled in parallel on host threads.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
+#include <fcntl.h>
+#include <spawn.h>
+#include <sys/wait.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <iterator>
 #include <map>
+#include <sstream>
 #include <tuple>
 #include <mutex>
 #include <string>
@@ -70,6 +80,78 @@ bool compile_unit(const std::string &src, const std::string &arch, std::vector<c
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     return true;
+}
+
+// The HIP compiler of the ROCm installation, for compiling in child
+// processes: hiprtc serialises compilations inside one process, so the
+// translation units of a plan compile one after another there.
+std::string clang_path()
+{
+    const char *root = std::getenv("ROCM_PATH");
+    const std::string c = std::string(root && *root ? root : "/opt/rocm") + "/lib/llvm/bin/clang++";
+    return access(c.c_str(), X_OK) == 0 ? c : std::string();
+}
+
+// Compile one translation unit with the HIP compiler in a child process
+// (device code only, one code object); false with a message when the
+// compiler cannot be run or fails (the caller then uses hiprtc).
+bool compile_unit_process(const std::string &clang, const std::string &src, const std::string &arch,
+                          std::vector<char> &code, std::string &err)
+{
+    const char *tmp = std::getenv("TMPDIR");
+    std::string dir = std::string(tmp && *tmp ? tmp : "/tmp") + "/svjit.XXXXXX";
+    std::vector<char> dbuf(dir.begin(), dir.end());
+    dbuf.push_back('\0');
+    if (!mkdtemp(dbuf.data())) {
+        err = "mkdtemp failed";
+        return false;
+    }
+    dir = dbuf.data();
+    const std::string in = dir + "/unit.hip", out = dir + "/unit.co", log = dir + "/unit.log";
+    {
+        std::ofstream f(in);
+        f << "#include <hip/hip_runtime.h>\n" << src;
+        if (!f) {
+            err = "cannot write " + in;
+            std::remove(in.c_str());
+            rmdir(dir.c_str());
+            return false;
+        }
+    }
+    const char *root = std::getenv("ROCM_PATH");
+    const std::string inc = std::string("-I") + (root && *root ? root : "/opt/rocm") + "/include";
+    const std::string off = "--offload-arch=" + arch;
+    std::vector<std::string> args = {clang, "-x", "hip", off, "--offload-device-only", "--no-gpu-bundle-output",
+                                     "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", inc,
+                                     "-c", in, "-o", out};
+    std::vector<char *> argv;
+    for (auto &a : args) argv.push_back(&a[0]);
+    argv.push_back(nullptr);
+    posix_spawn_file_actions_t fa;
+    posix_spawn_file_actions_init(&fa);
+    posix_spawn_file_actions_addopen(&fa, 1, log.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0600);
+    posix_spawn_file_actions_adddup2(&fa, 1, 2);
+    pid_t pid = 0;
+    int rc = posix_spawn(&pid, clang.c_str(), &fa, nullptr, argv.data(), environ);
+    posix_spawn_file_actions_destroy(&fa);
+    int status = 0;
+    bool ok = rc == 0 && waitpid(pid, &status, 0) == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0;
+    if (ok) {
+        std::ifstream f(out, std::ios::binary);
+        code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+        ok = !code.empty();
+    }
+    if (!ok) {
+        std::ifstream f(log);
+        std::stringstream ss;
+        ss << f.rdbuf();
+        err = "HIP compiler: " + ss.str().substr(0, 4000);
+    }
+    std::remove(in.c_str());
+    std::remove(out.c_str());
+    std::remove(log.c_str());
+    rmdir(dir.c_str());
+    return ok;
 }
 
 }  // namespace
@@ -133,6 +215,7 @@ int jit_prepare(sv_plan *p, std::string &err)
         for (uint32_t i : todo) names[i] = "tile_pass_" + std::to_string(serial0 + i);
         const std::string pre = jit_preamble(p->dtype);
         const std::string arch = arch_of(dev);
+        const std::string clang = clang_path();
         std::vector<std::vector<char>> code(units);
         std::vector<std::string> errs(units);
         std::vector<char> ok(units, 0);
@@ -154,7 +237,12 @@ int jit_prepare(sv_plan *p, std::string &err)
                     for (size_t j = u * per_unit; j < std::min(todo.size(), (u + 1) * per_unit); ++j)
                         src += jit_kernel(names[todo[j]], bodies[todo[j]], threads,
                                           bodies[todo[j]].compare(0, 13, "// persistent") == 0);
-                    ok[u] = compile_unit(src, arch, code[u], errs[u]) ? 1 : 0;
+                    // a child process per unit (parallel), else hiprtc in this process
+                    std::string perr;
+                    ok[u] = (!clang.empty() && compile_unit_process(clang, src, arch, code[u], perr)) ||
+                                    compile_unit(src, arch, code[u], errs[u])
+                                ? 1
+                                : 0;
                 }
             });
         }
