@@ -76,3 +76,28 @@ def test_benchmark_circuit_compiles(jit, persistent, b, rb):
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_persistent_form_compiles(jit, dtype):
     compile_circuit(jit, random_mixed_circuit(16, 250, seed=9, max_ctrl=5), dtype, 12, 4, persistent=1)
+
+
+def test_sources_compile_with_the_hip_compiler_command(jit, tmp_path):
+    """The library compiles generated units with the ROCm HIP compiler in child
+    processes (device code only, one code object); the same command line on a
+    unit of the benchmark circuit's passes gives an AMD GPU ELF code object."""
+    clang = "/opt/rocm/lib/llvm/bin/clang++"
+    if not os.access(clang, os.X_OK):
+        pytest.skip("no ROCm HIP compiler here")
+    c = random_layered_circuit(28, 2, seed=0)
+    ops, params = c.arrays()
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    src = tmp_path / "unit_src.hip"
+    rc = jit.jit_check(c.n, 0, ops.ctypes.data, len(ops), params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       12, 4, 0, str(src).encode(), None)
+    assert rc > 0
+    unit = tmp_path / "unit.hip"
+    unit.write_text("#include <hip/hip_runtime.h>\n" + src.read_text())
+    out = tmp_path / "unit.co"
+    subprocess.check_call([clang, "-x", "hip", "--offload-arch=gfx950", "--offload-device-only",
+                           "--no-gpu-bundle-output", "-O3", "-Xclang", "-target-feature", "-Xclang",
+                           "-packed-fp32-ops", "-I/opt/rocm/include", "-c", str(unit), "-o", str(out)])
+    head = out.read_bytes()[:20]
+    assert head[:4] == b"\x7fELF"
+    assert int.from_bytes(head[18:20], "little") == 224  # EM_AMDGPU
