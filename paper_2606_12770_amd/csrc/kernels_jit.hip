@@ -215,7 +215,9 @@ int jit_prepare(sv_plan *p, std::string &err)
         for (uint32_t i : todo) names[i] = "tile_pass_" + std::to_string(serial0 + i);
         const std::string pre = jit_preamble(p->dtype);
         const std::string arch = arch_of(dev);
-        const std::string clang = clang_path();
+        // child processes pay off from two units up (each starts a compiler and
+        // reads the HIP headers, about a second); a single unit goes to hiprtc
+        const std::string clang = units > 1 ? clang_path() : std::string();
         std::vector<std::vector<char>> code(units);
         std::vector<std::string> errs(units);
         std::vector<char> ok(units, 0);
