@@ -34,7 +34,7 @@ extern "C" {
 #define SV_ENOMEM       -2  /* the device cannot hold the requested state or plan */
 #define SV_EZEROPROB    -3  /* post-selection on a subspace of probability 0; state unchanged */
 #define SV_EDEVICE      -4  /* a HIP runtime call failed */
-#define SV_EUNSUPPORTED -5  /* valid request outside what this build implements */
+#define SV_EUNSUPPORTED -5  /* valid request outside what the library implements */
 
 /* ---- amplitude precision -------------------------------------------------- */
 #define SV_C64  0   /* complex64: float re, im (8 bytes per amplitude)   */
