@@ -15,6 +15,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -135,7 +136,11 @@ bool compile_unit_process(const std::string &clang, const std::string &src, cons
     int rc = posix_spawn(&pid, clang.c_str(), &fa, nullptr, argv.data(), environ);
     posix_spawn_file_actions_destroy(&fa);
     int status = 0;
-    bool ok = rc == 0 && waitpid(pid, &status, 0) == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0;
+    pid_t w = -1;
+    if (rc == 0)
+        do w = waitpid(pid, &status, 0);
+        while (w == -1 && errno == EINTR);
+    bool ok = rc == 0 && w == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0;
     if (ok) {
         std::ifstream f(out, std::ios::binary);
         code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
