@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "state_access.h"
 #include "sv_internal.h"
@@ -68,6 +69,20 @@ static inline int grid_for(uint64_t work, int block)
     return (int)g;
 }
 
+// The same row with every coefficient given as hi + lo (lo the FP32 rounding of
+// the FP64 coefficient's remainder), so the matrix the row applies is exact to
+// about 2^-48 and only the arithmetic rounds.
+template <typename C, typename R>
+__device__ __forceinline__ C mat_row2(const R *h, const R *l, C a, C b)
+{
+    const R lx = fma(l[0], a.x, fma(-l[1], a.y, fma(l[2], b.x, -l[3] * b.y)));
+    const R ly = fma(l[0], a.y, fma(l[1], a.x, fma(l[2], b.y, l[3] * b.x)));
+    C r;
+    r.x = fma(h[0], a.x, fma(-h[1], a.y, fma(h[2], b.x, fma(-h[3], b.y, lx))));
+    r.y = fma(h[0], a.y, fma(h[1], a.x, fma(h[2], b.y, fma(h[3], b.x, ly))));
+    return r;
+}
+
 template <typename R, bool NT>
 __global__ void __launch_bounds__(256) k_gate_u(typename CT<R>::T *__restrict__ psi, uint64_t nwork,
                                                 Deposit d, uint64_t cval, uint64_t tbit, Mat2<R> m)
@@ -80,6 +95,27 @@ __global__ void __launch_bounds__(256) k_gate_u(typename CT<R>::T *__restrict__ 
         const C a = load_state<NT>(psi + i0), b = load_state<NT>(psi + i1);
         store_state<NT>(psi + i0, mat_row(m.v[0], m.v[1], m.v[2], m.v[3], a, b));
         store_state<NT>(psi + i1, mat_row(m.v[4], m.v[5], m.v[6], m.v[7], a, b));
+    }
+}
+
+// Complex64 form: the matrix as hi + lo FP32 pairs.  A plain launch often
+// applies the same gate in every call of a long sequence (a value-load
+// rotation of each block-encoding call), and with its matrix rounded to FP32
+// the gate scales its subspace by the same factor every time, a drift that adds
+// up linearly; carried as hi + lo, the matrix keeps the norm to about 2^-48.
+// Plain launches move state through HBM, so the four extra FMAs per amplitude
+// cost nothing.
+template <bool NT>
+__global__ void __launch_bounds__(256) k_gate_u2(float2 *__restrict__ psi, uint64_t nwork, Deposit d,
+                                                 uint64_t cval, uint64_t tbit, Mat2<float> m, Mat2<float> lo)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += stride) {
+        const uint64_t i0 = deposit_zeros(w, d) | cval;
+        const uint64_t i1 = i0 | tbit;
+        const float2 a = load_state<NT>(psi + i0), b = load_state<NT>(psi + i1);
+        store_state<NT>(psi + i0, mat_row2(m.v, lo.v, a, b));
+        store_state<NT>(psi + i1, mat_row2(m.v + 4, lo.v + 4, a, b));
     }
 }
 
@@ -271,8 +307,15 @@ static int launch_plain_t(const PlainOp &op, int n, void *psi_v, hipStream_t st)
         const uint64_t nwork = 1ull << (n - 1 - c);
         Mat2<R> m;
         for (int k = 0; k < 8; ++k) m.v[k] = (R)op.m[k];
-        hipLaunchKernelGGL((k_gate_u<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
-                           make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target, m);
+        if constexpr (std::is_same<R, float>::value) {
+            Mat2<float> lo;
+            for (int k = 0; k < 8; ++k) lo.v[k] = (float)(op.m[k] - (double)m.v[k]);
+            hipLaunchKernelGGL((k_gate_u2<NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                               make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target, m, lo);
+        } else {
+            hipLaunchKernelGGL((k_gate_u<R, NT>), dim3(grid_for(nwork, B)), dim3(B), 0, st, psi, nwork,
+                               make_deposit(op.mask | (1ull << op.target), n), op.val, 1ull << op.target, m);
+        }
         break;
     }
     case SV_OP_X: {

@@ -142,10 +142,17 @@ __device__ __forceinline__ void reg_ur(C (&x)[NR], const R *m, uint32_t slotmask
         const int s1 = s | (1 << K);
         const C a = x[s], b = x[s1];
         C r0, r1;
-        r0.x = fma(m[0], a.x, m[1] * b.x);
-        r0.y = fma(m[0], a.y, m[1] * b.y);
-        r1.x = fma(m[2], a.x, m[3] * b.x);
-        r1.y = fma(m[2], a.y, m[3] * b.y);
+        if constexpr (sizeof(R) == 8) {
+            r0.x = fma(m[0], a.x, m[1] * b.x);
+            r0.y = fma(m[0], a.y, m[1] * b.y);
+            r1.x = fma(m[2], a.x, m[3] * b.x);
+            r1.y = fma(m[2], a.y, m[3] * b.y);
+        } else {  // hi m[0..3] + lo m[4..7]
+            r0.x = fma(m[0], a.x, fma(m[1], b.x, fma(m[4], a.x, m[5] * b.x)));
+            r0.y = fma(m[0], a.y, fma(m[1], b.y, fma(m[4], a.y, m[5] * b.y)));
+            r1.x = fma(m[2], a.x, fma(m[3], b.x, fma(m[6], a.x, m[7] * b.x)));
+            r1.y = fma(m[2], a.y, fma(m[3], b.y, fma(m[6], a.y, m[7] * b.y)));
+        }
         x[s] = r0;
         x[s1] = r1;
     }
@@ -388,9 +395,11 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
                 for (int j = 0; j < 8; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_u, x, m, op.slotmask)
             } else if (op.kind == T_UR) {
-                R m[4];
+                // complex64: the FP32 rounding (hi) and its remainder (lo)
+                constexpr int NM = sizeof(R) == 8 ? 4 : 8;
+                R m[NM];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) m[j] = pk[j];
+                for (int j = 0; j < NM; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_ur, x, m, op.slotmask)
             } else if (op.kind == T_X) {
                 SV_SLOT_DISPATCH(reg_x, x, op.slotmask)

@@ -231,4 +231,7 @@ namespace svi {
 // Builds steps/passes/stages/ops on the host; returns SV_OK or an error code.
 int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                const sv_apply_opts &opts, std::string &err);
+// Complex64 copy of a plan's tile parameters: projector phases rounded so that
+// the product of their norm factors stays next to 1, the rest to nearest.
+std::vector<float> tile_params_c64(const std::vector<TileOp> &tops, const std::vector<double> &tparams);
 }  // namespace svi

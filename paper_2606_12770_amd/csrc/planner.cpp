@@ -1231,4 +1231,69 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     return SV_OK;
 }
 
+// A projector phase multiplies every amplitude by c + i s or c - i s (the QSVT
+// phase rotations of Sec. II.D.5), so with (cos, sin) rounded to FP32 it
+// scales the norm of the whole state by c^2 + s^2, a few 1e-8 away from 1.  A
+// QSVT sequence has one distinct phase per step, so these factors do not
+// cancel: over the 71,002 phases of the second-order run of Sec. III.E.2 they
+// multiply to 1 + 2.6e-5.  Being global scalars they commute with every op,
+// and only their product matters.  Each pair is therefore rounded to the FP32
+// pair with the smallest angle error among those within one ulp of the
+// nearest rounding in each entry that keep the running product of the factors
+// within kNormBand of 1; where none does, to the one that brings the product
+// closest to 1.  Either way the angle error stays within the nearest
+// rounding's bound (half an ulp of each entry), and most pairs keep their
+// nearest rounding.
+// A real 2x2 gate (the value-load rotations of the block encoding, Sec.
+// II.D.1-II.D.3) applies the same matrix in every call of the sequence to its
+// controlled subspace; rounded to FP32 its columns' norms differ from 1 by up
+// to 5e-8 and that subspace gains or loses the same fraction in every call
+// (7e-5 over the second-order run, measured with FP64 arithmetic).  Such
+// gates therefore carry each entry as the FP32 rounding (hi, slots 0-3) plus
+// the FP32 rounding of the remainder (lo, slots 4-7), and the kernels apply
+// hi + lo.  All other parameters round to nearest.
+std::vector<float> tile_params_c64(const std::vector<TileOp> &tops, const std::vector<double> &tparams)
+{
+    constexpr double kNormBand = 1e-7;
+    std::vector<float> f(tparams.begin(), tparams.end());
+    double acc = 0.0;  // sum of (factor - 1): the log of the running product, to first order
+    for (const TileOp &t : tops) {
+        if (t.kind == T_UR) {  // hi in slots 0-3, the remainder of each entry in slots 4-7
+            for (int k = 0; k < 4; ++k) f[t.param + 4 + k] = (float)(tparams[t.param + k] - (double)f[t.param + k]);
+            continue;
+        }
+        if (t.kind != T_PROJ) continue;
+        const double c = tparams[t.param], s = tparams[t.param + 1];
+        const float cn = (float)c, sn = (float)s;
+        const float cc[3] = {cn, std::nextafter(cn, -2.0f), std::nextafter(cn, 2.0f)};
+        const float sc[3] = {sn, std::nextafter(sn, -2.0f), std::nextafter(sn, 2.0f)};
+        // angle error of (c', s') to first order: c (s' - s) - s (c' - c)
+        auto angle_err = [&](float a, float b) { return std::fabs(c * ((double)b - s) - s * ((double)a - c)); };
+        const double ulp_c = (double)cc[2] - (double)cn, ulp_s = (double)sc[2] - (double)sn;
+        const double lim = std::max(0.5 * (std::fabs(s) * ulp_c + std::fabs(c) * ulp_s), angle_err(cn, sn));
+        int in_band = -1, closest = 0;
+        double in_band_err = 0.0, closest_acc = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            const float a = cc[k / 3], b = sc[k % 3];
+            const double e = angle_err(a, b);
+            if (e > lim) continue;
+            const double na = std::fabs(acc + ((double)a * a + (double)b * b - 1.0));
+            if (na <= kNormBand && (in_band < 0 || e < in_band_err)) {
+                in_band = k;
+                in_band_err = e;
+            }
+            if (k == 0 || na < closest_acc) {
+                closest = k;
+                closest_acc = na;
+            }
+        }
+        const int k = in_band >= 0 ? in_band : closest;
+        const float bc = cc[k / 3], bs = sc[k % 3];
+        acc += (double)bc * bc + (double)bs * bs - 1.0;
+        f[t.param] = bc;
+        f[t.param + 1] = bs;
+    }
+    return f;
+}
+
 }  // namespace svi

@@ -199,7 +199,7 @@ int upload_plan(sv_plan *p)
         SV_OK)
         return rc;
     if (p->dtype == SV_C64) {
-        std::vector<float> f(p->tparams.begin(), p->tparams.end());
+        const std::vector<float> f = svi::tile_params_c64(p->tops, p->tparams);
         rc = up(&p->d_tparams, f.empty() ? nullptr : f.data(), f.size() * sizeof(float));
     } else {
         rc = up(&p->d_tparams, p->tparams.empty() ? nullptr : p->tparams.data(), p->tparams.size() * sizeof(double));
@@ -830,6 +830,7 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
     std::vector<svi::TileStage> stages;
     std::vector<svi::TileOp> tops;
     std::vector<double> prm;
+    std::vector<float> prmf;  // complex64: each plan's parameters as its own upload rounds them
     std::vector<const sv_plan *> seen;
     std::vector<uint64_t> pass_base(count);
     for (size_t i = 0; i < count; ++i) {
@@ -864,6 +865,11 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
         }
         prm.insert(prm.end(), p->tparams.begin(), p->tparams.end());
         prm.resize(tops.size() * svi::kParamStride, 0.0);
+        if (p->dtype == SV_C64) {
+            const std::vector<float> f = svi::tile_params_c64(p->tops, p->tparams);
+            prmf.insert(prmf.end(), f.begin(), f.end());
+            prmf.resize(tops.size() * svi::kParamStride, 0.0f);
+        }
     }
     auto cleanup = [&]() {
         for (auto *d : B->d_items) (void)hipFree(d);
@@ -890,8 +896,7 @@ int sv_batch_create(sv_state *const *states, sv_plan *const *plans, size_t count
     T.stages = upload(stages.data(), stages.size() * sizeof(svi::TileStage));
     T.ops = upload(tops.data(), tops.size() * sizeof(svi::TileOp));
     if (p0->dtype == SV_C64) {
-        std::vector<float> f(prm.begin(), prm.end());
-        T.prm = upload(f.data(), f.size() * sizeof(float));
+        T.prm = upload(prmf.data(), prmf.size() * sizeof(float));
     } else {
         T.prm = upload(prm.data(), prm.size() * sizeof(double));
     }

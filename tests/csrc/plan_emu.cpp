@@ -400,9 +400,10 @@ int emu_dense(const sv_plan &p, uint32_t di, cd *psi, std::vector<int> &rd, std:
 }  // namespace
 
 // When set, complex64 plans run with their parameters rounded to float, as
-// the library uploads them (tile and dense parameters, plain-op matrices and
-// phase angles' cosines and sines are then computed from the rounded values
-// only where the kernels do the same); the arithmetic stays double.
+// the library uploads them (tile parameters as the upload rounds them, dense
+// parameters to nearest, plain-op matrices as hi + lo pairs; phase angles'
+// cosines and sines are computed from the rounded values only where the
+// kernels do the same); the arithmetic stays double.
 static int g_round_params_f32 = 0;
 extern "C" void emu_set_param_rounding(int on) { g_round_params_f32 = on; }
 
@@ -436,11 +437,18 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;
     if (g_round_params_f32 && dtype == SV_C64) {
-        for (double &v : p.tparams) v = (double)(float)v;
+        const std::vector<float> f = tile_params_c64(p.tops, p.tparams);
+        for (size_t k = 0; k < f.size(); ++k) p.tparams[k] = f[k];
+        for (const TileOp &t : p.tops)  // real 2x2 gates apply hi + lo
+            if (t.kind == T_UR)
+                for (int k = 0; k < 4; ++k) p.tparams[t.param + k] += (double)f[t.param + 4 + k];
         for (double &v : p.dparams) v = (double)(float)v;
-        for (PlainOp &op : p.plain)
+        for (PlainOp &op : p.plain)  // plain launches carry their matrix as hi + lo FP32 pairs
             if (op.kind == SV_OP_U)
-                for (double &v : op.m) v = (double)(float)v;
+                for (double &v : op.m) {
+                    const float hi = (float)v;
+                    v = (double)hi + (double)(float)(v - (double)hi);
+                }
     }
     cd *psi = reinterpret_cast<cd *>(psi_io);
     std::vector<int> rd(1ull << n), wr(1ull << n);

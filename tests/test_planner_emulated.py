@@ -218,6 +218,99 @@ def test_six_qubit_dense_blocks_match_oracle(emu, n, seed):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_complex64_real_gates_carry_their_remainder(emu, mode):
+    """A block-encoding call applies the same value-load rotations to the same
+    controlled subspaces every time, so a rotation whose FP32 (cos, sin) has
+    c^2 + s^2 != 1 drains or inflates its subspace by the same fraction in each
+    call.  Complex64 plans carry real 2x2 matrices (tile passes) and every 2x2
+    matrix of a plain launch as hi + lo FP32 pairs: with the parameters rounded
+    as the library uploads them, 6,000 controlled rotations of five repeated
+    angles keep the norm to 2e-11 (hi + lo holds each entry to about 2^-48,
+    3.6e-15, a gate) and match the FP64 result to 1e-12, where the nearest
+    FP32 pairs alone would move the norm by more than 1e-5."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    n = 10
+    angles = [0.483873, -0.240160, 0.159892, 1.047198, -0.0468790]
+    rng = np.random.default_rng(3)
+    c = Circuit(n)
+    defect = 0.0
+    for k in range(6000):
+        th = angles[k % len(angles)]
+        t = int(rng.integers(n))
+        ctl = {(t + 1 + j) % n: int(rng.integers(2)) for j in range(int(rng.integers(0, 4)))}
+        c.ry(t, th, ctl)
+        cs, sn = np.float32(np.cos(th / 2)), np.float32(np.sin(th / 2))
+        defect += abs(float(cs) ** 2 + float(sn) ** 2 - 1.0) / 2 ** len(ctl)
+        if k % 5 == 4:
+            c.x(int(rng.integers(n)), {int(rng.integers(n)): 1} if k % 2 else None)
+    assert defect > 1e-5
+    psi0 = random_state(n, 9)
+    want = osv.run(c, psi0)
+    emu.emu_set_param_rounding.argtypes = [ctypes.c_int]
+    emu.emu_set_param_rounding.restype = None
+    emu.emu_set_param_rounding(1)
+    try:
+        got, _ = run_emu(emu, c, psi0, mode, 10, 4, 0)
+    finally:
+        emu.emu_set_param_rounding(0)
+    drift = abs(np.vdot(got, got).real - 1.0)
+    err = np.max(np.abs(got - want))
+    print(f"mode {mode}: norm drift {drift:.2e}, max error {err:.2e} (nearest pairs: weighted defect {defect:.2e})")
+    assert drift < 2e-11
+    assert err < 1e-12
+
+
+def test_complex64_projector_phases_keep_the_norm(emu):
+    """A QSVT sequence applies one projector phase per step, each with its own
+    angle, and every such gate multiplies the whole state by c^2 + s^2 once
+    (cos, sin) are rounded to FP32.  Rounded to nearest, the factors of 20,000
+    random phases multiply to more than 1e-6 away from 1 (checked below).
+    Complex64 plans round each pair within one ulp of the nearest so that the
+    running product stays next to 1: with the plan's parameters rounded as the
+    library uploads them the norm holds to 1e-7, and no amplitude moves further
+    from the FP64 result than the angle bound allows (half an ulp of each
+    entry, summed over the phases)."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    n, count = 10, 20000
+    rng = np.random.default_rng(11)
+    c = Circuit(n)
+    thetas = rng.uniform(-np.pi, np.pi, count)
+    for k, th in enumerate(thetas):
+        sig = int(rng.integers(n))
+        mask = int(rng.integers(1 << n)) & ~(1 << sig)
+        val = int(rng.integers(1 << n)) & mask
+        c.projphase(sig, mask, val, float(th))
+        if k % 7 == 0:
+            t = int(rng.integers(n))
+            c.x(t, {(t + 1) % n: 1})
+    cn = np.cos(thetas).astype(np.float32).astype(np.float64)
+    sn = np.sin(thetas).astype(np.float32).astype(np.float64)
+    nearest_drift = abs(np.prod(cn * cn + sn * sn) - 1.0)
+    assert nearest_drift > 1e-6
+    ulp_c = np.spacing(np.abs(cn).astype(np.float32)).astype(np.float64)
+    ulp_s = np.spacing(np.abs(sn).astype(np.float32)).astype(np.float64)
+    angle_bound = np.sum(np.maximum(0.5 * (np.abs(np.sin(thetas)) * ulp_c + np.abs(np.cos(thetas)) * ulp_s),
+                                    np.abs(np.cos(thetas) * (sn - np.sin(thetas))
+                                           - np.sin(thetas) * (cn - np.cos(thetas)))))
+    psi0 = random_state(n, 5)
+    want = osv.run(c, psi0)
+    emu.emu_set_param_rounding.argtypes = [ctypes.c_int]
+    emu.emu_set_param_rounding.restype = None
+    emu.emu_set_param_rounding(1)
+    try:
+        got, stats = run_emu(emu, c, psi0, 1, 10, 4, 0)
+    finally:
+        emu.emu_set_param_rounding(0)
+    drift = abs(np.vdot(got, got).real - 1.0)
+    err = np.max(np.abs(got - want))
+    print(f"norm drift {drift:.2e} (nearest rounding {nearest_drift:.2e}); max error {err:.2e}, "
+          f"angle bound {angle_bound:.2e}")
+    assert stats[1] >= 1
+    assert drift < 1e-7
+    assert err < angle_bound + 1e-7
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_complex64_hadamards_keep_the_norm(emu, mode):
     """Uncontrolled Hadamards stored as fp32(1/sqrt 2) would each shrink the
     state by 1.7e-8 (the rounding of 1/sqrt 2, always downward); complex64
