@@ -141,6 +141,18 @@ typedef struct {
                           for complex128), else 1 to 8.  Fewer leave more of the tile to
                           other qubits (fewer passes, each applying more gates); runs
                           shorter than a 128-byte line cost extra HBM traffic         */
+    int split_real;    /* fused, complex64: real 2x2 gates (rotations such as the value
+                          loads of a block encoding, Sec. II.D.2, II.D.3) in tile passes
+                          carry each matrix entry as its FP32 rounding plus the FP32
+                          rounding of the remainder, so their matrices hold the norm to
+                          about 2^-48 instead of 2^-24 (four more FMAs per amplitude
+                          pair).  A gate repeated in every call of a long sequence
+                          otherwise scales its controlled subspace by the same factor
+                          each time.  SV_SPLIT_REAL_AUTO (0): on when the sum over the
+                          plan's real gates of their FP32 matrices' column-norm errors
+                          exceeds 1e-4 (a bound on the norm change they can cause);
+                          SV_SPLIT_REAL_OFF (1); SV_SPLIT_REAL_ON (2).  Plain launches of
+                          complex64 plans always carry their matrices this way       */
 } sv_apply_opts;
 
 #define SV_TILE_LAUNCH_AUTO 0
@@ -157,6 +169,10 @@ typedef struct {
 #define SV_PEEPHOLE_AUTO 0
 #define SV_PEEPHOLE_OFF 1
 #define SV_PEEPHOLE_ON 2
+
+#define SV_SPLIT_REAL_AUTO 0
+#define SV_SPLIT_REAL_OFF 1
+#define SV_SPLIT_REAL_ON 2
 
 typedef struct sv_state sv_state;
 typedef struct sv_plan sv_plan;

@@ -142,17 +142,30 @@ __device__ __forceinline__ void reg_ur(C (&x)[NR], const R *m, uint32_t slotmask
         const int s1 = s | (1 << K);
         const C a = x[s], b = x[s1];
         C r0, r1;
-        if constexpr (sizeof(R) == 8) {
-            r0.x = fma(m[0], a.x, m[1] * b.x);
-            r0.y = fma(m[0], a.y, m[1] * b.y);
-            r1.x = fma(m[2], a.x, m[3] * b.x);
-            r1.y = fma(m[2], a.y, m[3] * b.y);
-        } else {  // hi m[0..3] + lo m[4..7]
-            r0.x = fma(m[0], a.x, fma(m[1], b.x, fma(m[4], a.x, m[5] * b.x)));
-            r0.y = fma(m[0], a.y, fma(m[1], b.y, fma(m[4], a.y, m[5] * b.y)));
-            r1.x = fma(m[2], a.x, fma(m[3], b.x, fma(m[6], a.x, m[7] * b.x)));
-            r1.y = fma(m[2], a.y, fma(m[3], b.y, fma(m[6], a.y, m[7] * b.y)));
-        }
+        r0.x = fma(m[0], a.x, m[1] * b.x);
+        r0.y = fma(m[0], a.y, m[1] * b.y);
+        r1.x = fma(m[2], a.x, m[3] * b.x);
+        r1.y = fma(m[2], a.y, m[3] * b.y);
+        x[s] = r0;
+        x[s1] = r1;
+    }
+}
+
+// T_UR2: the real matrix as hi m[0..3] + lo m[4..7]
+template <int K, int NR, bool FULL, typename C, typename R>
+__device__ __forceinline__ void reg_ur2(C (&x)[NR], const R *m, uint32_t slotmask)
+{
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+        if (s & (1 << K)) continue;
+        if (!FULL && !((slotmask >> s) & 1u)) continue;
+        const int s1 = s | (1 << K);
+        const C a = x[s], b = x[s1];
+        C r0, r1;
+        r0.x = fma(m[0], a.x, fma(m[1], b.x, fma(m[4], a.x, m[5] * b.x)));
+        r0.y = fma(m[0], a.y, fma(m[1], b.y, fma(m[4], a.y, m[5] * b.y)));
+        r1.x = fma(m[2], a.x, fma(m[3], b.x, fma(m[6], a.x, m[7] * b.x)));
+        r1.y = fma(m[2], a.y, fma(m[3], b.y, fma(m[6], a.y, m[7] * b.y)));
         x[s] = r0;
         x[s1] = r1;
     }
@@ -395,12 +408,15 @@ __device__ __forceinline__ void tile_compute(typename CTT<R>::T (&x)[1 << RB],
                 for (int j = 0; j < 8; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_u, x, m, op.slotmask)
             } else if (op.kind == T_UR) {
-                // complex64: the FP32 rounding (hi) and its remainder (lo)
-                constexpr int NM = sizeof(R) == 8 ? 4 : 8;
-                R m[NM];
+                R m[4];
 #pragma unroll
-                for (int j = 0; j < NM; ++j) m[j] = pk[j];
+                for (int j = 0; j < 4; ++j) m[j] = pk[j];
                 SV_SLOT_DISPATCH(reg_ur, x, m, op.slotmask)
+            } else if (op.kind == T_UR2) {  // complex64 plans only
+                R m[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) m[j] = pk[j];
+                SV_SLOT_DISPATCH(reg_ur2, x, m, op.slotmask)
             } else if (op.kind == T_X) {
                 SV_SLOT_DISPATCH(reg_x, x, op.slotmask)
             } else if (op.kind == T_PHASE) {

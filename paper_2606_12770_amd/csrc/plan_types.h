@@ -39,7 +39,12 @@ enum : uint8_t {
     T_SWAP = 6,   // permutation: exchange local bits a and b
     T_XFLIP = 7,  // permutation: flip local bit a
     T_UR = 8,     // real 2x2 matrix on register slot bit `slot` (4 reals)
+    T_UR2 = 9,    // the same, complex64 only, as hi (reals 0-3) + lo (reals 4-7)
 };
+
+// SV_SPLIT_REAL_AUTO splits the real gates of a complex64 plan when the sum of
+// their FP32 matrices' column-norm errors exceeds this bound.
+constexpr double kSplitRealBound = 1e-4;
 
 // Conditions of register-level ops are pre-split for the stage they run in:
 //   slotmask bit s : the register-slot part of the condition holds for slot s

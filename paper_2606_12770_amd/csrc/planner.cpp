@@ -316,6 +316,25 @@ int exact_hadamard_pairs(std::vector<OpInfo> &ops)
     return (int)(at.size() / 2);
 }
 
+// Bound on how far the FP32 rounding of the plan's real 2x2 gates can move
+// the norm: for each gate, the largest change of a column's squared norm when
+// its entries are rounded to nearest, summed over the gates.
+double real_gate_norm_bound(const std::vector<OpInfo> &ops)
+{
+    double sum = 0.0;
+    for (const OpInfo &o : ops) {
+        if (o.kind != SV_OP_U || o.m[1] != 0.0 || o.m[3] != 0.0 || o.m[5] != 0.0 || o.m[7] != 0.0) continue;
+        double d = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            const double a = o.m[2 * c], b = o.m[2 * c + 4];
+            const double fa = (float)a, fb = (float)b;
+            d = std::max(d, std::fabs((fa * fa + fb * fb) - (a * a + b * b)));
+        }
+        sum += d;
+    }
+    return sum;
+}
+
 // ---- dense k-qubit blocks -------------------------------------------------
 // The block matrix of a run of ops whose qubits (targets and controls) lie in
 // blk[0..dk-1] (ascending): column j is the run applied to the basis vector
@@ -441,6 +460,10 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         err = "coalesce_qubits must be 0 (automatic) or 1 to 8";
         return SV_EINVAL;
     }
+    if (opts.split_real < SV_SPLIT_REAL_AUTO || opts.split_real > SV_SPLIT_REAL_ON) {
+        err = "split_real must be SV_SPLIT_REAL_AUTO, _OFF or _ON";
+        return SV_EINVAL;
+    }
     if (opts.dense_qubits != 0 && opts.dense_qubits != 5 && opts.dense_qubits != 6) {
         err = "dense_qubits must be 0, 5 or 6";
         return SV_EINVAL;
@@ -489,6 +512,9 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
     info = fold_single_qubit_runs(info);
     n_ops = info.size();
     if (p->dtype == SV_C64) exact_hadamard_pairs(info);
+    const bool split_real = p->dtype == SV_C64 &&
+                            (opts.split_real == SV_SPLIT_REAL_ON ||
+                             (opts.split_real == SV_SPLIT_REAL_AUTO && real_gate_norm_bound(info) > kSplitRealBound));
 
     const int nthr = b - rb;
     // lowest qubits resident in every pass (each tile's runs of contiguous
@@ -1116,7 +1142,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 t.slot = (uint8_t)(it - cur_rs.begin());
                 if (o.kind == SV_OP_U) {
                     const bool real = o.m[1] == 0.0 && o.m[3] == 0.0 && o.m[5] == 0.0 && o.m[7] == 0.0;
-                    t.kind = real ? T_UR : T_U;
+                    t.kind = real ? (split_real ? T_UR2 : T_UR) : T_U;
                     double v[8];
                     if (real) {
                         for (int k = 0; k < 4; ++k) v[k] = o.m[2 * k];
@@ -1245,20 +1271,20 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
 // rounding's bound (half an ulp of each entry), and most pairs keep their
 // nearest rounding.
 // A real 2x2 gate (the value-load rotations of the block encoding, Sec.
-// II.D.1-II.D.3) applies the same matrix in every call of the sequence to its
+// II.D.2, II.D.3) applies the same matrix in every call of the sequence to its
 // controlled subspace; rounded to FP32 its columns' norms differ from 1 by up
 // to 5e-8 and that subspace gains or loses the same fraction in every call
-// (7e-5 over the second-order run, measured with FP64 arithmetic).  Such
-// gates therefore carry each entry as the FP32 rounding (hi, slots 0-3) plus
-// the FP32 rounding of the remainder (lo, slots 4-7), and the kernels apply
-// hi + lo.  All other parameters round to nearest.
+// (7e-5 over the second-order run, measured with FP64 arithmetic).  Gates the
+// planner marked T_UR2 therefore carry each entry as the FP32 rounding (hi,
+// slots 0-3) plus the FP32 rounding of the remainder (lo, slots 4-7), and the
+// kernels apply hi + lo.  All other parameters round to nearest.
 std::vector<float> tile_params_c64(const std::vector<TileOp> &tops, const std::vector<double> &tparams)
 {
     constexpr double kNormBand = 1e-7;
     std::vector<float> f(tparams.begin(), tparams.end());
     double acc = 0.0;  // sum of (factor - 1): the log of the running product, to first order
     for (const TileOp &t : tops) {
-        if (t.kind == T_UR) {  // hi in slots 0-3, the remainder of each entry in slots 4-7
+        if (t.kind == T_UR2) {  // hi in slots 0-3, the remainder of each entry in slots 4-7
             for (int k = 0; k < 4; ++k) f[t.param + 4 + k] = (float)(tparams[t.param + k] - (double)f[t.param + k]);
             continue;
         }

@@ -203,16 +203,16 @@ struct Gen {
             }
             break;
         }
-        case T_UR: {
-            // complex64 carries the matrix as hi (m0..m3) + lo (m4..m7)
-            const int nm = dbl ? 4 : 8;
+        case T_UR:
+        case T_UR2: {  // T_UR2 (complex64): hi m0..m3 + lo m4..m7
+            const bool two = t.kind == T_UR2;
             o << "    const R m0 = " << prm(t.param, 0);
-            for (int j = 1; j < nm; ++j) o << ", m" << j << " = " << prm(t.param, j);
+            for (int j = 1; j < (two ? 8 : 4); ++j) o << ", m" << j << " = " << prm(t.param, j);
             o << ";\n";
             for (int s = 0; s < NR; ++s) {
                 if (s & (1 << K) || !((t.slotmask >> s) & 1u)) continue;
-                o << "    gur(x[" << s << "], x[" << (s | (1 << K)) << "], m0, m1, m2, m3"
-                  << (dbl ? "" : ", m4, m5, m6, m7") << ");\n";
+                o << "    " << (two ? "gur2" : "gur") << "(x[" << s << "], x[" << (s | (1 << K))
+                  << "], m0, m1, m2, m3" << (two ? ", m4, m5, m6, m7" : "") << ");\n";
             }
             break;
         }
@@ -407,24 +407,23 @@ std::string jit_preamble(int dtype)
          "  const C a = x0, b = x1;\n"
          "  x0 = row2(m0, m1, m2, m3, a, b);\n"
          "  x1 = row2(m4, m5, m6, m7, a, b);\n}\n";
-    if (dbl)
-        o << "__device__ __forceinline__ void gur(C &x0, C &x1, R m0, R m1, R m2, R m3) {\n"
-             "  const C a = x0, b = x1;\n"
-             "  C r0, r1;\n"
-             "  r0.x = FMA(m0, a.x, m1 * b.x);\n"
-             "  r0.y = FMA(m0, a.y, m1 * b.y);\n"
-             "  r1.x = FMA(m2, a.x, m3 * b.x);\n"
-             "  r1.y = FMA(m2, a.y, m3 * b.y);\n"
-             "  x0 = r0;\n  x1 = r1;\n}\n";
-    else  // hi + lo
-        o << "__device__ __forceinline__ void gur(C &x0, C &x1, R m0, R m1, R m2, R m3, R l0, R l1, R l2, R l3) {\n"
-             "  const C a = x0, b = x1;\n"
-             "  C r0, r1;\n"
-             "  r0.x = FMA(m0, a.x, FMA(m1, b.x, FMA(l0, a.x, l1 * b.x)));\n"
-             "  r0.y = FMA(m0, a.y, FMA(m1, b.y, FMA(l0, a.y, l1 * b.y)));\n"
-             "  r1.x = FMA(m2, a.x, FMA(m3, b.x, FMA(l2, a.x, l3 * b.x)));\n"
-             "  r1.y = FMA(m2, a.y, FMA(m3, b.y, FMA(l2, a.y, l3 * b.y)));\n"
-             "  x0 = r0;\n  x1 = r1;\n}\n";
+    o << "__device__ __forceinline__ void gur(C &x0, C &x1, R m0, R m1, R m2, R m3) {\n"
+         "  const C a = x0, b = x1;\n"
+         "  C r0, r1;\n"
+         "  r0.x = FMA(m0, a.x, m1 * b.x);\n"
+         "  r0.y = FMA(m0, a.y, m1 * b.y);\n"
+         "  r1.x = FMA(m2, a.x, m3 * b.x);\n"
+         "  r1.y = FMA(m2, a.y, m3 * b.y);\n"
+         "  x0 = r0;\n  x1 = r1;\n}\n";
+    // hi (m) + lo (l)
+    o << "__device__ __forceinline__ void gur2(C &x0, C &x1, R m0, R m1, R m2, R m3, R l0, R l1, R l2, R l3) {\n"
+         "  const C a = x0, b = x1;\n"
+         "  C r0, r1;\n"
+         "  r0.x = FMA(m0, a.x, FMA(m1, b.x, FMA(l0, a.x, l1 * b.x)));\n"
+         "  r0.y = FMA(m0, a.y, FMA(m1, b.y, FMA(l0, a.y, l1 * b.y)));\n"
+         "  r1.x = FMA(m2, a.x, FMA(m3, b.x, FMA(l2, a.x, l3 * b.x)));\n"
+         "  r1.y = FMA(m2, a.y, FMA(m3, b.y, FMA(l2, a.y, l3 * b.y)));\n"
+         "  x0 = r0;\n  x1 = r1;\n}\n";
     o << "__device__ __forceinline__ void proj(C &x, R c, R si) {\n"
          "  const C a = x;\n"
          "  C r;\n"

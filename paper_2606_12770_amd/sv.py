@@ -24,6 +24,7 @@ SV_PLAIN_SPLIT_AUTO, SV_PLAIN_SPLIT_OFF = 0, 1
 SV_COMPILE_AUTO, SV_COMPILE_OFF, SV_COMPILE_ON = 0, 1, 2
 SV_DENSE_AUTO = -1
 SV_PEEPHOLE_AUTO, SV_PEEPHOLE_OFF, SV_PEEPHOLE_ON = 0, 1, 2
+SV_SPLIT_REAL_AUTO, SV_SPLIT_REAL_OFF, SV_SPLIT_REAL_ON = 0, 1, 2
 
 EXPORTED = [
     "sv_alloc", "sv_free", "sv_info", "sv_apply_circuit", "sv_plan_create", "sv_plan_free",
@@ -43,7 +44,7 @@ class sv_apply_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tile_qubits", ctypes.c_int), ("reg_qubits", ctypes.c_int),
                 ("dense_min_ops", ctypes.c_int), ("tile_launch", ctypes.c_int), ("plain_split", ctypes.c_int),
                 ("compile", ctypes.c_int), ("dense_bf16", ctypes.c_int), ("peephole", ctypes.c_int),
-                ("dense_qubits", ctypes.c_int), ("coalesce_qubits", ctypes.c_int)]
+                ("dense_qubits", ctypes.c_int), ("coalesce_qubits", ctypes.c_int), ("split_real", ctypes.c_int)]
 
 
 class sv_plan_info(ctypes.Structure):
@@ -116,9 +117,9 @@ def _dp(a):
 
 
 def _opts(mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0, tile_launch=0, plain_split=0, compile=0,
-          dense_bf16=0, peephole=0, dense_qubits=0, coalesce_qubits=0):
+          dense_bf16=0, peephole=0, dense_qubits=0, coalesce_qubits=0, split_real=0):
     return sv_apply_opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile, dense_bf16,
-                         peephole, dense_qubits, coalesce_qubits)
+                         peephole, dense_qubits, coalesce_qubits, split_real)
 
 
 # ---- the C entry points under their own names -------------------------------
@@ -161,10 +162,10 @@ def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_
 
 def sv_plan_create(n_qubits, dtype, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
                    tile_launch=0, plain_split=0, compile=0, dense_bf16=0, peephole=0, dense_qubits=0,
-                   coalesce_qubits=0):
+                   coalesce_qubits=0, split_real=0):
     ops, params = _ops_params(ops, params)
     o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile, dense_bf16, peephole,
-              dense_qubits, coalesce_qubits)
+              dense_qubits, coalesce_qubits, split_real)
     out = ctypes.c_void_p()
     _check(load_library().sv_plan_create(n_qubits, dtype, ops.ctypes.data, len(ops), _dp(params), len(params),
                                          ctypes.byref(o), ctypes.byref(out)))

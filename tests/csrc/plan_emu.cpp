@@ -284,7 +284,7 @@ int emu_tile(const sv_plan &p, uint32_t pi, cd *psi, std::vector<int> &rd, std::
                         if (op.kind == T_U) {
                             a = cd(prm[0], prm[1]) * a0 + cd(prm[2], prm[3]) * b0;
                             bb = cd(prm[4], prm[5]) * a0 + cd(prm[6], prm[7]) * b0;
-                        } else if (op.kind == T_UR) {
+                        } else if (op.kind == T_UR || op.kind == T_UR2) {
                             a = prm[0] * a0 + prm[1] * b0;
                             bb = prm[2] * a0 + prm[3] * b0;
                         } else if (op.kind == T_X) {
@@ -419,6 +419,10 @@ extern "C" void emu_set_dense_qubits(int v) { g_dense_qubits = v; }
 static int g_coalesce_qubits = 0;
 extern "C" void emu_set_coalesce_qubits(int v) { g_coalesce_qubits = v; }
 
+// sv_apply_opts.split_real of the plans emu_run builds (SV_SPLIT_REAL_AUTO by default).
+static int g_split_real = SV_SPLIT_REAL_AUTO;
+extern "C" void emu_set_split_real(int v) { g_split_real = v; }
+
 // Plans the op list and runs the plan on psi_io (interleaved re, im).  stats,
 // when given, receives 7 entries: launches, tile passes, register stages,
 // algorithmic bytes, ops split to plain launches, ops inside gate runs, ops
@@ -433,14 +437,15 @@ extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const d
     o.peephole = g_peephole;
     o.dense_qubits = g_dense_qubits;
     o.coalesce_qubits = g_coalesce_qubits;
+    o.split_real = g_split_real;
     std::string err;
     int rc = build_plan(&p, ops, n_ops, params, o, err);
     if (rc != SV_OK) return rc;
     if (g_round_params_f32 && dtype == SV_C64) {
         const std::vector<float> f = tile_params_c64(p.tops, p.tparams);
         for (size_t k = 0; k < f.size(); ++k) p.tparams[k] = f[k];
-        for (const TileOp &t : p.tops)  // real 2x2 gates apply hi + lo
-            if (t.kind == T_UR)
+        for (const TileOp &t : p.tops)  // split real 2x2 gates apply hi + lo
+            if (t.kind == T_UR2)
                 for (int k = 0; k < 4; ++k) p.tparams[t.param + k] += (double)f[t.param + 4 + k];
         for (double &v : p.dparams) v = (double)(float)v;
         for (PlainOp &op : p.plain)  // plain launches carry their matrix as hi + lo FP32 pairs

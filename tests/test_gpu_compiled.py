@@ -24,9 +24,10 @@ from tests.gpu_util import assert_c64_close, require_gpu
 pytestmark = pytest.mark.gpu
 
 
-def run(sv, circ, psi0, dtype, compile_mode, b=0, rb=0):
+def run(sv, circ, psi0, dtype, compile_mode, b=0, rb=0, split_real=0):
     ops, params = circ.arrays()
-    plan = sv.sv_plan_create(circ.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile_mode)
+    plan = sv.sv_plan_create(circ.n, dtype, ops, params, sv.SV_MODE_FUSED, b, rb, compile=compile_mode,
+                             split_real=split_real)
     info = sv.sv_plan_get_info(plan)
     st = sv.State(circ.n, dtype, psi0)
     sv.sv_plan_execute(plan, st.h, 1)
@@ -55,6 +56,53 @@ def test_compiled_equals_generic_and_oracle(n, b, rb, dtype):
         assert np.max(np.abs(got - want)) < 1e-12
     else:
         assert_c64_close(got, want, len(c), what=f"compiled n={n}")
+
+
+@pytest.mark.parametrize("n,b,rb", [(13, 12, 4), (16, 13, 5), (19, 12, 4)])
+def test_split_real_gates_compiled_equal_generic(n, b, rb):
+    """SV_SPLIT_REAL_ON (complex64 real 2x2 gates as hi + lo FP32 entries):
+    compiled passes and the generic kernel give bit-identical states, both
+    within the complex64 bar of the oracle."""
+    sv = require_gpu()
+    c = random_mixed_circuit(n, 400, seed=5 * n + b, max_ctrl=6)
+    psi0 = random_state(n, n + 3)
+    want = osv.run(c, psi0)
+    got, info = run(sv, c, psi0, 0, sv.SV_COMPILE_ON, b, rb, sv.SV_SPLIT_REAL_ON)
+    gen, _ = run(sv, c, psi0, 0, sv.SV_COMPILE_OFF, b, rb, sv.SV_SPLIT_REAL_ON)
+    assert info["n_compiled_kernels"] > 0
+    assert np.array_equal(got.view(np.uint64), gen.view(np.uint64))
+    assert_c64_close(got, want, len(c), what=f"split real n={n}")
+
+
+def test_split_real_gates_keep_the_norm_of_a_rotation_ladder():
+    """20,000 controlled rotations of five repeated angles (a value-load
+    pattern) on 14 qubits in complex64.  With nearest FP32 entries
+    (SV_SPLIT_REAL_OFF) each rotation scales its subspace by the same
+    c^2 + s^2 every time and the norm drifts systematically; with hi + lo
+    entries (SV_SPLIT_REAL_ON) only the FP32 arithmetic's drift is left, less
+    than a fifth of it, and the amplitudes match the oracle at least as well."""
+    sv = require_gpu()
+    n = 14
+    angles = [0.483873, -0.240160, 0.159892, 1.047198, -0.0468790]
+    rng = np.random.default_rng(21)
+    c = Circuit(n)
+    for k in range(20000):
+        t = int(rng.integers(n))
+        ctl = {(t + 1 + j) % n: int(rng.integers(2)) for j in range(int(rng.integers(0, 3)))}
+        c.ry(t, angles[k % len(angles)], ctl)
+        if k % 5 == 4:
+            xt = int(rng.integers(n))
+            c.x(xt, {(xt + 1 + int(rng.integers(n - 1))) % n: 1})
+    psi0 = random_state(n, 22)
+    want = osv.run(c, psi0)
+    res = {}
+    for split in (sv.SV_SPLIT_REAL_OFF, sv.SV_SPLIT_REAL_ON):
+        got, _ = run(sv, c, psi0, 0, sv.SV_COMPILE_AUTO, 12, 4, split)
+        res[split] = (abs(np.vdot(got, got).real - 1.0), np.max(np.abs(got - want)))
+        print(f"split_real {split}: norm drift {res[split][0]:.2e}, max error {res[split][1]:.2e}", flush=True)
+    assert res[sv.SV_SPLIT_REAL_OFF][0] > 1e-5
+    assert res[sv.SV_SPLIT_REAL_ON][0] < 0.2 * res[sv.SV_SPLIT_REAL_OFF][0]
+    assert res[sv.SV_SPLIT_REAL_ON][1] <= res[sv.SV_SPLIT_REAL_OFF][1]
 
 
 @pytest.mark.parametrize("dtype", [0, 1])

@@ -217,47 +217,85 @@ def test_six_qubit_dense_blocks_match_oracle(emu, n, seed):
     assert np.max(np.abs(got - want)) < 1e-12
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_complex64_real_gates_carry_their_remainder(emu, mode):
-    """A block-encoding call applies the same value-load rotations to the same
-    controlled subspaces every time, so a rotation whose FP32 (cos, sin) has
-    c^2 + s^2 != 1 drains or inflates its subspace by the same fraction in each
-    call.  Complex64 plans carry real 2x2 matrices (tile passes) and every 2x2
-    matrix of a plain launch as hi + lo FP32 pairs: with the parameters rounded
-    as the library uploads them, 6,000 controlled rotations of five repeated
-    angles keep the norm to 2e-11 (hi + lo holds each entry to about 2^-48,
-    3.6e-15, a gate) and match the FP64 result to 1e-12, where the nearest
-    FP32 pairs alone would move the norm by more than 1e-5."""
+def _rotation_ladder(count, seed=3):
+    """Controlled rotations of five repeated angles (a value-load pattern),
+    with an X now and then; returns the circuit and the bound the planner's
+    SV_SPLIT_REAL_AUTO compares with 1e-4 (per gate, the largest change of a
+    column's squared norm under nearest FP32 rounding)."""
     from paper_2606_12770_amd.circuits.ir import Circuit
     n = 10
     angles = [0.483873, -0.240160, 0.159892, 1.047198, -0.0468790]
-    rng = np.random.default_rng(3)
+    rng = np.random.default_rng(seed)
     c = Circuit(n)
-    defect = 0.0
-    for k in range(6000):
+    bound = 0.0
+    for k in range(count):
         th = angles[k % len(angles)]
         t = int(rng.integers(n))
         ctl = {(t + 1 + j) % n: int(rng.integers(2)) for j in range(int(rng.integers(0, 4)))}
         c.ry(t, th, ctl)
         cs, sn = np.float32(np.cos(th / 2)), np.float32(np.sin(th / 2))
-        defect += abs(float(cs) ** 2 + float(sn) ** 2 - 1.0) / 2 ** len(ctl)
+        bound += abs(float(cs) ** 2 + float(sn) ** 2 - 1.0)
         if k % 5 == 4:
-            c.x(int(rng.integers(n)), {int(rng.integers(n)): 1} if k % 2 else None)
-    assert defect > 1e-5
-    psi0 = random_state(n, 9)
-    want = osv.run(c, psi0)
+            xt = int(rng.integers(n))
+            c.x(xt, {(xt + 1 + int(rng.integers(n - 1))) % n: 1} if k % 2 else None)
+    return c, bound
+
+
+def _run_rounded(emu, c, psi0, mode, split):
     emu.emu_set_param_rounding.argtypes = [ctypes.c_int]
     emu.emu_set_param_rounding.restype = None
+    emu.emu_set_split_real.argtypes = [ctypes.c_int]
+    emu.emu_set_split_real.restype = None
     emu.emu_set_param_rounding(1)
+    emu.emu_set_split_real(split)
     try:
         got, _ = run_emu(emu, c, psi0, mode, 10, 4, 0)
     finally:
         emu.emu_set_param_rounding(0)
-    drift = abs(np.vdot(got, got).real - 1.0)
-    err = np.max(np.abs(got - want))
-    print(f"mode {mode}: norm drift {drift:.2e}, max error {err:.2e} (nearest pairs: weighted defect {defect:.2e})")
-    assert drift < 2e-11
-    assert err < 1e-12
+        emu.emu_set_split_real(0)
+    return got
+
+
+def test_complex64_real_gates_carry_their_remainder(emu):
+    """A block-encoding call applies the same value-load rotations to the same
+    controlled subspaces every time, so a rotation whose FP32 (cos, sin) has
+    c^2 + s^2 != 1 drains or inflates its subspace by the same fraction in each
+    call.  With the parameters rounded as the library uploads them, 6,000
+    controlled rotations of five repeated angles: tile passes with
+    SV_SPLIT_REAL_ON (hi + lo entries, each to about 2^-48, 3.6e-15, a gate)
+    and plain launches (always hi + lo) keep the norm to 2e-11 and match the
+    FP64 result to 1e-12; with SV_SPLIT_REAL_OFF the nearest FP32 entries move
+    the norm by more than 1e-6."""
+    c, bound = _rotation_ladder(6000)
+    psi0 = random_state(c.n, 9)
+    want = osv.run(c, psi0)
+    for mode, split, exact in ((1, 2, True), (0, 0, True), (1, 1, False)):
+        got = _run_rounded(emu, c, psi0, mode, split)
+        drift = abs(np.vdot(got, got).real - 1.0)
+        err = np.max(np.abs(got - want))
+        print(f"mode {mode} split_real {split}: norm drift {drift:.2e}, max error {err:.2e}")
+        if exact:
+            assert drift < 2e-11
+            assert err < 1e-12
+        else:
+            assert drift > 1e-6
+
+
+def test_split_real_auto_follows_the_norm_bound(emu):
+    """SV_SPLIT_REAL_AUTO splits the real gates of a complex64 plan exactly when
+    the summed FP32 column-norm errors of its real gates exceed 1e-4: the
+    emulated state is then bit for bit that of SV_SPLIT_REAL_ON, else that of
+    SV_SPLIT_REAL_OFF."""
+    for count in (300, 12000):
+        c, bound = _rotation_ladder(count, seed=4)
+        psi0 = random_state(c.n, 10)
+        auto = _run_rounded(emu, c, psi0, 1, 0)
+        on = _run_rounded(emu, c, psi0, 1, 2)
+        off = _run_rounded(emu, c, psi0, 1, 1)
+        assert not np.array_equal(on, off)
+        print(f"{count} rotations: bound {bound:.2e}")
+        assert np.array_equal(auto, on if bound > 1e-4 else off)
+        assert (bound > 1e-4) == (count == 12000)
 
 
 def test_complex64_projector_phases_keep_the_norm(emu):
@@ -318,7 +356,8 @@ def test_complex64_hadamards_keep_the_norm(emu, mode):
     parameters rounded to float as the library uploads them, 4,000 Hadamards
     (interleaved with CNOTs so that none fold together) keep the norm to
     1e-12, where the rounded matrix alone would lose 1.4e-4; with an odd
-    count, the one left over costs its single 3.4e-8."""
+    count, the one left over costs its single 3.4e-8 in a tile pass (a plain
+    launch carries its matrix as hi + lo and loses nothing)."""
     from paper_2606_12770_amd.circuits.ir import Circuit
     n = 12
     emu.emu_set_param_rounding.argtypes = [ctypes.c_int]
