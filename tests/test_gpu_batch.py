@@ -13,6 +13,8 @@
   fork from and join back to one stream, one graph): bit-identical to each
   plan run alone, graph and eager alike, with plain launches among the steps,
   states outside an arena, and plans freed before the batch runs.
+* Complex64 plans whose real gates carry hi + lo entries (split_real) run
+  in both batch forms bit-identical to each plan alone.
 * The 64-instance batched workload itself (21-28 qubits, complex64, d = 3):
   every instance's system amplitudes against the oracle's singular-value
   transform of its own L, amplitude by amplitude.
@@ -293,3 +295,42 @@ def test_concurrent_batch_of_compiled_plans(dtype, use_graph):
     sv.sv_batch_free(batch)
     for st in states:
         sv.sv_free(st)
+
+
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_batches_of_split_real_plans(concurrent):
+    sv = require_gpu()
+    circs, inits = _mixed_batch(20 + concurrent)
+    plans = []
+    for c in circs:
+        ops, params = c.arrays()
+        if concurrent:
+            plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, compile=sv.SV_COMPILE_ON,
+                                          split_real=sv.SV_SPLIT_REAL_ON))
+        else:
+            plans.append(sv.sv_plan_create(c.n, sv.SV_C64, ops, params, sv.SV_MODE_FUSED, 12, 4,
+                                          plain_split=sv.SV_PLAIN_SPLIT_OFF, split_real=sv.SV_SPLIT_REAL_ON))
+    refs = []
+    for c, v, p in zip(circs, inits, plans):
+        ref = sv.sv_alloc(c.n, sv.SV_C64, v)
+        sv.sv_plan_execute(p, ref, 1)
+        refs.append(sv.sv_amplitudes(ref))
+        sv.sv_free(ref)
+    states = (sv.sv_alloc_batch([c.n for c in circs], sv.SV_C64) if not concurrent
+              else [sv.sv_alloc(c.n, sv.SV_C64) for c in circs])
+    for st, v in zip(states, inits):
+        sv.sv_set_amplitudes(st, v, 0)
+    batch = sv.sv_batch_create(states, plans, False, ONE_GROUP if not concurrent else 0)
+    sv.sv_batch_execute(batch, 1)
+    for i, (c, v, st) in enumerate(zip(circs, inits, states)):
+        got = sv.sv_amplitudes(st)
+        print(f"split-real instance {i}: n={c.n} concurrent={concurrent} "
+              f"maxabs={np.max(np.abs(got - refs[i])):.1e}", flush=True)
+        assert np.array_equal(got.view(np.uint64), refs[i].view(np.uint64))
+        if c.n <= 17:
+            assert_c64_close(got, osv.run(c, v), len(c), what=f"split-real batch instance {i}")
+    sv.sv_batch_free(batch)
+    for st in states:
+        sv.sv_free(st)
+    for p in plans:
+        sv.sv_plan_free(p)
