@@ -62,6 +62,14 @@ extern "C" {
  *                                                    ctrl_* is the projector condition
  * The elementary gate set of Sec. III.F.2 (Toffoli, CNOT, H, X, R_Y, S, S^dagger and
  * their multi-controlled forms) maps onto U, X, RY and PHASE.
+ *
+ * Complex64 plans compute in FP32 and choose the FP32 form of each parameter so
+ * that long sequences keep the norm: uncontrolled Hadamard-type matrices in
+ * pairs of exactly representable scaled matrices whose scales multiply to 1;
+ * projector phases rounded, within an ulp of the nearest and no further in
+ * angle, so that their norm factors multiply to 1 within 1e-7; real 2x2
+ * matrices in tile passes as hi + lo pairs when sv_apply_opts.split_real asks;
+ * the 2x2 matrices of plain launches always as hi + lo pairs.
  */
 #define SV_OP_U          0
 #define SV_OP_X          1
