@@ -7,15 +7,20 @@
 //
 // Case file layout (little-endian): int32 n, dtype, mode, b, rb, dense_min_ops;
 // uint64 n_ops, n_params; n_ops 40-byte op records; n_params doubles; 2^n
-// complex128 amplitudes (interleaved re, im).
+// complex128 amplitudes (interleaved re, im).  SAN_ROUND_PARAMS=1 in the
+// environment rounds complex64 parameters as the library uploads them, and
+// SAN_SPLIT_REAL sets sv_apply_opts.split_real.
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "sv.h"
 
 extern "C" int emu_run(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int mode, int b,
                        int rb, double *psi, uint64_t *stats, int dense_min_ops);
+extern "C" void emu_set_param_rounding(int on);
+extern "C" void emu_set_split_real(int v);
 
 int main(int argc, char **argv)
 {
@@ -37,6 +42,8 @@ int main(int argc, char **argv)
     if (cnt[1] && std::fread(params.data(), sizeof(double), cnt[1], f) != cnt[1]) return 2;
     if (std::fread(psi.data(), sizeof(double), psi.size(), f) != psi.size()) return 2;
     std::fclose(f);
+    if (const char *v = std::getenv("SAN_ROUND_PARAMS")) emu_set_param_rounding(std::atoi(v));
+    if (const char *v = std::getenv("SAN_SPLIT_REAL")) emu_set_split_real(std::atoi(v));
     uint64_t stats[7] = {0, 0, 0, 0, 0, 0, 0};
     const int rc = emu_run(n, hdr[1], ops.data(), ops.size(), params.data(), hdr[2], hdr[3], hdr[4], psi.data(),
                            stats, hdr[5]);

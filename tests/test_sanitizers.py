@@ -41,7 +41,7 @@ def drivers():
     return plan, orc
 
 
-def run_case(exe, circ, psi0, dtype=0, mode=1, b=12, rb=4, dense_min_ops=0):
+def run_case(exe, circ, psi0, dtype=0, mode=1, b=12, rb=4, dense_min_ops=0, env=None):
     ops, params = circ.arrays()
     with tempfile.TemporaryDirectory() as td:
         case, out = os.path.join(td, "case.bin"), os.path.join(td, "out.bin")
@@ -51,7 +51,7 @@ def run_case(exe, circ, psi0, dtype=0, mode=1, b=12, rb=4, dense_min_ops=0):
             np.ascontiguousarray(ops).tofile(f)
             np.ascontiguousarray(params, dtype=np.float64).tofile(f)
             np.ascontiguousarray(psi0, dtype=np.complex128).tofile(f)
-        r = subprocess.run([exe, case, out], capture_output=True, text=True, env=ENV)
+        r = subprocess.run([exe, case, out], capture_output=True, text=True, env=dict(ENV, **(env or {})))
         assert r.returncode == 0, f"{os.path.basename(exe)} exited {r.returncode}\n{r.stderr[-4000:]}"
         assert "runtime error" not in r.stderr, r.stderr[-4000:]
         return np.fromfile(out, dtype=np.complex128)
@@ -91,3 +91,28 @@ def test_carleman_gate_runs_clean_under_sanitizers(drivers):
     want = osv.run(circ, psi0)
     got = run_case(drivers[0], circ, psi0, dtype=0, b=12, rb=4)
     assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_complex64_parameter_rounding_clean_under_sanitizers(drivers):
+    """The complex64 parameter conversion (projector phases rounded to a
+    balanced product, real gates split into hi + lo) on a circuit with both,
+    in the sanitized planner: the emulated state, computed in FP64 from the
+    rounded parameters, stays within FP32 parameter error of the oracle."""
+    from paper_2606_12770_amd.circuits.ir import Circuit
+    rng = np.random.default_rng(8)
+    n = 13
+    c = random_mixed_circuit(n, 200, seed=9, max_ctrl=4)
+    for k in range(300):
+        sig = int(rng.integers(n))
+        mask = int(rng.integers(1 << n)) & ~(1 << sig)
+        c.projphase(sig, mask, int(rng.integers(1 << n)) & mask, float(rng.uniform(-np.pi, np.pi)))
+        t = int(rng.integers(n))
+        c.ry(t, float(rng.uniform(-np.pi, np.pi)), {(t + 1) % n: 1})
+    psi0 = random_state(n, 4)
+    want = osv.run(c, psi0)
+    for split in ("1", "2"):
+        got = run_case(drivers[0], c, psi0, dtype=0, b=12, rb=4,
+                       env={"SAN_ROUND_PARAMS": "1", "SAN_SPLIT_REAL": split})
+        err = np.max(np.abs(got - want))
+        print(f"split_real {split}: max error {err:.2e}")
+        assert err < 1e-5
