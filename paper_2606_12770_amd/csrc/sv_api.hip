@@ -384,6 +384,8 @@ int sv_plan_create(int n_qubits, int dtype, const sv_op *ops, size_t n_ops, cons
     if (o.dense_bf16 != 0 && o.dense_bf16 != 1) return fail(SV_EINVAL, "dense_bf16 must be 0 or 1");
     if (o.peephole != SV_PEEPHOLE_AUTO && o.peephole != SV_PEEPHOLE_OFF && o.peephole != SV_PEEPHOLE_ON)
         return fail(SV_EINVAL, "peephole must be SV_PEEPHOLE_AUTO, _OFF or _ON");
+    if (o.split_real < SV_SPLIT_REAL_AUTO || o.split_real > SV_SPLIT_REAL_ON)
+        return fail(SV_EINVAL, "split_real must be SV_SPLIT_REAL_AUTO, _OFF or _ON");
     int rc = validate_ops(n_qubits, ops, n_ops, params, n_params);
     if (rc != SV_OK) return rc;
     int dev = 0;

@@ -135,6 +135,22 @@ def test_out_of_range_ops_are_refused_before_any_launch():
     assert _plan_create_rc(n, op(ir.U, target=3, param=0), params) != sv.SV_EINVAL
 
 
+def test_unknown_option_values_are_refused_on_the_host():
+    from paper_2606_12770_amd.circuits import ir
+    lib = sv.load_library()
+    r = np.zeros(1, dtype=OP_DTYPE)
+    r["kind"], r["target"] = ir.X, 1
+    params = np.zeros(1)
+    for field, value in (("split_real", 3), ("split_real", -1), ("peephole", 5), ("compile", 7)):
+        o = sv._opts()
+        setattr(o, field, value)
+        out = ctypes.c_void_p()
+        rc = lib.sv_plan_create(4, sv.SV_C64, r.ctypes.data, 1, params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                1, ctypes.byref(o), ctypes.byref(out))
+        assert rc == sv.SV_EINVAL, (field, value)
+        assert field.split("_")[0] in sv.sv_last_error(), sv.sv_last_error()
+
+
 def test_sequence_entries_are_checked_against_the_plan_count():
     lib = sv.load_library()
     plans = (ctypes.c_void_p * 1)(None)
