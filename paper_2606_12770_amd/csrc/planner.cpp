@@ -685,6 +685,12 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
         PassBuild pb;
         pb.S = lowmask;
         const size_t wend = std::min(n_ops, first + W);
+        // Once every qubit is blocked (acted on non-diagonally by a skipped op,
+        // or both an X target and diagonal in skipped ops), no later op of the
+        // window commutes with all skipped ones: every op touches a qubit, and
+        // commutes_with_all fails on any blocked qubit.  The scans stop there.
+        const uint64_t allq = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+        auto all_blocked = [&](uint64_t Z, uint64_t X, uint64_t G) { return ((G | (X & Z)) & allq) == allq; };
         // ops of the window that a resident set S would let into the pass now
         auto gain = [&](uint64_t S) {
             uint64_t Z = 0, X = 0, G = 0;
@@ -699,6 +705,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 Z |= o.z;
                 X |= o.x;
                 G |= o.g;
+                if (all_blocked(Z, X, G)) break;
             }
             return cnt;
         };
@@ -732,6 +739,7 @@ int build_plan(sv_plan *p, const sv_op *ops, size_t n_ops, const double *params,
                 Z |= o.z;
                 X |= o.x;
                 G |= o.g;
+                if (all_blocked(Z, X, G)) break;
             }
             if (cand < 0) break;
             if (lookahead && n_alt > 1) {
