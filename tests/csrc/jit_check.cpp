@@ -20,6 +20,10 @@ std::string jit_kernel(const std::string &name, const std::string &body, int thr
 
 using namespace svi;
 
+// sv_apply_opts.split_real of the plans jit_check builds (SV_SPLIT_REAL_AUTO by default).
+static int g_split_real = SV_SPLIT_REAL_AUTO;
+extern "C" void jit_check_set_split_real(int v) { g_split_real = v; }
+
 extern "C" int jit_check(int n, int dtype, const sv_op *ops, size_t n_ops, const double *params, int tile_qubits,
                          int reg_qubits, int persistent, const char *src_out, const char *code_out)
 {
@@ -30,6 +34,7 @@ extern "C" int jit_check(int n, int dtype, const sv_op *ops, size_t n_ops, const
     o.mode = SV_MODE_FUSED;
     o.tile_qubits = tile_qubits;
     o.reg_qubits = reg_qubits;
+    o.split_real = g_split_real;
     std::string err;
     if (build_plan(&p, ops, n_ops, params, o, err) != SV_OK) return -1;
     std::set<std::string> bodies;

@@ -78,6 +78,30 @@ def test_persistent_form_compiles(jit, dtype):
     compile_circuit(jit, random_mixed_circuit(16, 250, seed=9, max_ctrl=5), dtype, 12, 4, persistent=1)
 
 
+@pytest.mark.parametrize("b,rb", [(12, 4), (13, 4)])
+def test_split_real_gates_compile(jit, tmp_path, b, rb):
+    """Complex64 plans with SV_SPLIT_REAL_ON emit their real 2x2 gates as
+    hi + lo calls (gur2) and compile; with SV_SPLIT_REAL_OFF the same circuit
+    emits none."""
+    c = random_mixed_circuit(15, 250, seed=31, max_ctrl=5)
+    ops, params = c.arrays()
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    jit.jit_check_set_split_real.argtypes = [ctypes.c_int]
+    jit.jit_check_set_split_real.restype = None
+    counts = {}
+    for split in (1, 2):
+        src = tmp_path / f"split{split}.hip"
+        jit.jit_check_set_split_real(split)
+        try:
+            rc = jit.jit_check(c.n, 0, ops.ctypes.data, len(ops), params.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               b, rb, 0, str(src).encode(), None)
+        finally:
+            jit.jit_check_set_split_real(0)
+        assert rc > 0, f"generated source did not compile (code {rc})"
+        counts[split] = src.read_text().count("gur2(x[")
+    assert counts[1] == 0 and counts[2] > 0, counts
+
+
 def test_sources_compile_with_the_hip_compiler_command(jit, tmp_path):
     """The library compiles generated units with the ROCm HIP compiler in child
     processes (device code only, one code object); the same command line on a
