@@ -281,6 +281,24 @@ def test_complex64_real_gates_carry_their_remainder(emu):
             assert drift > 1e-6
 
 
+@pytest.mark.parametrize("n,b,rb", [(14, 12, 4), (15, 13, 4), (14, 12, 5), (13, 10, 4)])
+def test_split_real_plans_match_oracle(emu, n, b, rb):
+    """Plans with SV_SPLIT_REAL_ON at several geometries (512-thread tiles
+    included): in FP64 emulation (parameters unrounded) the state matches the
+    oracle to 1e-12, the same as without the split."""
+    c = random_mixed_circuit(n, 400, seed=3 * n + b, max_ctrl=5)
+    psi0 = random_state(n, n)
+    want = osv.run(c, psi0)
+    emu.emu_set_split_real.argtypes = [ctypes.c_int]
+    emu.emu_set_split_real.restype = None
+    emu.emu_set_split_real(2)
+    try:
+        got, _ = run_emu(emu, c, psi0, 1, b, rb, 0)
+    finally:
+        emu.emu_set_split_real(0)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
 def test_split_real_auto_follows_the_norm_bound(emu):
     """SV_SPLIT_REAL_AUTO splits the real gates of a complex64 plan exactly when
     the summed FP32 column-norm errors of its real gates exceed 1e-4: the
