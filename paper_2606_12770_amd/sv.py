@@ -153,9 +153,11 @@ def _ops_params(ops, params):
 
 
 def sv_apply_circuit(state, ops, params, mode=SV_MODE_FUSED, tile_qubits=0, reg_qubits=0, dense_min_ops=0,
-                     tile_launch=0, plain_split=0, compile=0, peephole=0):
+                     tile_launch=0, plain_split=0, compile=0, peephole=0, dense_bf16=0, dense_qubits=0,
+                     coalesce_qubits=0, split_real=0):
     ops, params = _ops_params(ops, params)
-    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile, 0, peephole)
+    o = _opts(mode, tile_qubits, reg_qubits, dense_min_ops, tile_launch, plain_split, compile, dense_bf16, peephole,
+              dense_qubits, coalesce_qubits, split_real)
     _check(load_library().sv_apply_circuit(state, ops.ctypes.data, len(ops), _dp(params), len(params),
                                            ctypes.byref(o)))
 
